@@ -1,0 +1,250 @@
+"""FP64 reference ("oracle") for adaptive frameless reconstruction.
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. It wraps the plain C reference in ``afr_oracle.c`` (built
+with gcc into ``_liboracle.so``) and shares nothing with the GPU library: no code, headers, tables
+or constants. Inputs come from ``afr_scenes`` (random draws and analytic scenes only).
+
+Layouts follow the C file: slot planes ``[H, W, K]`` (slot 0 newest), ``count [H, W]``, tile
+statistics ``[NSTAT, Ty, Tx]``, images ``[3, H, W]``, ``aux [2, H, W] = (E_max, W')``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "afr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+
+STAT_NAMES = ("gx", "gy", "gt", "vol", "var", "lmean", "ex2", "ey2", "sx2", "sy2", "kt2")
+NSTAT = len(STAT_NAMES)
+STAT = {n: i for i, n in enumerate(STAT_NAMES)}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C reference with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("e_min", ctypes.c_double), ("e_max", ctypes.c_double),
+                ("g_floor", ctypes.c_double), ("dt_floor", ctypes.c_double),
+                ("age_floor", ctypes.c_double), ("t_now", ctypes.c_double),
+                ("radius", ctypes.c_int), ("tile", ctypes.c_int)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Buffer(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("k", ctypes.c_int),
+                ("fp16", ctypes.c_int), ("t_ref", ctypes.c_double),
+                ("ox", _dp), ("oy", _dp), ("ta", _dp), ("r", _dp), ("g", _dp), ("b", _dp),
+                ("count", ctypes.POINTER(ctypes.c_uint8)), ("src", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        fp = ctypes.POINTER(ctypes.c_float)
+        lib.or_f16_round.restype = ctypes.c_double
+        lib.or_f16_round.argtypes = [ctypes.c_double]
+        lib.or_build.restype = ctypes.c_int
+        lib.or_build.argtypes = [ctypes.c_int64, fp, fp, fp, fp, fp, fp, ctypes.POINTER(_Buffer),
+                                 ctypes.POINTER(ctypes.c_int64)]
+        lib.or_pixel_stats.restype = ctypes.c_int
+        lib.or_pixel_stats.argtypes = [ctypes.POINTER(_Buffer), ctypes.POINTER(_Params)] + [_dp] * 5
+        lib.or_extents.restype = None
+        lib.or_extents.argtypes = [ctypes.c_double] * 4 + [ctypes.POINTER(_Params), _dp]
+        lib.or_estimate.restype = ctypes.c_int
+        lib.or_estimate.argtypes = [ctypes.POINTER(_Buffer), ctypes.POINTER(_Params), _dp]
+        lib.or_reconstruct.restype = ctypes.c_int
+        lib.or_reconstruct.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params), _dp, _dp]
+        lib.or_backward.restype = ctypes.c_int
+        lib.or_backward.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
+        _lib_handle = lib
+    return _lib_handle
+
+
+@dataclass
+class Params:
+    """Filter constants. ``alpha`` is 3.47 per second (Sec. 4), expressed per millisecond."""
+    sigma: float = 1.0
+    tau: float = 0.5
+    alpha: float = 3.47e-3
+    e_min: float = 0.5
+    e_max: float = 1.0
+    g_floor: float = 1e-3
+    dt_floor: float = 1e-3
+    age_floor: float = 1e-3
+    t_now: float = 0.0
+    radius: int = 2
+    tile: int = 8
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+    def _c(self) -> _Params:
+        return _Params(float(self.sigma), float(self.tau), float(self.alpha), float(self.e_min),
+                       float(self.e_max), float(self.g_floor), float(self.dt_floor),
+                       float(self.age_floor), float(self.t_now), int(self.radius), int(self.tile))
+
+
+@dataclass
+class Buffer:
+    """Per-pixel deep buffer in FP64 (FP16 mode holds binary16-rounded values)."""
+    width: int
+    height: int
+    k: int
+    fp16: bool
+    t_ref: float
+    ox: np.ndarray
+    oy: np.ndarray
+    ta: np.ndarray
+    r: np.ndarray
+    g: np.ndarray
+    b: np.ndarray
+    count: np.ndarray
+    src: np.ndarray
+
+    @staticmethod
+    def empty(width, height, k, fp16=False, t_ref=0.0) -> "Buffer":
+        z = lambda: np.zeros((height, width, k), np.float64)
+        return Buffer(width, height, k, bool(fp16), float(t_ref), z(), z(), z(), z(), z(), z(),
+                      np.zeros((height, width), np.uint8), np.full((height, width, k), -1, np.int32))
+
+    def colours(self) -> np.ndarray:
+        return np.stack([self.r, self.g, self.b])
+
+    def with_colours(self, rgb) -> "Buffer":
+        rgb = np.asarray(rgb, np.float64)
+        return replace(self, r=rgb[0].copy(), g=rgb[1].copy(), b=rgb[2].copy())
+
+    def _c(self) -> _Buffer:
+        for a in (self.ox, self.oy, self.ta, self.r, self.g, self.b):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+            assert a.shape == (self.height, self.width, self.k)
+        assert self.count.dtype == np.uint8 and self.count.flags.c_contiguous
+        assert self.src.dtype == np.int32 and self.src.flags.c_contiguous
+        d = lambda a: a.ctypes.data_as(_dp)
+        return _Buffer(self.width, self.height, self.k, int(self.fp16), float(self.t_ref),
+                       d(self.ox), d(self.oy), d(self.ta), d(self.r), d(self.g), d(self.b),
+                       self.count.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                       self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def f16_round(v) -> np.ndarray:
+    lib = _lib()
+    v = np.asarray(v, np.float64)
+    return np.array([lib.or_f16_round(float(a)) for a in v.reshape(-1)]).reshape(v.shape)
+
+
+def build_buffer(stream, width, height, k, precision="fp32", t_ref=None):
+    """Per-pixel deep buffer from a stream; returns ``(Buffer, dropped)``."""
+    x, y, t, r, g, b = (np.ascontiguousarray(a, np.float32) for a in stream.arrays())
+    if t_ref is None:
+        t_ref = float(t.max()) if t.size else 0.0
+    buf = Buffer.empty(width, height, k, precision == "fp16", float(np.float32(t_ref)))
+    bc = buf._c()
+    dropped = ctypes.c_int64(0)
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    rc = _lib().or_build(len(x), fp(x), fp(y), fp(t), fp(r), fp(g), fp(b), ctypes.byref(bc),
+                         ctypes.byref(dropped))
+    if rc:
+        raise ValueError(f"or_build failed ({rc})")
+    return buf, int(dropped.value)
+
+
+def pixel_stats(buf: Buffer, params: Params) -> dict:
+    hw = (buf.height, buf.width)
+    outs = [np.zeros(hw, np.float64) for _ in range(5)]
+    rc = _lib().or_pixel_stats(ctypes.byref(buf._c()), ctypes.byref(params._c()),
+                               *(o.ctypes.data_as(_dp) for o in outs))
+    if rc:
+        raise ValueError(f"or_pixel_stats failed ({rc})")
+    return dict(zip(("lbar", "omega", "gx", "gy", "gt"), outs))
+
+
+def extents(gx, gy, gt, vol, params: Params) -> dict:
+    out = np.zeros(5, np.float64)
+    _lib().or_extents(float(gx), float(gy), float(gt), float(vol), ctypes.byref(params._c()),
+                      out.ctypes.data_as(_dp))
+    return dict(zip(("ex2", "ey2", "sx2", "sy2", "kt2"), out))
+
+
+def tiles_shape(width, height, tile):
+    return (-(-height // tile), -(-width // tile))
+
+
+def estimate(buf: Buffer, params: Params) -> np.ndarray:
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    stats = np.zeros((NSTAT, ty, tx), np.float64)
+    rc = _lib().or_estimate(ctypes.byref(buf._c()), ctypes.byref(params._c()),
+                            stats.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError(f"or_estimate failed ({rc})")
+    return stats
+
+
+def reconstruct(buf: Buffer, stats: np.ndarray, params: Params):
+    stats = np.ascontiguousarray(stats, np.float64)
+    rgb = np.zeros((3, buf.height, buf.width), np.float64)
+    aux = np.zeros((2, buf.height, buf.width), np.float64)
+    rc = _lib().or_reconstruct(ctypes.byref(buf._c()), stats.ctypes.data_as(_dp),
+                               ctypes.byref(params._c()), rgb.ctypes.data_as(_dp),
+                               aux.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError(f"or_reconstruct failed ({rc})")
+    return rgb, aux
+
+
+def backward(buf: Buffer, stats: np.ndarray, params: Params, grad_rgb):
+    stats = np.ascontiguousarray(stats, np.float64)
+    grad_rgb = np.ascontiguousarray(grad_rgb, np.float64)
+    gslot = np.zeros((3, buf.height, buf.width, buf.k), np.float64)
+    gpar = np.zeros(2, np.float64)
+    rc = _lib().or_backward(ctypes.byref(buf._c()), stats.ctypes.data_as(_dp),
+                            ctypes.byref(params._c()), grad_rgb.ctypes.data_as(_dp),
+                            gslot.ctypes.data_as(_dp), gpar.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError(f"or_backward failed ({rc})")
+    return gslot, gpar
+
+
+def forward(buf: Buffer, params: Params):
+    """Estimate then reconstruct: ``(rgb, aux, stats)``."""
+    stats = estimate(buf, params)
+    rgb, aux = reconstruct(buf, stats, params)
+    return rgb, aux, stats
+
+
+def rms(img, gt) -> float:
+    """Root-mean-square error over pixels and channels (the gold-standard comparison of Sec. 7)."""
+    d = np.asarray(img, np.float64) - np.asarray(gt, np.float64)
+    return float(np.sqrt(np.mean(d * d)))
+
+
+def rms_grad(img, gt, scale=1.0):
+    """d(scale * RMS)/d img."""
+    d = np.asarray(img, np.float64) - np.asarray(gt, np.float64)
+    e = float(np.sqrt(np.mean(d * d)))
+    if e == 0.0:
+        return np.zeros_like(d)
+    return scale * d / (d.size * e)

@@ -1,0 +1,609 @@
+/*
+ * afr_oracle.c -- plain, slow FP64 reference for temporally adaptive reconstruction from a deep
+ * buffer of space-time samples (Dayal, Woolley, Watson, Luebke: "Adaptive Frameless Rendering").
+ *
+ * TEST INFRASTRUCTURE. This file is the checker, not the product: only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg load it. It shares no code, header, table or constant
+ * generator with the GPU library, and the GPU library never calls it.
+ *
+ * Everything is double precision, single-threaded, with no blocking, fusion or reordering beyond
+ * what each definition states. Where the paper is silent or garbled, the reading used is stated at
+ * the function that needs it.
+ *
+ * Layouts (all row-major, C order):
+ *   slot planes  [H][W][K]   slot 0 is the newest sample of a pixel, count[p] slots are filled
+ *   count        [H][W]      uint8
+ *   src          [H][W][K]   stream index of the sample in each slot, -1 when empty
+ *   stats        [OR_NSTAT][Ty][Tx]   per statistics tile
+ *   rgb          [3][H][W],  aux [2][H][W] = (E_max, W')
+ *
+ * Parity status: every function here is pinned by the tests listed in its comment, except where a
+ * comment says "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum {
+    OR_GX = 0, OR_GY, OR_GT, OR_VOL, OR_VAR, OR_LMEAN, OR_EX2, OR_EY2, OR_SX2, OR_SY2, OR_KT2,
+    OR_NSTAT
+};
+
+typedef struct {
+    double sigma;     /* spatial width scale (not in the paper; scales e_x, e_y)              */
+    double tau;       /* temporal sensitivity (not in the paper; scales G_t)                  */
+    double alpha;     /* age-weight rate per ms: exp(-alpha * age), Sec. 4 (3.47 per second)  */
+    double e_min;     /* smooth lower clamp of the spatial std, px                            */
+    double e_max;     /* smooth upper clamp scale of the spatial std, px (INFINITY = none)    */
+    double g_floor;   /* quadrature floor of spatial gradients, 1/px                          */
+    double dt_floor;  /* floor of the new/old age separation, ms                              */
+    double age_floor; /* floor of the mean tile age in the density estimate, ms               */
+    double t_now;     /* reconstruction time, ms                                              */
+    int radius;       /* gather radius R: Chebyshev block of (2R+1)^2 pixels                  */
+    int tile;         /* statistics tile edge B_g, px                                         */
+} or_params;
+
+typedef struct {
+    int width, height, k, fp16;
+    double t_ref;                    /* stream reference time (float32-representable), ms     */
+    double *ox, *oy, *ta, *r, *g, *b; /* [H][W][K]; ta = t (FP32 mode) or age_ref (FP16 mode) */
+    uint8_t *count;                  /* [H][W] */
+    int32_t *src;                    /* [H][W][K] */
+} or_buffer;
+
+/* ------------------------------------------------------------------------------------------------
+ * IEEE 754 binary16 round-to-nearest-even, written from the format's definition: 11 significant
+ * bits, normal exponents -14..15, subnormal quantum 2^-24, largest finite 65504. The input is scaled
+ * by the binary16 quantum of its binade (an exact power-of-two scaling), rounded to an integer with
+ * ties to even, and scaled back. Pinned against NumPy's float32 -> float16 conversion.
+ * --------------------------------------------------------------------------------------------- */
+double or_f16_round(double v)
+{
+    if (isnan(v) || isinf(v) || v == 0.0)
+        return v;
+    double a = fabs(v);
+    int e;
+    frexp(a, &e);                 /* a = f * 2^e with f in [0.5, 1): binade exponent is e - 1 */
+    int q = (e - 1) - 10;         /* quantum exponent for 11 significant bits                   */
+    if (q < -24)
+        q = -24;                  /* subnormal range: fixed quantum 2^-24                       */
+    double m = nearbyint(ldexp(a, -q)); /* default rounding mode: nearest, ties to even          */
+    double r = ldexp(m, q);
+    if (r > 65504.0)
+        r = INFINITY;
+    return copysign(r, v);
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Build the per-pixel deep buffer (Sec. 4: each pixel holds a queue; a new sample enters at the
+ * front and, when the queue is full, the sample at the back leaves; Sec. 5.2: the reconstructor's
+ * samples arrive as one time-ordered stream).
+ *
+ * Valid samples: all six fields finite, 0 <= x < W, 0 <= y < H, t <= t_ref; in FP16 mode the
+ * rounded age and colours must also be finite. Others are dropped and counted.
+ * Arrival order is ascending (t, stream index): a later sample with an equal time counts as newer.
+ * Stored per slot: ox = x - floor(x), oy = y - floor(y), ta = t (FP32 mode) or
+ * age_ref = f16(fp32(t_ref - t)) (FP16 mode), and the colour (rounded to binary16 in FP16 mode).
+ *
+ * This replays the queue insertion literally. Pinned against a sort-and-take-top-K brute force and
+ * against the counting invariants (count = min(K, arrivals); K >= occupancy keeps every sample).
+ * --------------------------------------------------------------------------------------------- */
+typedef struct { float t; int64_t i; } or_key;
+
+static int or_key_cmp(const void *pa, const void *pb)
+{
+    const or_key *a = (const or_key *)pa, *b = (const or_key *)pb;
+    if (a->t < b->t) return -1;
+    if (a->t > b->t) return 1;
+    return (a->i > b->i) - (a->i < b->i);
+}
+
+int or_build(int64_t n, const float *x, const float *y, const float *t, const float *r,
+             const float *g, const float *b, or_buffer *out, int64_t *dropped)
+{
+    const int W = out->width, H = out->height, K = out->k;
+    if (W <= 0 || H <= 0 || K < 1 || K > 255 || n < 0)
+        return 1;
+    const size_t HW = (size_t)W * H, HWK = HW * K;
+    const float t_ref = (float)out->t_ref;
+    for (size_t s = 0; s < HWK; ++s) {
+        out->ox[s] = out->oy[s] = out->ta[s] = out->r[s] = out->g[s] = out->b[s] = 0.0;
+        out->src[s] = -1;
+    }
+    memset(out->count, 0, HW);
+
+    or_key *keys = (or_key *)malloc(sizeof(or_key) * (size_t)(n > 0 ? n : 1));
+    if (!keys)
+        return 4;
+    int64_t nv = 0, nd = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int ok = isfinite(x[i]) && isfinite(y[i]) && isfinite(t[i]) && isfinite(r[i]) &&
+                 isfinite(g[i]) && isfinite(b[i]);
+        ok = ok && x[i] >= 0.0f && x[i] < (float)W && y[i] >= 0.0f && y[i] < (float)H;
+        ok = ok && t[i] <= t_ref;
+        if (ok && out->fp16) {
+            float age = t_ref - t[i];
+            ok = isfinite(or_f16_round(age)) && isfinite(or_f16_round(r[i])) &&
+                 isfinite(or_f16_round(g[i])) && isfinite(or_f16_round(b[i]));
+        }
+        if (ok) {
+            keys[nv].t = t[i];
+            keys[nv].i = i;
+            ++nv;
+        } else {
+            ++nd;
+        }
+    }
+    qsort(keys, (size_t)nv, sizeof(or_key), or_key_cmp);
+
+    for (int64_t a = 0; a < nv; ++a) {
+        const int64_t i = keys[a].i;
+        const double fx = floor((double)x[i]), fy = floor((double)y[i]);
+        const size_t p = (size_t)fy * W + (size_t)fx;
+        const size_t base = p * K;
+        int c = out->count[p];
+        int last = c < K ? c : K - 1;         /* the back sample leaves when the queue is full */
+        for (int k = last; k >= 1; --k) {
+            out->ox[base + k] = out->ox[base + k - 1];
+            out->oy[base + k] = out->oy[base + k - 1];
+            out->ta[base + k] = out->ta[base + k - 1];
+            out->r[base + k] = out->r[base + k - 1];
+            out->g[base + k] = out->g[base + k - 1];
+            out->b[base + k] = out->b[base + k - 1];
+            out->src[base + k] = out->src[base + k - 1];
+        }
+        double vox = (double)x[i] - fx, voy = (double)y[i] - fy;
+        if (out->fp16) {
+            float age = t_ref - t[i];             /* binary32 subtraction, then binary16 */
+            out->ox[base] = or_f16_round(vox);
+            out->oy[base] = or_f16_round(voy);
+            out->ta[base] = or_f16_round((double)age);
+            out->r[base] = or_f16_round(r[i]);
+            out->g[base] = or_f16_round(g[i]);
+            out->b[base] = or_f16_round(b[i]);
+        } else {
+            out->ox[base] = vox;
+            out->oy[base] = voy;
+            out->ta[base] = (double)t[i];
+            out->r[base] = r[i];
+            out->g[base] = g[i];
+            out->b[base] = b[i];
+        }
+        out->src[base] = (int32_t)i;
+        out->count[p] = (uint8_t)(c < K ? c + 1 : K);
+    }
+    free(keys);
+    if (dropped)
+        *dropped = nd;
+    return 0;
+}
+
+/* Age of a slot at the reconstruction time. FP32 mode stores the time itself; FP16 mode stores the
+ * age relative to t_ref, so the age at t_now adds (t_now - t_ref). */
+static double slot_age(const or_buffer *buf, const or_params *p, size_t s)
+{
+    return buf->fp16 ? (p->t_now - buf->t_ref) + buf->ta[s] : p->t_now - buf->ta[s];
+}
+
+/* Luminance of linear RGB. The paper says only "luminance" (Sec. 4); the Rec. 709 weights are the
+ * reading used here. */
+static double luminance(double r, double g, double b)
+{
+    return 0.2126 * r + 0.7152 * g + 0.0722 * b;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Per-pixel statistics and gradients (Sec. 4 variance weights, Sec. 4.1 crosshair gradients).
+ *
+ *   omega = exp(-alpha * age)                       age weight, Sec. 4 (e^{-3.47 a})
+ *   Omega_p = sum omega,  Lbar_p = sum omega L / Omega_p           (n_p >= 1)
+ *   Temporal gradient (n_p >= 2): slots ranked newest first are split at h = ceil(n_p / 2) into a
+ *   "new" half (rank < h) and an "old" half; with unweighted means of L and age over each half,
+ *       G_t(p) = |L_new - L_old| / max(a_old - a_new, dt_floor).
+ *   This is the crosshair's |L(t) - L(t0)| / (t - t0) of Sec. 4.1 with "same sub-pixel spot"
+ *   relaxed to "same pixel", since scattered samples have no collocated pairs (a reading).
+ *   Spatial gradient: G_x(p) is the mean of |Lbar_p - Lbar_q| over q = p -/+ x_hat inside the image
+ *   with n_q >= 1 (the crosshair's average of one-sided differences at 1 px spacing); G_y alike.
+ *
+ * Undefined values are written as NaN. Pinned by closed forms: linear luminance ramps give the
+ * ramp slopes, L = c t at fixed positions gives |c|, constant colour gives zero.
+ * --------------------------------------------------------------------------------------------- */
+int or_pixel_stats(const or_buffer *buf, const or_params *p, double *lbar, double *omega,
+                   double *gx, double *gy, double *gt)
+{
+    const int W = buf->width, H = buf->height, K = buf->k;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t px = (size_t)j * W + i;
+            const int n = buf->count[px];
+            lbar[px] = omega[px] = gt[px] = NAN;
+            if (n == 0)
+                continue;
+            double sw = 0.0, swl = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const size_t s = px * K + k;
+                const double L = luminance(buf->r[s], buf->g[s], buf->b[s]);
+                const double w = exp(-p->alpha * slot_age(buf, p, s));
+                sw += w;
+                swl += w * L;
+            }
+            omega[px] = sw;
+            lbar[px] = swl / sw;
+            if (n >= 2) {
+                const int h = (n + 1) / 2;
+                double ln = 0.0, lo = 0.0, an = 0.0, ao = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const size_t s = px * K + k;
+                    const double L = luminance(buf->r[s], buf->g[s], buf->b[s]);
+                    const double a = slot_age(buf, p, s);
+                    if (k < h) { ln += L; an += a; }
+                    else       { lo += L; ao += a; }
+                }
+                ln /= h; an /= h;
+                lo /= (n - h); ao /= (n - h);
+                gt[px] = fabs(ln - lo) / fmax(ao - an, p->dt_floor);
+            }
+        }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t px = (size_t)j * W + i;
+            gx[px] = gy[px] = NAN;
+            if (buf->count[px] == 0)
+                continue;
+            double sx = 0.0, sy = 0.0;
+            int nx = 0, ny = 0;
+            if (i > 0 && buf->count[px - 1] > 0)     { sx += fabs(lbar[px] - lbar[px - 1]); ++nx; }
+            if (i + 1 < W && buf->count[px + 1] > 0) { sx += fabs(lbar[px] - lbar[px + 1]); ++nx; }
+            if (j > 0 && buf->count[px - W] > 0)     { sy += fabs(lbar[px] - lbar[px - W]); ++ny; }
+            if (j + 1 < H && buf->count[px + W] > 0) { sy += fabs(lbar[px] - lbar[px + W]); ++ny; }
+            if (nx) gx[px] = sx / nx;
+            if (ny) gy[px] = sy / ny;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Filter extents from gradients and sample volume (Sec. 5.1):
+ *   e_x G_x = e_y G_y = e_t G_t  and  e_x e_y e_t = V  give
+ *   e_x = cbrt(V G_y G_t / G_x^2), e_y = cbrt(V G_x G_t / G_y^2), e_t = cbrt(V G_x G_y / G_t^2).
+ * (The printed volume equation names e_z; it is read as e_t.) Here G_t is scaled by tau, spatial
+ * gradients get a quadrature floor, and the temporal Gaussian is written with k_t = 1 / e_t:
+ *   ex2 = e_x^2, ey2 = e_y^2, kt2 = 1 / e_t^2 = cbrt(u^2 / (V Gx Gy))^2 with u = tau G_t.
+ * When u == 0 (static content) the limit is ex2 = ey2 = kt2 = 0: every age weighs the same and the
+ * spatial width sits at its floor. Spatial stds get a smooth clamp,
+ *   sx2 = e_min^2 + z e_max^2 / (e_max^2 + z),  z = sigma^2 ex2   (sx2 = e_min^2 + z if e_max = inf),
+ * which is C-infinity in sigma and tau. Extents are standard deviations with support constant 1
+ * (the paper says "proportional"; a reading). Pinned by the paper's own constraints in a test mode
+ * (g_floor = e_min = 0, e_max = inf, sigma = tau = 1) and by unit covariance.
+ * --------------------------------------------------------------------------------------------- */
+void or_extents(double gx, double gy, double gt, double vol, const or_params *p, double *out5)
+{
+    const double hx = sqrt(gx * gx + p->g_floor * p->g_floor);
+    const double hy = sqrt(gy * gy + p->g_floor * p->g_floor);
+    const double u = p->tau * gt;
+    double ex2 = 0.0, ey2 = 0.0, kt2 = 0.0;
+    if (u != 0.0) {
+        const double cx = cbrt(vol * hy * u / (hx * hx));
+        const double cy = cbrt(vol * hx * u / (hy * hy));
+        const double ck = cbrt(u * u / (vol * hx * hy));
+        ex2 = cx * cx;
+        ey2 = cy * cy;
+        kt2 = ck * ck;
+    }
+    const double zx = p->sigma * p->sigma * ex2, zy = p->sigma * p->sigma * ey2;
+    const double em2 = p->e_max * p->e_max, en2 = p->e_min * p->e_min;
+    double sx2, sy2;
+    if (isinf(p->e_max)) {
+        sx2 = en2 + zx;
+        sy2 = en2 + zy;
+    } else {
+        sx2 = en2 + zx * em2 / (em2 + zx);
+        sy2 = en2 + zy * em2 / (em2 + zy);
+    }
+    out5[0] = ex2;
+    out5[1] = ey2;
+    out5[2] = sx2;
+    out5[3] = sy2;
+    out5[4] = kt2;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Per-tile statistics (Sec. 4 tile variation, Sec. 4.1 age-weighted gradient averaging, Sec. 5.1
+ * sample volume). Tiles are fixed B_g x B_g squares (the paper's adaptive K-D tiles belong to its
+ * sampler; a reading), clipped at the image border.
+ *   G_*(T) = sum Omega_p G_*(p) / sum Omega_p over the tile pixels where G_*(p) is defined, else 0.
+ *   n_T = total slots, abar_T = mean slot age, R_l = n_T / (A_T * 2 max(abar_T, age_floor)) in
+ *   samples per px^2 ms (for uniform arrival over a span D, 2 abar = D), V = 1 / R_l; an empty tile
+ *   has V = +inf (it has no defined gradient, so its extents are the u == 0 limit anyway).
+ *   L_m = sum omega L / sum omega and v_T = sum omega (L - L_m)^2 / sum omega over the tile's
+ *   slots, computed in two passes.
+ * Pinned by closed forms: age grids give V, two-valued luminance gives v_T, ramps give gradients.
+ * --------------------------------------------------------------------------------------------- */
+int or_estimate(const or_buffer *buf, const or_params *p, double *stats)
+{
+    const int W = buf->width, H = buf->height, K = buf->k, B = p->tile;
+    if (B < 1 || W < 1 || H < 1)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty;
+    double *lbar = (double *)malloc(sizeof(double) * HW * 5);
+    if (!lbar)
+        return 4;
+    double *omega = lbar + HW, *gx = lbar + 2 * HW, *gy = lbar + 3 * HW, *gt = lbar + 4 * HW;
+    or_pixel_stats(buf, p, lbar, omega, gx, gy, gt);
+
+    for (int ty = 0; ty < Ty; ++ty)
+        for (int tx = 0; tx < Tx; ++tx) {
+            const size_t T = (size_t)ty * Tx + tx;
+            const int i0 = tx * B, i1 = (tx + 1) * B < W ? (tx + 1) * B : W;
+            const int j0 = ty * B, j1 = (ty + 1) * B < H ? (ty + 1) * B : H;
+            double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+            double n_t = 0.0, sum_age = 0.0, sw = 0.0, swl = 0.0;
+            for (int j = j0; j < j1; ++j)
+                for (int i = i0; i < i1; ++i) {
+                    const size_t px = (size_t)j * W + i;
+                    const double *gp[3] = {gx, gy, gt};
+                    for (int c = 0; c < 3; ++c)
+                        if (!isnan(gp[c][px])) {
+                            num[c] += omega[px] * gp[c][px];
+                            den[c] += omega[px];
+                        }
+                    for (int k = 0; k < buf->count[px]; ++k) {
+                        const size_t s = px * K + k;
+                        const double a = slot_age(buf, p, s);
+                        const double L = luminance(buf->r[s], buf->g[s], buf->b[s]);
+                        const double w = exp(-p->alpha * a);
+                        n_t += 1.0;
+                        sum_age += a;
+                        sw += w;
+                        swl += w * L;
+                    }
+                }
+            double lm = 0.0, var = 0.0;
+            if (n_t > 0.0) {
+                lm = swl / sw;
+                double acc = 0.0;
+                for (int j = j0; j < j1; ++j)
+                    for (int i = i0; i < i1; ++i) {
+                        const size_t px = (size_t)j * W + i;
+                        for (int k = 0; k < buf->count[px]; ++k) {
+                            const size_t s = px * K + k;
+                            const double L = luminance(buf->r[s], buf->g[s], buf->b[s]);
+                            const double w = exp(-p->alpha * slot_age(buf, p, s));
+                            acc += w * (L - lm) * (L - lm);
+                        }
+                    }
+                var = acc / sw;
+            }
+            const double area = (double)(i1 - i0) * (j1 - j0);
+            double vol = INFINITY;
+            if (n_t > 0.0) {
+                const double abar = sum_age / n_t;
+                const double rate = n_t / (area * 2.0 * fmax(abar, p->age_floor));
+                vol = 1.0 / rate;
+            }
+            double g3[3];
+            for (int c = 0; c < 3; ++c)
+                g3[c] = den[c] > 0.0 ? num[c] / den[c] : 0.0;
+            double e5[5];
+            or_extents(g3[0], g3[1], g3[2], vol, p, e5);
+            stats[OR_GX * NT + T] = g3[0];
+            stats[OR_GY * NT + T] = g3[1];
+            stats[OR_GT * NT + T] = g3[2];
+            stats[OR_VOL * NT + T] = vol;
+            stats[OR_VAR * NT + T] = var;
+            stats[OR_LMEAN * NT + T] = lm;
+            stats[OR_EX2 * NT + T] = e5[0];
+            stats[OR_EY2 * NT + T] = e5[1];
+            stats[OR_SX2 * NT + T] = e5[2];
+            stats[OR_SY2 * NT + T] = e5[3];
+            stats[OR_KT2 * NT + T] = e5[4];
+        }
+    free(lbar);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Gather reconstruction (Sec. 5.2: per pixel, the normalised weighted average of nearby samples;
+ * Sec. 5.1: Gaussian filter, axis-aligned in x, y and t, shaped per tile).
+ * For pixel p = (i, j) in tile T, every filled slot s of every pixel q with |q_x - i| <= R and
+ * |q_y - j| <= R inside the image contributes with exponent
+ *   E_s = -1/2 (dx^2 / sx2 + dy^2 / sy2 + a^2 kt2),
+ *   dx = (q_x + ox) - (i + 1/2),  dy = (q_y + oy) - (j + 1/2),  a = slot age at t_now,
+ * using T's sx2, sy2, kt2 (the temporal Gaussian is one-sided in age, centred at t_now, since all
+ * samples lie in the past). C_p = sum exp(E_s - E_max) c_s / W',  W' = sum exp(E_s - E_max); the
+ * shift by E_max = max_s E_s only keeps the terms representable: C_p = sum w c / sum w.
+ * A block with no slots gives C_p = 0, E_max = 0, W' = 0. Support truncation is the integer block
+ * (the paper's epsilon cut-off / splat size is replaced by a fixed radius; a reading).
+ * Pinned by: constant colour, convexity, tau = 0 against an independent spatial Gaussian gather,
+ * one-sample blocks, newest-sample limit (traditional frameless, Sec. 5), linearity, mirror and
+ * shift covariance, hand-computed tiny cases.
+ * --------------------------------------------------------------------------------------------- */
+static int block_bounds(int c, int R, int N, int *lo, int *hi)
+{
+    *lo = c - R < 0 ? 0 : c - R;
+    *hi = c + R > N - 1 ? N - 1 : c + R;
+    return *hi >= *lo;
+}
+
+int or_reconstruct(const or_buffer *buf, const double *stats, const or_params *p, double *rgb,
+                   double *aux)
+{
+    const int W = buf->width, H = buf->height, K = buf->k, B = p->tile, R = p->radius;
+    if (B < 1 || R < 0)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t px = (size_t)j * W + i;
+            const size_t T = (size_t)(j / B) * Tx + (i / B);
+            const double sx2 = stats[OR_SX2 * NT + T], sy2 = stats[OR_SY2 * NT + T];
+            const double kt2 = stats[OR_KT2 * NT + T];
+            if (!(sx2 > 0.0) || !(sy2 > 0.0) || !(kt2 >= 0.0))
+                return 2;
+            int qx0, qx1, qy0, qy1;
+            block_bounds(i, R, W, &qx0, &qx1);
+            block_bounds(j, R, H, &qy0, &qy1);
+            double emax = -INFINITY;
+            int any = 0;
+            for (int qy = qy0; qy <= qy1; ++qy)
+                for (int qx = qx0; qx <= qx1; ++qx) {
+                    const size_t q = (size_t)qy * W + qx;
+                    for (int k = 0; k < buf->count[q]; ++k) {
+                        const size_t s = q * K + k;
+                        const double dx = (qx + buf->ox[s]) - (i + 0.5);
+                        const double dy = (qy + buf->oy[s]) - (j + 0.5);
+                        const double a = slot_age(buf, p, s);
+                        const double E = -0.5 * (dx * dx / sx2 + dy * dy / sy2 + a * a * kt2);
+                        if (E > emax) emax = E;
+                        any = 1;
+                    }
+                }
+            double wsum = 0.0, cr = 0.0, cg = 0.0, cb = 0.0;
+            if (any) {
+                for (int qy = qy0; qy <= qy1; ++qy)
+                    for (int qx = qx0; qx <= qx1; ++qx) {
+                        const size_t q = (size_t)qy * W + qx;
+                        for (int k = 0; k < buf->count[q]; ++k) {
+                            const size_t s = q * K + k;
+                            const double dx = (qx + buf->ox[s]) - (i + 0.5);
+                            const double dy = (qy + buf->oy[s]) - (j + 0.5);
+                            const double a = slot_age(buf, p, s);
+                            const double E = -0.5 * (dx * dx / sx2 + dy * dy / sy2 + a * a * kt2);
+                            const double w = exp(E - emax);
+                            wsum += w;
+                            cr += w * buf->r[s];
+                            cg += w * buf->g[s];
+                            cb += w * buf->b[s];
+                        }
+                    }
+                rgb[px] = cr / wsum;
+                rgb[HW + px] = cg / wsum;
+                rgb[2 * HW + px] = cb / wsum;
+                aux[px] = emax;
+                aux[HW + px] = wsum;
+            } else {
+                rgb[px] = rgb[HW + px] = rgb[2 * HW + px] = 0.0;
+                aux[px] = 0.0;
+                aux[HW + px] = 0.0;
+            }
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Adjoint of the reconstruction (not in the paper: gradients for fitting sigma and tau).
+ * With pi_s(p) = exp(E_s - E_max) / W' and g(p, ch) = dl/dC(p, ch), tile statistics held fixed:
+ *   dl/dc_{s,ch} = sum_p g(p, ch) pi_s(p)
+ *   dl/dtheta    = sum_p sum_ch g(p, ch) sum_s pi_s(p) (c_{s,ch} - C_{p,ch}) dE_s/dtheta
+ *   dE/dtheta    = 1/2 (dx^2 dsx2/dtheta / sx2^2 + dy^2 dsy2/dtheta / sy2^2) - 1/2 a^2 dkt2/dtheta
+ * From the extents: z = sigma^2 ex2, dsx2/dz = e_max^4 / (e_max^2 + z)^2 (1 without a clamp),
+ * dz/dsigma = 2 sigma ex2, dz/dtau = sigma^2 (2/3) ex2 / tau, dkt2/dtau = (4/3) kt2 / tau,
+ * dkt2/dsigma = 0. Requires tau > 0. Everything (E, E_max, W', C) is recomputed here.
+ * Pinned by FP64 central finite differences of or_reconstruct and by the adjoint identity
+ * <J v, u> = <v, J^T u>.
+ * --------------------------------------------------------------------------------------------- */
+int or_backward(const or_buffer *buf, const double *stats, const or_params *p,
+                const double *grad_rgb, double *grad_slot, double *grad_params)
+{
+    const int W = buf->width, H = buf->height, K = buf->k, B = p->tile, R = p->radius;
+    if (B < 1 || R < 0 || !(p->tau > 0.0))
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty, HWK = HW * K;
+    for (size_t s = 0; s < 3 * HWK; ++s)
+        grad_slot[s] = 0.0;
+    double g_sigma = 0.0, g_tau = 0.0;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t px = (size_t)j * W + i;
+            const size_t T = (size_t)(j / B) * Tx + (i / B);
+            const double sx2 = stats[OR_SX2 * NT + T], sy2 = stats[OR_SY2 * NT + T];
+            const double kt2 = stats[OR_KT2 * NT + T];
+            const double ex2 = stats[OR_EX2 * NT + T], ey2 = stats[OR_EY2 * NT + T];
+            if (!(sx2 > 0.0) || !(sy2 > 0.0))
+                return 2;
+            const double zx = p->sigma * p->sigma * ex2, zy = p->sigma * p->sigma * ey2;
+            double dsx_dz = 1.0, dsy_dz = 1.0;
+            if (!isinf(p->e_max)) {
+                const double em2 = p->e_max * p->e_max;
+                dsx_dz = em2 * em2 / ((em2 + zx) * (em2 + zx));
+                dsy_dz = em2 * em2 / ((em2 + zy) * (em2 + zy));
+            }
+            const double dsx_dsig = dsx_dz * 2.0 * p->sigma * ex2;
+            const double dsy_dsig = dsy_dz * 2.0 * p->sigma * ey2;
+            const double dsx_dtau = dsx_dz * p->sigma * p->sigma * (2.0 / 3.0) * ex2 / p->tau;
+            const double dsy_dtau = dsy_dz * p->sigma * p->sigma * (2.0 / 3.0) * ey2 / p->tau;
+            const double dkt_dtau = (4.0 / 3.0) * kt2 / p->tau;
+
+            int qx0, qx1, qy0, qy1;
+            block_bounds(i, R, W, &qx0, &qx1);
+            block_bounds(j, R, H, &qy0, &qy1);
+            double emax = -INFINITY;
+            int any = 0;
+            for (int qy = qy0; qy <= qy1; ++qy)
+                for (int qx = qx0; qx <= qx1; ++qx) {
+                    const size_t q = (size_t)qy * W + qx;
+                    for (int k = 0; k < buf->count[q]; ++k) {
+                        const size_t s = q * K + k;
+                        const double dx = (qx + buf->ox[s]) - (i + 0.5);
+                        const double dy = (qy + buf->oy[s]) - (j + 0.5);
+                        const double a = slot_age(buf, p, s);
+                        const double E = -0.5 * (dx * dx / sx2 + dy * dy / sy2 + a * a * kt2);
+                        if (E > emax) emax = E;
+                        any = 1;
+                    }
+                }
+            if (!any)
+                continue;
+            double wsum = 0.0, C[3] = {0, 0, 0};
+            for (int qy = qy0; qy <= qy1; ++qy)
+                for (int qx = qx0; qx <= qx1; ++qx) {
+                    const size_t q = (size_t)qy * W + qx;
+                    for (int k = 0; k < buf->count[q]; ++k) {
+                        const size_t s = q * K + k;
+                        const double dx = (qx + buf->ox[s]) - (i + 0.5);
+                        const double dy = (qy + buf->oy[s]) - (j + 0.5);
+                        const double a = slot_age(buf, p, s);
+                        const double E = -0.5 * (dx * dx / sx2 + dy * dy / sy2 + a * a * kt2);
+                        const double w = exp(E - emax);
+                        wsum += w;
+                        C[0] += w * buf->r[s];
+                        C[1] += w * buf->g[s];
+                        C[2] += w * buf->b[s];
+                    }
+                }
+            for (int c = 0; c < 3; ++c)
+                C[c] /= wsum;
+            const double g0 = grad_rgb[px], g1 = grad_rgb[HW + px], g2 = grad_rgb[2 * HW + px];
+            for (int qy = qy0; qy <= qy1; ++qy)
+                for (int qx = qx0; qx <= qx1; ++qx) {
+                    const size_t q = (size_t)qy * W + qx;
+                    for (int k = 0; k < buf->count[q]; ++k) {
+                        const size_t s = q * K + k;
+                        const double dx = (qx + buf->ox[s]) - (i + 0.5);
+                        const double dy = (qy + buf->oy[s]) - (j + 0.5);
+                        const double a = slot_age(buf, p, s);
+                        const double E = -0.5 * (dx * dx / sx2 + dy * dy / sy2 + a * a * kt2);
+                        const double pi = exp(E - emax) / wsum;
+                        grad_slot[s] += g0 * pi;
+                        grad_slot[HWK + s] += g1 * pi;
+                        grad_slot[2 * HWK + s] += g2 * pi;
+                        const double h = g0 * (buf->r[s] - C[0]) + g1 * (buf->g[s] - C[1]) +
+                                         g2 * (buf->b[s] - C[2]);
+                        const double dsig = 0.5 * (dx * dx * dsx_dsig / (sx2 * sx2) +
+                                                   dy * dy * dsy_dsig / (sy2 * sy2));
+                        const double dtau = 0.5 * (dx * dx * dsx_dtau / (sx2 * sx2) +
+                                                   dy * dy * dsy_dtau / (sy2 * sy2)) -
+                                            0.5 * a * a * dkt_dtau;
+                        g_sigma += pi * h * dsig;
+                        g_tau += pi * h * dtau;
+                    }
+                }
+        }
+    grad_params[0] = g_sigma;
+    grad_params[1] = g_tau;
+    return 0;
+}
