@@ -1,0 +1,205 @@
+/*
+ * afr.h -- C ABI of libafr: temporally adaptive reconstruction of an image from a temporally deep
+ * buffer of space-time samples, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dayal, Woolley, Watson, Luebke, "Adaptive Frameless Rendering".
+ *   - samples stream from a sampler into a reconstructor (Sec. 4.2, Sec. 5.2);
+ *   - each pixel keeps a short queue of its newest samples (Sec. 4);
+ *   - local colour gradients in space and time and the local sample density shape an axis-aligned
+ *     Gaussian space-time filter per tile (Sec. 4.1, Sec. 5.1);
+ *   - each pixel is the normalised weighted average of nearby samples (Sec. 5.2).
+ *
+ * Conventions shared by every call
+ *   Memory      All array arguments are DEVICE pointers owned by the caller (for example PyTorch
+ *               tensors); structs themselves live in host memory. The library never allocates device
+ *               memory: calls that need scratch space take a caller-provided workspace whose size is
+ *               given by the matching *_workspace_bytes query.
+ *   Layout      Per-slot planes are [K][H][W] (row-major, slot-major: plane k holds every pixel's
+ *               k-th newest sample, slot 0 is the newest). Images are planar [C][H][W]. Tile statistics
+ *               are planar [AFR_NSTAT][tiles_y][tiles_x].
+ *   Units       Positions in pixels (pixel (i, j) covers [i, i+1) x [j, j+1)), time in milliseconds.
+ *   Streams     Every call enqueues asynchronous work on the given HIP stream (0 = null stream) and
+ *               returns without synchronising. Calls are re-entrant; calls on different streams that
+ *               share output or workspace memory race.
+ *   Errors      Arguments are validated on the host before anything is launched: an invalid call
+ *               returns AFR_E_INVALID or AFR_E_RANGE and enqueues nothing. A failed launch returns
+ *               AFR_E_DEVICE. Faults inside kernels surface at the caller's next synchronisation.
+ *               No C++ exception crosses this interface. Every output is fully overwritten, so a call
+ *               can be re-issued after an error.
+ */
+#ifndef AFR_H
+#define AFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum afr_status {
+    AFR_OK = 0,
+    AFR_E_INVALID = 1,      /* NULL pointer, inconsistent sizes or layout                       */
+    AFR_E_RANGE = 2,        /* a size or parameter outside its documented range                 */
+    AFR_E_DEVICE = 3,       /* a HIP launch or runtime call failed                              */
+    AFR_E_NOMEM = 4,        /* the caller's workspace is smaller than the query returned        */
+    AFR_E_UNSUPPORTED = 5   /* a valid request that this build does not implement               */
+} afr_status;
+
+/* Storage precision of a deep buffer. Arithmetic is FP32 (FP64 in the statistics) either way. */
+typedef enum afr_precision {
+    AFR_FP32 = 0,           /* ox, oy, t, r, g, b stored as float; tage holds the time t        */
+    AFR_FP16 = 1            /* stored as IEEE binary16 (round to nearest even); tage holds the   */
+                            /* age relative to t_ref, age_ref = t_ref - t, so recent samples get */
+                            /* the finest quantisation                                           */
+} afr_precision;
+
+/* A stream of samples (Sec. 4.2: the sampler streams every sample to the reconstructor). Device
+ * SoA float32 arrays of length n: sub-pixel position (x, y), time t in ms, and linear RGB colour. The
+ * order of the stream does not matter: samples are ranked by the key (t, index). */
+typedef struct afr_samples {
+    const float *x, *y, *t, *r, *g, *b;
+    int64_t n;
+} afr_samples;
+
+/* Per-pixel deep buffer (Sec. 4): pixel p keeps count[p] <= K slots, newest first. For every filled
+ * slot: ox = x - floor(x), oy = y - floor(y) in [0, 1], tage (see afr_precision) and the colour.
+ * Empty slots hold zeros. src (optional, may be NULL) receives the stream index of each slot or -1;
+ * it maps slot gradients back to stream samples. */
+typedef struct afr_deep_buffer {
+    int32_t width, height;  /* pixels, >= 1                                                     */
+    int32_t k;              /* slots per pixel, 1..255                                           */
+    int32_t precision;      /* afr_precision                                                     */
+    float t_ref;            /* stream reference time: samples with t > t_ref are dropped         */
+    void *ox, *oy, *tage, *r, *g, *b; /* [K][H][W] of float (AFR_FP32) or binary16 (AFR_FP16)    */
+    uint8_t *count;         /* [H][W]                                                            */
+    int32_t *src;           /* [K][H][W] or NULL                                                 */
+} afr_deep_buffer;
+
+/* Per-tile statistics, planes of float [tiles_y][tiles_x] in this order. */
+enum {
+    AFR_STAT_GX = 0,  /* age-weighted mean horizontal luminance gradient, 1/px   (Sec. 4.1)      */
+    AFR_STAT_GY,      /* age-weighted mean vertical luminance gradient, 1/px     (Sec. 4.1)      */
+    AFR_STAT_GT,      /* age-weighted mean temporal luminance gradient, 1/ms     (Sec. 4.1)      */
+    AFR_STAT_VOL,     /* space-time volume per sample V = 1/R_l, px^2 ms; +inf if empty (5.1)    */
+    AFR_STAT_VAR,     /* age-weighted luminance variance of the tile              (Sec. 4)       */
+    AFR_STAT_LMEAN,   /* age-weighted mean luminance of the tile                  (Sec. 4)       */
+    AFR_STAT_EX2,     /* e_x^2 before width scaling and clamping, px^2            (Sec. 5.1)     */
+    AFR_STAT_EY2,     /* e_y^2 before width scaling and clamping, px^2            (Sec. 5.1)     */
+    AFR_STAT_SX2,     /* horizontal filter variance used by the gather, px^2                     */
+    AFR_STAT_SY2,     /* vertical filter variance used by the gather, px^2                       */
+    AFR_STAT_KT2,     /* temporal filter rate squared 1/e_t^2, 1/ms^2             (Sec. 5.1)     */
+    AFR_NSTAT
+};
+
+typedef struct afr_tile_stats {
+    int32_t tile;               /* tile edge B_g in px; must equal afr_params.tile               */
+    int32_t tiles_x, tiles_y;   /* ceil(width / tile), ceil(height / tile)                       */
+    float *data;                /* [AFR_NSTAT][tiles_y][tiles_x]                                 */
+} afr_tile_stats;
+
+/* Filter constants. Defaults in brackets. */
+typedef struct afr_params {
+    float sigma;       /* spatial width scale [1.0]; >= 0                                        */
+    float tau;         /* temporal sensitivity, scales G_t [0.5]; >= 0 (> 0 for the backward)    */
+    float alpha;       /* age-weight rate, per ms [3.47e-3]: exp(-3.47 a) with a in s (Sec. 4)   */
+    float e_min;       /* spatial std floor, px [0.5]; > 0                                       */
+    float e_max;       /* spatial std clamp scale, px [1.0]; > 0 or +inf                         */
+    float g_floor;     /* quadrature floor of spatial gradients, 1/px [1e-3]; >= 0               */
+    float dt_floor;    /* floor of the new/old age separation, ms [1e-3]; > 0                    */
+    float age_floor;   /* floor of the mean age in the density estimate, ms [1e-3]; > 0          */
+    int32_t radius;    /* gather radius R: Chebyshev block of (2R+1)^2 pixels [2]; 0..4          */
+    int32_t tile;      /* statistics tile edge B_g, px [8]; 1..16                                */
+    float t_now;       /* reconstruction time, ms; >= the buffer's t_ref                         */
+} afr_params;
+
+/* Human-readable name of a status code. */
+const char *afr_status_string(afr_status status);
+
+/* Library version string. */
+const char *afr_version(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Deep-buffer build (Sec. 4 per-pixel queues fed by the Sec. 4.2 / 5.2 sample stream).
+ *
+ * Bins every valid sample to its home pixel (floor(x), floor(y)) and keeps, per pixel, the
+ * min(K, arrivals) samples with the largest key (t, stream index), newest in slot 0: the state the
+ * paper's queue reaches when the stream is inserted in time order (a later sample with an equal time
+ * counts as newer). A sample is valid when all six fields are finite, 0 <= x < width,
+ * 0 <= y < height and t <= out->t_ref; in FP16 mode its age and colours must also round to finite
+ * binary16 values. Invalid samples are dropped, not errors.
+ *
+ *   s            device sample stream; n < 2^31
+ *   out          geometry, precision, t_ref and destination planes (all overwritten)
+ *   ws, ws_bytes device workspace of at least afr_build_workspace_bytes(n, width, height, k) bytes
+ *   dropped_dev  optional device int64: receives the number of dropped samples
+ * ------------------------------------------------------------------------------------------- */
+size_t afr_build_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t k);
+afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                 size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Gradient, density and filter-extent estimation per tile (Sec. 4, 4.1, 5.1).
+ *
+ * Per pixel: luminance L (Rec. 709 weights), age weight w = exp(-alpha a), age-weighted mean Lbar.
+ * Spatial gradient: mean |Lbar_p - Lbar_q| over the filled 4-neighbours in x (resp. y). Temporal
+ * gradient: slots split by rank into a newer and an older half, |L_new - L_old| divided by
+ * max(a_old - a_new, dt_floor). Per tile: age-weighted means of the three gradients over the pixels
+ * where they are defined (0 otherwise), V = A * 2 max(mean age, age_floor) / n, the age-weighted
+ * luminance mean and variance, and the extents: with Gx' = sqrt(Gx^2 + g_floor^2) (same for y) and
+ * u = tau Gt, ex2 = cbrt(V Gy' u / Gx'^2)^2, ey2 = cbrt(V Gx' u / Gy'^2)^2,
+ * kt2 = cbrt(u^2 / (V Gx' Gy'))^2 (all 0 when u = 0), then
+ * sx2 = e_min^2 + z e_max^2 / (e_max^2 + z), z = sigma^2 ex2 (likewise sy2).
+ *
+ *   buf   a built deep buffer; out->data receives every statistic plane (overwritten)
+ * ------------------------------------------------------------------------------------------- */
+afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *params,
+                                  afr_tile_stats *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Adaptive space-time gather (Sec. 5.1 Gaussian filter, Sec. 5.2 normalised weighted average).
+ *
+ * Pixel p = (i, j) in tile T gathers every filled slot s of the pixels q with |q_x - i| <= R and
+ * |q_y - j| <= R inside the image, with E_s = -1/2 (dx^2/sx2 + dy^2/sy2 + a^2 kt2),
+ * dx = q_x + ox - (i + 1/2), dy = q_y + oy - (j + 1/2), a = t_now - t, using T's statistics:
+ *   C_p = sum_s exp(E_s - E_max) c_s / W',  W' = sum_s exp(E_s - E_max),  E_max = max_s E_s.
+ * A pixel whose block holds no slot gets C_p = 0, E_max = 0, W' = 0.
+ *
+ *   rgb   [3][H][W] float output
+ *   aux   [2][H][W] float output (E_max, W'), or NULL; the backward needs it
+ * afr_reconstruct runs the LDS-tiled separable form; afr_reconstruct_plain runs the direct form
+ * (one thread per pixel, one exponential per pair). Both compute the same quantity.
+ * ------------------------------------------------------------------------------------------- */
+afr_status afr_reconstruct(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                           const afr_params *params, float *rgb, float *aux, hipStream_t stream);
+afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                 const afr_params *params, float *rgb, float *aux,
+                                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Adjoint of afr_reconstruct with the tile statistics held fixed (they are inputs of the gather,
+ * as the paper's tile information is, Sec. 4.2). With pi_s(p) = exp(E_s - E_max)/W':
+ *   grad_slot[ch][s] = sum_p grad_rgb[ch][p] pi_s(p)
+ *   grad_params[0]   = dl/dsigma, grad_params[1] = dl/dtau, through sx2, sy2 and kt2.
+ * The per-pair weights are recomputed, not stored. Requires tau > 0. Deterministic: no floating-
+ * point atomics; reductions run in a fixed order.
+ *
+ *   rgb, aux   outputs of the forward call on the same inputs
+ *   grad_rgb   [3][H][W] dl/dC
+ *   grad_slot  [3][K][H][W] float output (empty slots get 0)
+ *   grad_params 2 floats, device
+ *   ws         at least afr_backward_workspace_bytes(width, height) bytes
+ * ------------------------------------------------------------------------------------------- */
+size_t afr_backward_workspace_bytes(int32_t width, int32_t height);
+afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                    const afr_params *params, const float *rgb, const float *aux,
+                                    const float *grad_rgb, float *grad_slot, float *grad_params,
+                                    void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFR_H */

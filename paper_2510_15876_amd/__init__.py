@@ -1,0 +1,355 @@
+"""Adaptive frameless reconstruction on MI355X: Python binding of ``libafr.so``.
+
+The binding only marshals arguments: every step of the reconstruction path runs in the HIP kernels
+behind the C ABI declared in ``include/afr.h``. PyTorch supplies device memory and the current HIP
+stream. There is no CPU fallback: calls fail loudly when the library is missing or no GPU is present.
+
+Function names follow the C ABI: ``build_deep_buffer``, ``estimate_gradients``, ``reconstruct``,
+``reconstruct_plain``, ``reconstruct_backward``; ``ReconstructFn`` wraps forward and adjoint as a
+``torch.autograd.Function`` with gradients for the sample colours and for ``sigma`` and ``tau``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, replace
+from typing import Optional
+
+import torch
+
+__all__ = [
+    "AfrError", "Params", "DeepBuffer", "STAT_NAMES", "NSTAT", "STAT", "library", "lib_path",
+    "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain",
+    "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libafr.so")
+
+STAT_NAMES = ("gx", "gy", "gt", "vol", "var", "lmean", "ex2", "ey2", "sx2", "sy2", "kt2")
+NSTAT = len(STAT_NAMES)
+STAT = {n: i for i, n in enumerate(STAT_NAMES)}
+PRECISIONS = {"fp32": 0, "fp16": 1}
+
+
+class AfrError(RuntimeError):
+    pass
+
+
+# ---- C structs (mirror include/afr.h) ------------------------------------------------------------
+
+class _Samples(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("r", ctypes.c_void_p), ("g", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
+class _DeepBuffer(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("t_ref", ctypes.c_float),
+                ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("tage", ctypes.c_void_p),
+                ("r", ctypes.c_void_p), ("g", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("src", ctypes.c_void_p)]
+
+
+class _TileStats(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("tiles_x", ctypes.c_int32),
+                ("tiles_y", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float), ("tau", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("e_min", ctypes.c_float), ("e_max", ctypes.c_float),
+                ("g_floor", ctypes.c_float), ("dt_floor", ctypes.c_float),
+                ("age_floor", ctypes.c_float), ("radius", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("t_now", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def library():
+    """Load libafr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise AfrError(f"{_LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp, st = ctypes.c_void_p, ctypes.c_int
+    lib.afr_status_string.restype = ctypes.c_char_p
+    lib.afr_status_string.argtypes = [st]
+    lib.afr_version.restype = ctypes.c_char_p
+    lib.afr_version.argtypes = []
+    lib.afr_build_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_build_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32]
+    lib.afr_build_deep_buffer.restype = st
+    lib.afr_build_deep_buffer.argtypes = [P(_Samples), P(_DeepBuffer), vp, ctypes.c_size_t, vp, vp]
+    lib.afr_estimate_gradients.restype = st
+    lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
+    for name in ("afr_reconstruct", "afr_reconstruct_plain"):
+        f = getattr(lib, name)
+        f.restype = st
+        f.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp, vp, vp]
+    lib.afr_backward_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.afr_reconstruct_backward.restype = st
+    lib.afr_reconstruct_backward.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp, vp, vp,
+                                             vp, vp, vp, ctypes.c_size_t, vp]
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = library().afr_status_string(status).decode()
+        raise AfrError(f"{what}: {msg} (status {status})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise AfrError("libafr takes device tensors")
+    if not t.is_contiguous():
+        raise AfrError("libafr takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---- Python-side containers ----------------------------------------------------------------------
+
+@dataclass
+class Params:
+    """Filter constants (see ``afr_params`` in include/afr.h)."""
+    sigma: float = 1.0
+    tau: float = 0.5
+    alpha: float = 3.47e-3
+    e_min: float = 0.5
+    e_max: float = 1.0
+    g_floor: float = 1e-3
+    dt_floor: float = 1e-3
+    age_floor: float = 1e-3
+    radius: int = 2
+    tile: int = 8
+    t_now: float = 0.0
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+    def _c(self) -> _Params:
+        return _Params(self.sigma, self.tau, self.alpha, self.e_min, self.e_max, self.g_floor,
+                       self.dt_floor, self.age_floor, int(self.radius), int(self.tile),
+                       self.t_now)
+
+
+def tiles_shape(width: int, height: int, tile: int):
+    return (-(-height // tile), -(-width // tile))
+
+
+class DeepBuffer:
+    """Per-pixel deep buffer in device memory: ``planes[6, K, H, W]`` (ox, oy, tage, r, g, b; plane k
+    holds every pixel's k-th newest sample), ``count[H, W]`` (uint8), ``src[K, H, W]`` (int32 stream
+    index, -1 when empty)."""
+
+    FIELDS = ("ox", "oy", "tage", "r", "g", "b")
+
+    def __init__(self, width: int, height: int, k: int, precision: str = "fp32",
+                 t_ref: float = 0.0, device="cuda", with_src: bool = True):
+        if precision not in PRECISIONS:
+            raise AfrError(f"precision must be one of {tuple(PRECISIONS)}")
+        self.width, self.height, self.k = int(width), int(height), int(k)
+        self.precision = precision
+        self.t_ref = float(t_ref)
+        dt = torch.float16 if precision == "fp16" else torch.float32
+        self.planes = torch.empty((6, self.k, self.height, self.width), dtype=dt, device=device)
+        self.count = torch.empty((self.height, self.width), dtype=torch.uint8, device=device)
+        self.src = (torch.empty((self.k, self.height, self.width), dtype=torch.int32, device=device)
+                    if with_src else None)
+
+    def field(self, name: str) -> torch.Tensor:
+        return self.planes[self.FIELDS.index(name)]
+
+    def colours(self) -> torch.Tensor:
+        return self.planes[3:6]
+
+    def clone(self) -> "DeepBuffer":
+        o = DeepBuffer.__new__(DeepBuffer)
+        o.width, o.height, o.k, o.precision, o.t_ref = (self.width, self.height, self.k,
+                                                         self.precision, self.t_ref)
+        o.planes = self.planes.clone()
+        o.count = self.count.clone()
+        o.src = None if self.src is None else self.src.clone()
+        return o
+
+    def _c(self, colours: Optional[torch.Tensor] = None) -> _DeepBuffer:
+        p = self.planes
+        c = p[3:6] if colours is None else colours
+        if colours is not None and (colours.dtype != p.dtype or tuple(colours.shape) != tuple(p[3:6].shape)):
+            raise AfrError("replacement colours must match the buffer's colour planes")
+        if colours is not None and not colours.is_contiguous():
+            raise AfrError("replacement colours must be contiguous")
+        base = c.data_ptr()
+        step = c[0].numel() * c.element_size()
+        return _DeepBuffer(self.width, self.height, self.k, PRECISIONS[self.precision],
+                           self.t_ref, p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr(),
+                           base, base + step, base + 2 * step, _ptr(self.count).value,
+                           None if self.src is None else _ptr(self.src).value)
+
+
+def _stats_c(stats: torch.Tensor, tile: int) -> _TileStats:
+    if stats.dtype != torch.float32 or stats.dim() != 3 or stats.shape[0] != NSTAT:
+        raise AfrError(f"tile statistics must be float32 [{NSTAT}, Ty, Tx]")
+    return _TileStats(int(tile), int(stats.shape[2]), int(stats.shape[1]), _ptr(stats).value)
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device, key: str) -> torch.Tensor:
+    k = (key, str(device))
+    t = _ws_cache.get(k)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[k] = t
+    return t
+
+
+# ---- entry points --------------------------------------------------------------------------------
+
+def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precision: str = "fp32",
+                      t_ref: Optional[float] = None, out: Optional[DeepBuffer] = None,
+                      stream=None, dropped: Optional[torch.Tensor] = None):
+    """Build the per-pixel deep buffer from a device sample stream (float32 SoA).
+
+    Returns ``(buffer, dropped)`` where ``dropped`` is a device int64 tensor of one element."""
+    lib = library()
+    xs = [x, y, t, r, g, b]
+    for a in xs:
+        if a.dtype != torch.float32 or not a.is_cuda or a.dim() != 1:
+            raise AfrError("sample arrays must be 1-D float32 device tensors")
+    n = int(x.shape[0])
+    if t_ref is None:
+        raise AfrError("t_ref is required (every sample with t > t_ref is dropped)")
+    dev = x.device
+    if out is None:
+        out = DeepBuffer(width, height, k, precision, t_ref, device=dev)
+    else:
+        out.t_ref = float(t_ref)
+    if dropped is None:
+        dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+    s = _Samples(*(a.data_ptr() if n else None for a in xs), n)
+    wsb = lib.afr_build_workspace_bytes(n, width, height, k)
+    ws = _workspace(wsb, dev, "build")
+    bc = out._c()
+    _check(lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(bc), _ptr(ws), wsb,
+                                     _ptr(dropped), _stream(stream)), "afr_build_deep_buffer")
+    return out, dropped
+
+
+def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tensor] = None,
+                       stream=None, colours=None) -> torch.Tensor:
+    """Per-tile statistics ``[NSTAT, Ty, Tx]`` float32 (planes in ``STAT_NAMES`` order)."""
+    lib = library()
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    if out is None:
+        out = torch.empty((NSTAT, ty, tx), dtype=torch.float32, device=buf.planes.device)
+    bc, pc, sc = buf._c(colours), params._c(), _stats_c(out, params.tile)
+    _check(lib.afr_estimate_gradients(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc),
+                                      _stream(stream)), "afr_estimate_gradients")
+    return out
+
+
+def _reconstruct(name, buf, stats, params, rgb, aux, want_aux, stream, colours=None):
+    lib = library()
+    dev = buf.planes.device
+    if rgb is None:
+        rgb = torch.empty((3, buf.height, buf.width), dtype=torch.float32, device=dev)
+    if aux is None and want_aux:
+        aux = torch.empty((2, buf.height, buf.width), dtype=torch.float32, device=dev)
+    bc, pc, sc = buf._c(colours), params._c(), _stats_c(stats, params.tile)
+    _check(getattr(lib, name)(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc), _ptr(rgb),
+                              _ptr(aux), _stream(stream)), name)
+    return rgb, aux
+
+
+def reconstruct(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, aux=None,
+                want_aux: bool = True, stream=None, colours=None):
+    """LDS-tiled gather. Returns ``(rgb [3,H,W], aux [2,H,W] or None)``."""
+    return _reconstruct("afr_reconstruct", buf, stats, params, rgb, aux, want_aux, stream, colours)
+
+
+def reconstruct_plain(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, aux=None,
+                      want_aux: bool = True, stream=None, colours=None):
+    """Direct gather (one thread per pixel, one exponential per pair)."""
+    return _reconstruct("afr_reconstruct_plain", buf, stats, params, rgb, aux, want_aux, stream,
+                        colours)
+
+
+def reconstruct_backward(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb, aux, grad_rgb,
+                         grad_slot=None, grad_params=None, stream=None, colours=None):
+    """Adjoint of the gather: ``(grad_slot [3,K,H,W] float32, grad_params [2] = (d sigma, d tau))``."""
+    lib = library()
+    dev = buf.planes.device
+    if grad_slot is None:
+        grad_slot = torch.empty((3, buf.k, buf.height, buf.width), dtype=torch.float32, device=dev)
+    if grad_params is None:
+        grad_params = torch.empty(2, dtype=torch.float32, device=dev)
+    wsb = lib.afr_backward_workspace_bytes(buf.width, buf.height)
+    ws = _workspace(wsb, dev, "backward")
+    bc, pc, sc = buf._c(colours), params._c(), _stats_c(stats, params.tile)
+    grad_rgb = grad_rgb.contiguous().float()
+    _check(lib.afr_reconstruct_backward(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
+                                        _ptr(rgb), _ptr(aux), _ptr(grad_rgb), _ptr(grad_slot),
+                                        _ptr(grad_params), _ptr(ws), wsb, _stream(stream)),
+           "afr_reconstruct_backward")
+    return grad_slot, grad_params
+
+
+class ReconstructFn(torch.autograd.Function):
+    """Differentiable estimate + gather.
+
+    Inputs: slot colours ``[3, K, H, W]`` (the buffer's colour planes or a replacement of the same
+    dtype), ``sigma`` and ``tau`` (0-d float tensors). Tile statistics are recomputed from the buffer
+    at the given sigma and tau and treated as constants (stop-gradient) in the adjoint, matching
+    ``afr_reconstruct_backward``. Gradients flow to the colours and to sigma and tau.
+    """
+
+    @staticmethod
+    def forward(ctx, colours, sigma, tau, buf: DeepBuffer, params: Params, form: str = "tiled"):
+        p = params.with_(sigma=float(sigma), tau=float(tau))
+        colours = colours.detach().contiguous()
+        stats = estimate_gradients(buf, p, colours=colours)
+        fn = reconstruct if form == "tiled" else reconstruct_plain
+        rgb, aux = fn(buf, stats, p, colours=colours)
+        ctx.save_for_backward(colours, rgb, aux, stats)
+        ctx.buf, ctx.params = buf, p
+        ctx.colour_dtype = colours.dtype
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        colours, rgb, aux, stats = ctx.saved_tensors
+        gslot, gpar = reconstruct_backward(ctx.buf, stats, ctx.params, rgb, aux, grad_rgb,
+                                           colours=colours)
+        gc = gslot.to(ctx.colour_dtype) if ctx.needs_input_grad[0] else None
+        gs = gpar[0] if ctx.needs_input_grad[1] else None
+        gt = gpar[1] if ctx.needs_input_grad[2] else None
+        return gc, gs, gt, None, None, None
+
+
+def reconstruct_differentiable(buf: DeepBuffer, params: Params, sigma, tau, colours=None,
+                               form: str = "tiled"):
+    """``rgb = ReconstructFn(colours, sigma, tau)``; colours default to the buffer's own planes."""
+    c = buf.colours() if colours is None else colours
+    return ReconstructFn.apply(c, sigma, tau, buf, params, form)

@@ -1,0 +1,141 @@
+// C ABI entry points of libafr: synchronous argument validation, workspace carving, and launches on
+// the caller's stream. No entry point allocates device memory or synchronises.
+#include <cmath>
+
+#include "afr_internal.h"
+
+namespace {
+
+using namespace afr;
+
+afr_status from_hip(hipError_t e) { return e == hipSuccess ? AFR_OK : AFR_E_DEVICE; }
+
+bool finite(float v) { return std::isfinite(v); }
+
+afr_status check_buffer(const afr_deep_buffer *b) {
+    if (!b) return AFR_E_INVALID;
+    if (b->width < 1 || b->height < 1) return AFR_E_RANGE;
+    if (b->k < 1 || b->k > 255) return AFR_E_RANGE;
+    if (b->precision != AFR_FP32 && b->precision != AFR_FP16) return AFR_E_RANGE;
+    // every flat slot index must fit in int32 arithmetic on the device
+    if ((int64_t)b->width * b->height * b->k >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    if (!finite(b->t_ref)) return AFR_E_RANGE;
+    if (!b->ox || !b->oy || !b->tage || !b->r || !b->g || !b->b || !b->count) return AFR_E_INVALID;
+    return AFR_OK;
+}
+
+afr_status check_params(const afr_params *p, const afr_deep_buffer *b) {
+    if (!p) return AFR_E_INVALID;
+    const float vals[] = {p->sigma, p->tau, p->alpha, p->e_min, p->g_floor, p->dt_floor,
+                          p->age_floor, p->t_now};
+    for (float v : vals)
+        if (!finite(v)) return AFR_E_RANGE;
+    if (p->sigma < 0.0f || p->tau < 0.0f || p->alpha < 0.0f || p->g_floor < 0.0f) return AFR_E_RANGE;
+    if (!(p->e_min > 0.0f) || !(p->e_max > 0.0f) || std::isnan(p->e_max)) return AFR_E_RANGE;
+    if (!(p->dt_floor > 0.0f) || !(p->age_floor > 0.0f)) return AFR_E_RANGE;
+    if (p->radius < 0 || p->radius > kMaxRadius) return AFR_E_RANGE;
+    if (p->tile < 1 || p->tile > kMaxTile) return AFR_E_RANGE;
+    if (b && !(p->t_now >= b->t_ref)) return AFR_E_RANGE;
+    return AFR_OK;
+}
+
+afr_status check_stats(const afr_tile_stats *s, const afr_deep_buffer *b, const afr_params *p) {
+    if (!s || !s->data) return AFR_E_INVALID;
+    if (s->tile != p->tile) return AFR_E_INVALID;
+    if (s->tiles_x != (b->width + s->tile - 1) / s->tile ||
+        s->tiles_y != (b->height + s->tile - 1) / s->tile)
+        return AFR_E_INVALID;
+    return AFR_OK;
+}
+
+#define AFR_TRY(expr)                         \
+    do {                                      \
+        const afr_status _st = (expr);        \
+        if (_st != AFR_OK) return _st;        \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *afr_status_string(afr_status s) {
+    switch (s) {
+        case AFR_OK: return "ok";
+        case AFR_E_INVALID: return "invalid argument";
+        case AFR_E_RANGE: return "argument out of range";
+        case AFR_E_DEVICE: return "device error";
+        case AFR_E_NOMEM: return "workspace too small";
+        case AFR_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *afr_version(void) { return "afr 0.1.0 gfx950"; }
+
+size_t afr_build_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t k) {
+    (void)k;
+    if (n < 0 || width < 1 || height < 1) return 0;
+    return build_ws_bytes(n, width, height);
+}
+
+afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                 size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream) {
+    AFR_TRY(check_buffer(out));
+    if (!s || s->n < 0) return AFR_E_INVALID;
+    if (s->n >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    if (s->n > 0 && (!s->x || !s->y || !s->t || !s->r || !s->g || !s->b)) return AFR_E_INVALID;
+    if (!ws) return AFR_E_INVALID;
+    if (ws_bytes < build_ws_bytes(s->n, out->width, out->height)) return AFR_E_NOMEM;
+    const BuildWs w = build_ws_carve(ws, s->n, out->width, out->height);
+    unsigned long long *dropped =
+        dropped_dev ? reinterpret_cast<unsigned long long *>(dropped_dev) : w.dropped_internal;
+    return from_hip(launch_build(*s, *out, w, dropped, stream));
+}
+
+afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *params,
+                                  afr_tile_stats *out, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(out, buf, params));
+    return from_hip(launch_estimate(*buf, *params, *out, stream));
+}
+
+afr_status afr_reconstruct(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                           const afr_params *params, float *rgb, float *aux, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!rgb) return AFR_E_INVALID;
+    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, rgb, aux, stream));
+}
+
+afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                 const afr_params *params, float *rgb, float *aux,
+                                 hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!rgb) return AFR_E_INVALID;
+    return from_hip(launch_reconstruct_plain(*buf, *stats, *params, rgb, aux, stream));
+}
+
+size_t afr_backward_workspace_bytes(int32_t width, int32_t height) {
+    if (width < 1 || height < 1) return 0;
+    return backward_ws_bytes(width, height);
+}
+
+afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                    const afr_params *params, const float *rgb, const float *aux,
+                                    const float *grad_rgb, float *grad_slot, float *grad_params,
+                                    void *ws, size_t ws_bytes, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!(params->tau > 0.0f)) return AFR_E_RANGE;
+    if (!rgb || !aux || !grad_rgb || !grad_slot || !grad_params || !ws) return AFR_E_INVALID;
+    if (ws_bytes < backward_ws_bytes(buf->width, buf->height)) return AFR_E_NOMEM;
+    return from_hip(launch_backward(*buf, *stats, *params, rgb, aux, grad_rgb, grad_slot,
+                                    grad_params, ws, stream));
+}
+
+}  // extern "C"

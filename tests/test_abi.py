@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function that
+include/afr.h declares, and validates arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def afr():
+    import paper_2510_15876_amd as afr
+    if not os.path.exists(afr.lib_path()):
+        from paper_2510_15876_amd import _build
+        _build.build()
+    afr.library()
+    return afr
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "afr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(afr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("afr_build_deep_buffer", "afr_estimate_gradients", "afr_reconstruct",
+              "afr_reconstruct_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(afr):
+    lib = afr.library()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_no_torch_types_in_the_header():
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "afr.h")).read(), flags=re.S)
+    for bad in ("torch", "at::", "c10", "Tensor"):
+        assert bad not in src
+
+
+def test_status_strings_and_sizes(afr):
+    lib = afr.library()
+    assert lib.afr_status_string(0) == b"ok"
+    assert lib.afr_status_string(4) == b"workspace too small"
+    assert lib.afr_version().startswith(b"afr")
+    a = lib.afr_build_workspace_bytes(1000, 64, 64, 4)
+    b = lib.afr_build_workspace_bytes(2000, 64, 64, 4)
+    assert b - a >= 7680 and a > 64 * 64 * 8
+    assert lib.afr_build_workspace_bytes(-1, 64, 64, 4) == 0
+    assert lib.afr_backward_workspace_bytes(512, 512) >= 3 * 512 * 512 * 4
+    assert lib.afr_backward_workspace_bytes(0, 5) == 0
+
+
+def _fake_buffer(afr, w=16, h=8, k=4, prec=0, t_ref=10.0, null_plane=False):
+    # host addresses only: every call below must fail validation before touching them
+    dummy = 0x1000
+    return afr._DeepBuffer(w, h, k, prec, t_ref, None if null_plane else dummy, dummy, dummy,
+                           dummy, dummy, dummy, dummy, None)
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (dict(), None),
+    (dict(k=0), 2), (dict(k=256), 2), (dict(w=0), 2), (dict(prec=3), 2),
+    (dict(null_plane=True), 1), (dict(w=1 << 16, h=1 << 12, k=16), 2),
+])
+def test_buffer_validation(afr, mutate, expect):
+    lib = afr.library()
+    kw = dict(w=16, h=8, k=4, prec=0, t_ref=10.0)
+    kw.update(mutate)
+    b = _fake_buffer(afr, **kw)
+    p = afr.Params(t_now=11.0)._c()
+    # NULL stats pointer: a valid buffer gets as far as the statistics check (invalid = 1)
+    st = lib.afr_estimate_gradients(ctypes.byref(b), ctypes.byref(p), None, None)
+    assert st == (1 if expect is None else expect)
+
+
+@pytest.mark.parametrize("field,value,expect", [
+    ("t_now", 9.0, 2),          # t_now < t_ref
+    ("radius", 5, 2), ("radius", -1, 2), ("tile", 0, 2), ("tile", 17, 2),
+    ("e_min", 0.0, 2), ("e_max", 0.0, 2), ("sigma", -1.0, 2), ("tau", float("nan"), 2),
+    ("dt_floor", 0.0, 2), ("age_floor", -1.0, 2), ("alpha", float("inf"), 2),
+])
+def test_param_validation(afr, field, value, expect):
+    lib = afr.library()
+    b = _fake_buffer(afr)
+    p = afr.Params(t_now=11.0).with_(**{field: value})._c()
+    s = afr._TileStats(8, 2, 1, 0x1000)
+    assert lib.afr_estimate_gradients(ctypes.byref(b), ctypes.byref(p), ctypes.byref(s), None) == expect
+
+
+def test_stats_geometry_and_workspace_checks(afr):
+    lib = afr.library()
+    b = _fake_buffer(afr, w=17, h=9)
+    p = afr.Params(t_now=11.0)._c()
+    bad = afr._TileStats(8, 2, 2, 0x1000)   # needs 3 x 2 tiles
+    assert lib.afr_reconstruct(ctypes.byref(b), ctypes.byref(bad), ctypes.byref(p), 0x2000, None, None) == 1
+    wrong_tile = afr._TileStats(4, 5, 3, 0x1000)
+    assert lib.afr_reconstruct(ctypes.byref(b), ctypes.byref(wrong_tile), ctypes.byref(p), 0x2000, None, None) == 1
+    ok = afr._TileStats(8, 3, 2, 0x1000)
+    assert lib.afr_reconstruct(ctypes.byref(b), ctypes.byref(ok), ctypes.byref(p), None, None, None) == 1
+    # backward: tau must be positive, workspace must be large enough
+    p0 = afr.Params(t_now=11.0, tau=0.0)._c()
+    args = [0x2000] * 6
+    assert lib.afr_reconstruct_backward(ctypes.byref(b), ctypes.byref(ok), ctypes.byref(p0), *args[:5], 0x3000, 1 << 30, None) == 2
+    small = lib.afr_backward_workspace_bytes(17, 9) - 1
+    assert lib.afr_reconstruct_backward(ctypes.byref(b), ctypes.byref(ok), ctypes.byref(p), *args[:5], 0x3000, small, None) == 4
+    # build: negative n, too small a workspace
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, -1)
+    assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None) == 1
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000)
+    assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 16, None, None) == 4
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1 << 31)
+    assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 40, None, None) == 2

@@ -1,0 +1,132 @@
+"""GPU adjoint against the FP64 reference adjoint and FP64 central finite differences (h = 1e-3).
+
+Slot-colour gradients are sums over up to (2R+1)^2 pixels of g(p) pi_s(p) with mixed signs, so the
+float32 result carries an absolute error proportional to the sum of the absolute terms,
+A_s = sum_p |g(p)| pi_s(p) (computed by the reference adjoint on |g|), not to |g_ref|. Tolerance per
+component: |g - g_ref| <= 1e-4 |g_ref| + 1e-5 A_s (each term is accurate to a few float32 ulps).
+d(sigma) and d(tau): 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+import afr_scenes as S
+import oracle as O
+from helpers import DEV, afr_mod, gpu_build, params, slots_to_reference_layout, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def _frame(seq, f, k):
+    wl = seq.frame_workload(f)
+    return wl
+
+
+def _loss_grad_gpu(rgb, gt):
+    torch = torch_mod()
+    d = rgb.double() - gt
+    e = torch.sqrt((d * d).mean())
+    return (d / (d.numel() * e)).float()
+
+
+def _check_slots(g, g_ref, a_ref):
+    tol = 1e-4 * np.abs(g_ref) + 1e-5 * a_ref
+    bad = np.abs(g - g_ref) > tol
+    rel = np.abs(g - g_ref).max() / max(np.abs(g_ref).max(), 1e-300)
+    print(f"  slot grads: max |diff| / max |g_ref| = {rel:.3g}", flush=True)
+    assert not bad.any(), f"{bad.sum()} slot gradients off; worst {np.abs(g - g_ref)[bad].max():.3g}"
+
+
+@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("size,k,precision", [(96, 4, "fp32"), (128, 8, "fp16"), (512, 8, "fp32")])
+def test_backward_matches_reference_adjoint(form, size, k, precision):
+    torch = torch_mod()
+    afr = afr_mod()
+    seq = S.make_c4_sequence(n_frames=2, width=size, height=size, k=k)
+    wl = seq.frame_workload(1)
+    print(f"backward parity {form} {size}x{size} K={k} {precision}", flush=True)
+    gt = S.ground_truth(seq.scene, size, size, wl.t_now, 4)
+    gbuf, _ = gpu_build(wl.stream, size, size, k, precision, wl.t_ref)
+    obuf, _ = O.build_buffer(wl.stream, size, size, k, precision, wl.t_ref)
+    gp, op = params(wl.t_now, sigma=1.0, tau=0.5)
+    stats = afr.estimate_gradients(gbuf, gp)
+    fn = afr.reconstruct if form == "tiled" else afr.reconstruct_plain
+    rgb, aux = fn(gbuf, stats, gp)
+    ost = O.estimate(obuf, op)
+    orgb, _ = O.reconstruct(obuf, ost, op)
+    # one upstream gradient, computed by the reference, drives both adjoints
+    og = O.rms_grad(orgb, gt)
+    g = torch.from_numpy(og).float().to(DEV)
+    gslot, gpar = afr.reconstruct_backward(gbuf, stats, gp, rgb, aux, g)
+    oslot, opar = O.backward(obuf, ost, op, og)
+    aslot, _ = O.backward(obuf, ost, op, np.abs(og))
+    print(f"  d(sigma, tau) gpu {gpar.cpu().numpy()} ref {opar}", flush=True)
+    np.testing.assert_allclose(gpar.cpu().numpy(), opar, rtol=1e-4)
+    _check_slots(slots_to_reference_layout(gslot.cpu().numpy()).astype(np.float64), oslot, aslot)
+
+
+def test_param_gradients_match_finite_differences_over_frames():
+    """C4 shape, reduced: 4 consecutive 60 Hz frames of a 256x256 K=8 stream; loss = mean over
+    frames of RMS against the analytic ground truth; FD of the FP64 reference forward."""
+    torch = torch_mod()
+    afr = afr_mod()
+    seq = S.make_c4_sequence(n_frames=4, width=256, height=256, k=8)
+    sig, tau, h = 1.0, 0.5, 1e-3
+    g_gpu = np.zeros(2)
+    fd = np.zeros(2)
+    for f in range(4):
+        wl = seq.frame_workload(f)
+        print(f"fd frame {f}", flush=True)
+        gt = S.ground_truth(seq.scene, 256, 256, wl.t_now, 4)
+        gbuf, _ = gpu_build(wl.stream, 256, 256, 8, "fp32", wl.t_ref)
+        gp, op = params(wl.t_now, sigma=sig, tau=tau)
+        stats = afr.estimate_gradients(gbuf, gp)
+        rgb, aux = afr.reconstruct(gbuf, stats, gp)
+        g = _loss_grad_gpu(rgb, torch.from_numpy(gt).to(DEV)) / 4.0
+        _, gpar = afr.reconstruct_backward(gbuf, stats, gp, rgb, aux, g)
+        g_gpu += gpar.cpu().numpy()
+        obuf, _ = O.build_buffer(wl.stream, 256, 256, 8, "fp32", wl.t_ref)
+        for i, name in enumerate(("sigma", "tau")):
+            lp = O.rms(O.forward(obuf, op.with_(**{name: getattr(op, name) + h}))[0], gt)
+            lm = O.rms(O.forward(obuf, op.with_(**{name: getattr(op, name) - h}))[0], gt)
+            fd[i] += (lp - lm) / (2 * h) / 4.0
+    print(f"gpu {g_gpu} fd {fd}", flush=True)
+    np.testing.assert_allclose(g_gpu, fd, rtol=1e-4)
+
+
+def test_autograd_function_matches_backward_and_reaches_stream_colours():
+    torch = torch_mod()
+    afr = afr_mod()
+    wl = S.make_workload("c1")
+    xs = [torch.from_numpy(a).to(DEV) for a in wl.stream.arrays()]
+    buf, _ = afr.build_deep_buffer(*xs, wl.width, wl.height, wl.k, "fp32", wl.t_ref)
+    p = afr.Params(t_now=wl.t_now)
+    gt = torch.from_numpy(S.ground_truth(wl.scene, wl.width, wl.height, wl.t_now, 4)).float().to(DEV)
+    sig = torch.tensor(1.2, device=DEV, requires_grad=True)
+    tau = torch.tensor(0.4, device=DEV, requires_grad=True)
+    # stream colours -> slot colours by the build's src map; autograd scatters back by index
+    col = torch.stack(xs[3:6]).requires_grad_(True)
+    src = buf.src.long()
+    slot = torch.where(src[None] >= 0, col[:, src.clamp(min=0)], torch.zeros((), device=DEV))
+    rgb = afr.reconstruct_differentiable(buf, p, sig, tau, colours=slot.contiguous())
+    loss = torch.sqrt(((rgb - gt) ** 2).mean())
+    loss.backward()
+    ob, _ = O.build_buffer(wl.stream, wl.width, wl.height, wl.k, "fp32", wl.t_ref)
+    op = O.Params(t_now=wl.t_now, sigma=1.2, tau=0.4)
+    orgb, _, ost = O.forward(ob, op)
+    og = O.rms_grad(orgb, gt.cpu().numpy().astype(np.float64))
+    oslot, opar = O.backward(ob, ost, op, og)
+    # End to end, the upstream gradient comes from the GPU's own forward output, which differs from
+    # the reference's by dC; |d(dl/dC)| <= max|dC| / (N RMS) per pixel, and it reaches a slot
+    # through sum_p pi_s(p) (the reference adjoint of a ones image).
+    dC = float(np.abs(rgb.detach().cpu().numpy() - orgb).max())
+    dg = dC / (orgb.size * O.rms(orgb, gt.cpu().numpy()))
+    aslot, _ = O.backward(ob, ost, op, np.abs(og) + 2 * dg / 1e-5)
+    np.testing.assert_allclose([sig.grad.item(), tau.grad.item()], opar, rtol=1e-4)
+    # stream-colour gradient = slot gradient scattered by src (each sample sits in at most one slot)
+    ref = np.zeros((3, len(wl.stream)))
+    aref = np.zeros((3, len(wl.stream)))
+    s = ob.src.reshape(-1)  # reference layout [H, W, K]
+    for c in range(3):
+        ref[c, s[s >= 0]] = oslot[c].reshape(-1)[s >= 0]
+        aref[c, s[s >= 0]] = aslot[c].reshape(-1)[s >= 0]
+    _check_slots(col.grad.cpu().numpy().astype(np.float64), ref, aref)

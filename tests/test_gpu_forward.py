@@ -1,0 +1,136 @@
+"""GPU estimate and gather against the FP64 reference.
+
+Tolerances:
+  * gather, float32 arithmetic, same stored buffer and statistics: max |C - C_ref| <= 1e-5 on [0,1]
+    colours (the target for plain FP32 output); the same bound holds end to end, statistics
+    included, and for the FP16-storage buffer against the reference on the same FP16 buffer;
+  * FP16 storage against the reference on the FP32 buffer: <= 2e-3 (storage quantisation);
+  * tile statistics: the estimator accumulates in FP64 but takes age weights from a float32
+    exponential (<= 2 ulp, 2.4e-7 relative) and stores float32, so gradients and means get
+    rtol 2e-6 with an absolute floor of 1e-7 / px (luminance in [0, 1]).
+"""
+import numpy as np
+import pytest
+
+import afr_scenes as S
+import oracle as O
+from helpers import (DEV, afr_mod, gpu_build, log_weight_sum, oracle_build_cached, params,
+                     reconstruct, stats_f32_as_f64, stats_to_gpu, torch_mod, workload)
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["plain", "tiled"]
+CASES = [("c1", "fp32"), ("c2", "fp32"), ("c0", "fp32"), ("c3", "fp16")]
+
+
+def _stat_tol(name):
+    return {"vol": (2e-6, 0.0), "var": (2e-6, 1e-9), "lmean": (2e-6, 1e-7)}.get(name, (2e-6, 1e-7))
+
+
+@pytest.mark.parametrize("name,precision", CASES + [("c3", "fp32")])
+def test_estimate_matches_reference(name, precision):
+    afr = afr_mod()
+    wl = workload(name)
+    print(f"estimate parity {name} {precision}", flush=True)
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, precision, wl.t_ref)
+    obuf, _ = oracle_build_cached(name, precision, wl.k)
+    gp, op = params(wl.t_now)
+    gst = afr.estimate_gradients(gbuf, gp).cpu().numpy().astype(np.float64)
+    ost = O.estimate(obuf, op)
+    for i, n in enumerate(O.STAT_NAMES):
+        rtol, atol = _stat_tol(n)
+        np.testing.assert_allclose(gst[i], ost[i], rtol=rtol, atol=atol, err_msg=f"stat {n}")
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("name,precision", CASES)
+def test_gather_matches_reference_on_reference_statistics(form, name, precision):
+    wl = workload(name)
+    print(f"gather parity {form} {name} {precision}", flush=True)
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, precision, wl.t_ref)
+    obuf, _ = oracle_build_cached(name, precision, wl.k)
+    gp, op = params(wl.t_now)
+    ost = O.estimate(obuf, op)
+    rgb, aux = reconstruct(form, gbuf, stats_to_gpu(ost), gp)
+    orgb, oaux = O.reconstruct(obuf, stats_f32_as_f64(ost), op)
+    err = np.abs(rgb.cpu().numpy() - orgb).max()
+    print(f"  max |C - C_ref| = {err:.3g}", flush=True)
+    assert err <= 1e-5
+    ga = aux.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(log_weight_sum(ga), log_weight_sum(oaux), rtol=0, atol=2e-5)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("name,precision", CASES)
+def test_end_to_end_matches_reference(form, name, precision):
+    afr = afr_mod()
+    wl = workload(name)
+    print(f"end-to-end parity {form} {name} {precision}", flush=True)
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, precision, wl.t_ref)
+    obuf, _ = oracle_build_cached(name, precision, wl.k)
+    gp, op = params(wl.t_now)
+    rgb, _ = reconstruct(form, gbuf, afr.estimate_gradients(gbuf, gp), gp)
+    orgb, _, _ = O.forward(obuf, op)
+    err = np.abs(rgb.cpu().numpy() - orgb).max()
+    print(f"  max |C - C_ref| = {err:.3g}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_fp16_storage_error_against_fp32_reference(form):
+    """The FP16-storage path against the FP64 reference run on the FP32 buffer: the storage
+    quantisation bound."""
+    afr = afr_mod()
+    wl = workload("c3")
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, "fp16", wl.t_ref)
+    obuf, _ = oracle_build_cached("c3", "fp32", wl.k)
+    gp, op = params(wl.t_now)
+    rgb, _ = reconstruct(form, gbuf, afr.estimate_gradients(gbuf, gp), gp)
+    orgb, _, _ = O.forward(obuf, op)
+    d = np.abs(rgb.cpu().numpy() - orgb)
+    print(f"fp16 storage {form}: max {d.max():.3g} p99 {np.quantile(d, 0.99):.3g} mean {d.mean():.3g}",
+          flush=True)
+    assert d.max() <= 2e-3
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("w,h,k,radius,tile", [(37, 23, 3, 2, 8), (1, 1, 2, 2, 8), (13, 5, 1, 0, 8),
+                                               (29, 31, 4, 4, 5), (40, 17, 5, 1, 16),
+                                               (19, 11, 2, 3, 1), (64, 8, 6, 2, 8)])
+def test_edge_geometries(form, w, h, k, radius, tile):
+    """Ragged image edges, a 1x1 image, R from 0 to 4, tiles from 1 to 16, holes (empty pixels)."""
+    afr = afr_mod()
+    rng = np.random.default_rng(w * 1000 + h * 10 + k)
+    n = max(1, int(w * h * k * 0.8))
+    scene = S.DiscScene(w, h, rng, 6, 50.0, speed=0.3, radius=(2.0, 6.0))
+    s = S.uniform_stream(scene, w, h, n, 50.0, 50.0, rng)
+    print(f"edge geometry {form} {w}x{h} K={k} R={radius} B={tile}", flush=True)
+    for precision in ("fp32", "fp16"):
+        gbuf, _ = gpu_build(s, w, h, k, precision, 50.0)
+        obuf, _ = O.build_buffer(s, w, h, k, precision, 50.0)
+        gp, op = params(53.0, radius=radius, tile=tile)
+        rgb, aux = reconstruct(form, gbuf, afr.estimate_gradients(gbuf, gp), gp)
+        orgb, oaux, _ = O.forward(obuf, op)
+        assert np.abs(rgb.cpu().numpy() - orgb).max() <= 1e-5
+        ga = aux.cpu().numpy()
+        assert np.array_equal(ga[1] > 0, oaux[1] > 0)  # coverage agrees exactly
+
+
+def test_reference_statistics_round_trip_and_constants():
+    """A constant-colour buffer reproduces the constant through the GPU gather (north-star
+    invariant), and the tiled and plain forms agree to float32 rounding."""
+    torch = torch_mod()
+    afr = afr_mod()
+    wl = workload("c2")
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, "fp32", wl.t_ref)
+    gp, _ = params(wl.t_now)
+    filled = (torch.arange(wl.k, device=DEV)[:, None, None] < gbuf.count[None, :, :].long())
+    const = torch.tensor([0.25, 0.5, 0.75], device=DEV)[:, None, None, None] * filled
+    stats = afr.estimate_gradients(gbuf, gp)
+    for fn in (afr.reconstruct, afr.reconstruct_plain):
+        rgb, _ = fn(gbuf, stats, gp, colours=const.float().contiguous())
+        for c, v in enumerate((0.25, 0.5, 0.75)):
+            assert float((rgb[c] - v).abs().max()) <= 1e-6
+    a, _ = afr.reconstruct(gbuf, stats, gp)
+    b, _ = afr.reconstruct_plain(gbuf, stats, gp)
+    assert float((a - b).abs().max()) <= 2e-6
