@@ -178,6 +178,15 @@ afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stat
                                  const afr_params *params, float *rgb, float *aux,
                                  hipStream_t stream);
 
+/* afr_reconstruct with an explicit launch shape: tiles_per_wave (1, 2 or 4; 0 = the library's choice)
+ * statistics tiles are processed side by side by one 64-lane wave. The shape changes only how work is
+ * spread over lanes: every pixel sums the same terms in the same order, so all shapes give bit-identical
+ * output. Used by the tuner; shapes the kernel does not support for the given radius fall back to a
+ * supported one. */
+afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                  const afr_params *params, int32_t tiles_per_wave, float *rgb,
+                                  float *aux, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Adjoint of afr_reconstruct with the tile statistics held fixed (they are inputs of the gather,
  * as the paper's tile information is, Sec. 4.2). With pi_s(p) = exp(E_s - E_max)/W':

@@ -19,7 +19,7 @@ import torch
 
 __all__ = [
     "AfrError", "Params", "DeepBuffer", "STAT_NAMES", "NSTAT", "STAT", "library", "lib_path",
-    "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain",
+    "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
 ]
 
@@ -97,6 +97,9 @@ def library():
         f = getattr(lib, name)
         f.restype = st
         f.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp, vp, vp]
+    lib.afr_reconstruct_launch.restype = st
+    lib.afr_reconstruct_launch.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), ctypes.c_int32,
+                                           vp, vp, vp]
     lib.afr_backward_workspace_bytes.restype = ctypes.c_size_t
     lib.afr_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.afr_reconstruct_backward.restype = st
@@ -287,6 +290,22 @@ def reconstruct(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, 
                 want_aux: bool = True, stream=None, colours=None):
     """LDS-tiled gather. Returns ``(rgb [3,H,W], aux [2,H,W] or None)``."""
     return _reconstruct("afr_reconstruct", buf, stats, params, rgb, aux, want_aux, stream, colours)
+
+
+def reconstruct_launch(buf: DeepBuffer, stats: torch.Tensor, params: Params, tiles_per_wave: int,
+                       rgb=None, aux=None, want_aux: bool = True, stream=None, colours=None):
+    """LDS-tiled gather with an explicit launch shape (bit-identical output for every shape)."""
+    lib = library()
+    dev = buf.planes.device
+    if rgb is None:
+        rgb = torch.empty((3, buf.height, buf.width), dtype=torch.float32, device=dev)
+    if aux is None and want_aux:
+        aux = torch.empty((2, buf.height, buf.width), dtype=torch.float32, device=dev)
+    bc, pc, sc = buf._c(colours), params._c(), _stats_c(stats, params.tile)
+    _check(lib.afr_reconstruct_launch(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
+                                      int(tiles_per_wave), _ptr(rgb), _ptr(aux), _stream(stream)),
+           "afr_reconstruct_launch")
+    return rgb, aux
 
 
 def reconstruct_plain(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, aux=None,

@@ -106,7 +106,19 @@ afr_status afr_reconstruct(const afr_deep_buffer *buf, const afr_tile_stats *sta
     AFR_TRY(check_params(params, buf));
     AFR_TRY(check_stats(stats, buf, params));
     if (!rgb) return AFR_E_INVALID;
-    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, rgb, aux, stream));
+    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, 2, rgb, aux, stream));
+}
+
+afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                  const afr_params *params, int32_t tiles_per_wave, float *rgb,
+                                  float *aux, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!rgb) return AFR_E_INVALID;
+    if (tiles_per_wave < 0 || tiles_per_wave > 4) return AFR_E_RANGE;
+    const int tpw = tiles_per_wave == 0 ? 2 : tiles_per_wave;
+    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, tpw, rgb, aux, stream));
 }
 
 afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stats *stats,

@@ -5,12 +5,15 @@
 // per pixel; the same final state is the top-K by key (t, stream index) of the samples binned to the
 // pixel, which this file computes with a counting sort:
 //   1. k_build_clear   zero the per-pixel arrival counters and the dropped counter
-//   2. k_build_count   validate each sample, count arrivals per home pixel (integer atomics)
+//   2. k_build_count   read x, y; samples inside the image take an arrival rank in their home pixel
+//                      (the return value of an integer atomic), others are dropped
 //   3. scan            exclusive prefix sum of the counts -> bucket offsets
-//   4. k_build_scatter write (time, index) keys into each pixel's bucket (order inside is arbitrary)
-//   5. k_build_select  per pixel: register top-K over its bucket, then gather and store the slots
+//   4. k_build_scatter read the whole sample and write one 32-byte record (order key, ox, oy, t, r,
+//                      g, b) to bucket[offset + rank]; a sample that fails the remaining validity
+//                      checks writes key 0 and is dropped (no atomics in this pass)
+//   5. k_build_select  per pixel: register top-K over its contiguous records, then store the slots
 // Every decision is integer or an exact comparison of stored float32 inputs, so the result is
-// bit-exact and independent of launch shape and atomic order.
+// bit-exact and independent of launch shape and atomic order (the rank only orders a bucket).
 #include "afr_internal.h"
 
 namespace afr {
@@ -26,11 +29,14 @@ struct ValidCtx {
     int32_t fp16;
 };
 
-// Validity rule shared by the count and scatter passes (they must agree sample by sample).
-__device__ inline bool sample_valid(float x, float y, float t, float r, float g, float b,
-                                    const ValidCtx &c) {
-    bool ok = isfinite(x) && isfinite(y) && isfinite(t) && isfinite(r) && isfinite(g) && isfinite(b);
-    ok = ok && x >= 0.0f && x < (float)c.w && y >= 0.0f && y < (float)c.h && t <= c.t_ref;
+// Validity: the position decides the home pixel (checked in the count pass); time, colour and the
+// binary16 range are checked in the scatter pass. Together they are the rule of afr.h.
+__device__ inline bool position_valid(float x, float y, const ValidCtx &c) {
+    return isfinite(x) && isfinite(y) && x >= 0.0f && x < (float)c.w && y >= 0.0f && y < (float)c.h;
+}
+
+__device__ inline bool payload_valid(float t, float r, float g, float b, const ValidCtx &c) {
+    bool ok = isfinite(t) && isfinite(r) && isfinite(g) && isfinite(b) && t <= c.t_ref;
     if (ok && c.fp16) {
         // binary16 round-to-nearest-even overflows to infinity exactly when |v| >= 65520
         const float age = c.t_ref - t;
@@ -51,18 +57,20 @@ __global__ void k_build_clear(int32_t *cnt, int32_t hw, unsigned long long *drop
     if (blockIdx.x == 0 && threadIdx.x == 0) *dropped = 0ull;
 }
 
-__global__ void k_build_count(afr_samples s, ValidCtx c, int32_t *cnt,
+__global__ void k_build_count(afr_samples s, ValidCtx c, int32_t *cnt, int32_t *rank,
                               unsigned long long *dropped) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) {
         const float x = s.x[i], y = s.y[i];
-        if (sample_valid(x, y, s.t[i], s.r[i], s.g[i], s.b[i], c)) {
+        int rk = -1;
+        if (position_valid(x, y, c)) {
             const int p = (int)floorf(y) * c.w + (int)floorf(x);
-            atomicAdd(&cnt[p], 1);
+            rk = atomicAdd(&cnt[p], 1);
         } else {
             ++bad;
         }
+        rank[i] = rk;
     }
     bad = wave_sum_int(bad);  // every lane reaches this point: no early exit above
     if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
@@ -147,111 +155,144 @@ __device__ inline unsigned long long order_key(float t, int i) {
 
 __device__ inline int key_index(unsigned long long key) { return (int)(unsigned)(key & 0xffffffffu); }
 
-__global__ void k_build_scatter(afr_samples s, ValidCtx c, const int32_t *off, int32_t *cnt,
-                                unsigned long long *bucket) {
+// One bucket record per sample routed to a pixel: order key (0 = invalid) and the stored fields.
+struct alignas(16) Record {
+    unsigned long long key;
+    float ox, oy, t, r, g, b;
+};
+static_assert(sizeof(Record) == 32, "bucket record is 32 bytes");
+
+__global__ void k_build_scatter(afr_samples s, ValidCtx c, const int32_t *off, const int32_t *rank,
+                                Record *bucket, unsigned long long *dropped) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) {
-        const float x = s.x[i], y = s.y[i], t = s.t[i];
-        if (!sample_valid(x, y, t, s.r[i], s.g[i], s.b[i], c)) continue;
-        const int p = (int)floorf(y) * c.w + (int)floorf(x);
-        const int pos = off[p] + atomicSub(&cnt[p], 1) - 1;
-        bucket[pos] = order_key(t, (int)i);
+        const int rk = rank[i];
+        if (rk < 0) continue;
+        const float x = s.x[i], y = s.y[i], t = s.t[i], r = s.r[i], g = s.g[i], b = s.b[i];
+        const float fx = floorf(x), fy = floorf(y);
+        const int p = (int)fy * c.w + (int)fx;
+        Record rec;
+        const bool ok = payload_valid(t, r, g, b, c);
+        bad += ok ? 0 : 1;
+        rec.key = ok ? order_key(t, (int)i) : 0ull;
+        rec.ox = x - fx;
+        rec.oy = y - fy;
+        rec.t = t;
+        rec.r = r;
+        rec.g = g;
+        rec.b = b;
+        bucket[off[p] + rk] = rec;
     }
+    bad = wave_sum_int(bad);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
 }
 
-
 template <typename S>
-__device__ inline void store_slot(const afr_samples &s, const afr_deep_buffer &out, size_t o,
-                                  int i) {
+__device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Record *rec) {
     S *ox = static_cast<S *>(out.ox), *oy = static_cast<S *>(out.oy);
     S *ta = static_cast<S *>(out.tage), *r = static_cast<S *>(out.r);
     S *g = static_cast<S *>(out.g), *b = static_cast<S *>(out.b);
-    if (i >= 0) {
-        const float x = s.x[i], y = s.y[i];
-        ox[o] = Codec<S>::enc(x - floorf(x));
-        oy[o] = Codec<S>::enc(y - floorf(y));
-        ta[o] = Codec<S>::enc_time(s.t[i], out.t_ref);
-        r[o] = Codec<S>::enc(s.r[i]);
-        g[o] = Codec<S>::enc(s.g[i]);
-        b[o] = Codec<S>::enc(s.b[i]);
+    if (rec) {
+        const Record e = *rec;
+        ox[o] = Codec<S>::enc(e.ox);
+        oy[o] = Codec<S>::enc(e.oy);
+        ta[o] = Codec<S>::enc_time(e.t, out.t_ref);
+        r[o] = Codec<S>::enc(e.r);
+        g[o] = Codec<S>::enc(e.g);
+        b[o] = Codec<S>::enc(e.b);
+        if (out.src) out.src[o] = key_index(e.key);
     } else {
         ox[o] = oy[o] = ta[o] = r[o] = g[o] = b[o] = Codec<S>::enc(0.0f);
+        if (out.src) out.src[o] = -1;
     }
-    if (out.src) out.src[o] = i;
 }
 
 template <typename S, int KMAX>
-__global__ void k_build_select(afr_samples s, afr_deep_buffer out, const int32_t *off,
-                               const unsigned long long *bucket) {
+__global__ void k_build_select(afr_deep_buffer out, const int32_t *off, const Record *bucket) {
     const int hw = out.width * out.height;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= hw) return;
     const int K = out.k;
     const int b0 = off[p], b1 = off[p + 1];
     unsigned long long top[KMAX];
+    int pos[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) top[k] = 0ull;
+    for (int k = 0; k < KMAX; ++k) {
+        top[k] = 0ull;
+        pos[k] = -1;
+    }
+    int nvalid = 0;
     for (int e = b0; e < b1; ++e) {
-        // insertion into a descending register list: one unsigned compare and two selects per
-        // entry, so every lane runs the same instruction stream
-        unsigned long long c = bucket[e];
+        // insertion into a descending register list: one unsigned compare and selects per entry,
+        // so every lane runs the same instruction stream
+        unsigned long long c = bucket[e].key;
+        int ce = e;
+        nvalid += c != 0ull;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const unsigned long long a = top[k];
+            const int ae = pos[k];
             const bool gt = c > a;
             top[k] = gt ? c : a;
+            pos[k] = gt ? ce : ae;
             c = gt ? a : c;
+            ce = gt ? ae : ce;
         }
     }
-    const int n = min(b1 - b0, K);
+    const int n = min(nvalid, K);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-        if (k < K) store_slot<S>(s, out, (size_t)k * hw + p, k < n ? key_index(top[k]) : -1);
+        if (k < K) store_slot<S>(out, (size_t)k * hw + p, k < n ? bucket + pos[k] : nullptr);
     out.count[p] = (uint8_t)n;
 }
 
-// Depths above 64: rank by repeated maximum scans over the bucket (O(arrivals * K), no lists).
+// Depths above 64: rank by repeated maximum scans over the records (O(arrivals * K), no lists).
 template <typename S>
-__global__ void k_build_select_scan(afr_samples s, afr_deep_buffer out, const int32_t *off,
-                                    const unsigned long long *bucket) {
+__global__ void k_build_select_scan(afr_deep_buffer out, const int32_t *off, const Record *bucket) {
     const int hw = out.width * out.height;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= hw) return;
     const int K = out.k;
     const int b0 = off[p], b1 = off[p + 1];
-    const int n = min(b1 - b0, K);
+    int nvalid = 0;
+    for (int e = b0; e < b1; ++e) nvalid += bucket[e].key != 0ull;
+    const int n = min(nvalid, K);
     unsigned long long prev = ~0ull;
     for (int k = 0; k < K; ++k) {
         unsigned long long best = 0ull;
+        int be = -1;
         if (k < n) {
             for (int e = b0; e < b1; ++e) {
-                const unsigned long long c = bucket[e];
-                best = (c < prev && c > best) ? c : best;
+                const unsigned long long c = bucket[e].key;
+                const bool take = c < prev && c > best;
+                best = take ? c : best;
+                be = take ? e : be;
             }
             prev = best;
         }
-        store_slot<S>(s, out, (size_t)k * hw + p, k < n ? key_index(best) : -1);
+        store_slot<S>(out, (size_t)k * hw + p, k < n ? bucket + be : nullptr);
     }
     out.count[p] = (uint8_t)n;
 }
 
 template <typename S>
-hipError_t launch_select(const afr_samples &s, const afr_deep_buffer &out, const BuildWs &ws,
-                         hipStream_t st) {
+hipError_t launch_select(const afr_deep_buffer &out, const BuildWs &ws, hipStream_t st) {
+    const Record *bucket = static_cast<const Record *>(ws.bucket);
     const int hw = out.width * out.height;
     const int threads = 256, blocks = (hw + threads - 1) / threads;
     if (out.k <= 4)
-        k_build_select<S, 4><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select<S, 4><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     else if (out.k <= 8)
-        k_build_select<S, 8><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select<S, 8><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     else if (out.k <= 16)
-        k_build_select<S, 16><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select<S, 16><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     else if (out.k <= 32)
-        k_build_select<S, 32><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select<S, 32><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     else if (out.k <= 64)
-        k_build_select<S, 64><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select<S, 64><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     else
-        k_build_select_scan<S><<<blocks, threads, 0, st>>>(s, out, ws.off, ws.bucket);
+        k_build_select_scan<S><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
     return hipGetLastError();
 }
 
@@ -260,8 +301,9 @@ hipError_t launch_select(const afr_samples &s, const afr_deep_buffer &out, const
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
     const size_t hw = (size_t)w * h;
     const size_t nb = (hw + kScanBlock - 1) / kScanBlock;
-    return align_up(hw * 4) + align_up((hw + 1) * 4) + align_up((nb + 1) * 4) +
-           align_up((size_t)(n > 0 ? n : 1) * 8) + align_up(8);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    return align_up(hw * 4) + align_up((hw + 1) * 4) + align_up((nb + 1) * 4) + align_up(nn * 4) +
+           align_up(nn * sizeof(Record)) + align_up(8);
 }
 
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
@@ -273,10 +315,13 @@ BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     p += align_up(hw * 4);
     o.off = reinterpret_cast<int32_t *>(p);
     p += align_up((hw + 1) * 4);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
     o.bsum = reinterpret_cast<int32_t *>(p);
     p += align_up((nb + 1) * 4);
-    o.bucket = reinterpret_cast<unsigned long long *>(p);
-    p += align_up((size_t)(n > 0 ? n : 1) * 8);
+    o.rank = reinterpret_cast<int32_t *>(p);
+    p += align_up(nn * 4);
+    o.bucket = p;
+    p += align_up(nn * sizeof(Record));
     o.dropped_internal = reinterpret_cast<unsigned long long *>(p);
     return o;
 }
@@ -288,15 +333,17 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     const int nb = (hw + kScanBlock - 1) / kScanBlock;
     const int sblocks = (int)std::min<int64_t>((s.n + 255) / 256, 8192);
     k_build_clear<<<std::max(1, std::min((hw + 255) / 256, 4096)), 256, 0, st>>>(ws.cnt, hw, dropped);
-    if (s.n > 0) k_build_count<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.cnt, dropped);
+    if (s.n > 0) k_build_count<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.cnt, ws.rank, dropped);
     k_scan_blocks<<<nb, kScanThreads, 0, st>>>(ws.cnt, hw, ws.off, ws.bsum);
     k_scan_sums<<<1, kScanThreads, 0, st>>>(ws.bsum, nb);
     k_scan_add<<<nb, kScanThreads, 0, st>>>(ws.off, hw, ws.bsum, nb);
-    if (s.n > 0) k_build_scatter<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.off, ws.cnt, ws.bucket);
+    Record *bucket = static_cast<Record *>(ws.bucket);
+    if (s.n > 0)
+        k_build_scatter<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.off, ws.rank, bucket, dropped);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return out.precision == AFR_FP16 ? launch_select<__half>(s, out, ws, st)
-                                     : launch_select<float>(s, out, ws, st);
+    return out.precision == AFR_FP16 ? launch_select<__half>(out, ws, st)
+                                     : launch_select<float>(out, ws, st);
 }
 
 }  // namespace afr

@@ -90,7 +90,8 @@ struct BuildWs {
     int32_t *cnt;       // [HW]       arrivals per pixel
     int32_t *off;       // [HW + 1]   bucket offsets (exclusive scan of cnt)
     int32_t *bsum;      // [nblk + 1] scan block sums
-    unsigned long long *bucket;  // [n] order key of (time, stream index) per valid sample
+    int32_t *rank;      // [n]        arrival rank of each sample in its home pixel, -1 if dropped
+    void *bucket;       // [n]        32-byte records grouped by home pixel
     unsigned long long *dropped_internal;
 };
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h);
@@ -103,8 +104,10 @@ hipError_t launch_estimate(const afr_deep_buffer &buf, const afr_params &p, cons
 
 hipError_t launch_reconstruct_plain(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                                     const afr_params &p, float *rgb, float *aux, hipStream_t st);
+// tiles_per_wave: launch shape of the tiled gather (1, 2 or 4); it does not change the result.
 hipError_t launch_reconstruct_tiled(const afr_deep_buffer &buf, const afr_tile_stats &stats,
-                                    const afr_params &p, float *rgb, float *aux, hipStream_t st);
+                                    const afr_params &p, int tiles_per_wave, float *rgb, float *aux,
+                                    hipStream_t st);
 
 size_t backward_ws_bytes(int32_t w, int32_t h);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,

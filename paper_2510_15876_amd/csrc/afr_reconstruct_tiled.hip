@@ -111,7 +111,8 @@ __device__ inline int xcd_remap(int b, int nblocks) {
 }
 
 // One wave per TPW horizontally adjacent tiles; LPT = 64 / TPW lanes per tile, each lane owning
-// ROWS = 8 * 8 / LPT output rows of one tile column.
+// ROWS = 8 * 8 / LPT output rows of one tile column. TPW only changes how work is spread over lanes;
+// every pixel sums the same terms in the same order, so the output is identical for every TPW.
 template <typename S, int R, int TPW>
 __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, TiledParams p,
                                                             TileGeom tg,
@@ -140,41 +141,67 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, Tiled
     const int T = ty * tg.tiles_x + min(tcol, tg.tiles_x - 1);
     const int qx_org = tcol * kB - R, qy_org = ty * kB - R;
 
-    // This lane's tile constants (log2 units) and the Gaussian recurrence factors.
+    // This lane's tile constants (log2 units) and the Gaussian recurrence factors
+    // g[m] = exp2(-(2(m - R) + 1) c): X(m+1) = X(m) * rho * g[m], starting from the smallest X(-R).
     const float sx2 = stats[AFR_STAT_SX2 * tg.nt + T], sy2 = stats[AFR_STAT_SY2 * tg.nt + T];
     const float kt2 = stats[AFR_STAT_KT2 * tg.nt + T];
     const float cx2 = kLog2e * (0.5f / sx2), cy2 = kLog2e * (0.5f / sy2);
     const float ct2 = kLog2e * (0.5f * kt2);
-    float gxm[R > 0 ? R : 1], gym[R > 0 ? R : 1];
+    float gxm[NM], gym[NM];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        gxm[m] = exp2f(-(float)(2 * m + 1) * cx2);
-        gym[m] = exp2f(-(float)(2 * m + 1) * cy2);
+    for (int m = 0; m < 2 * R; ++m) {
+        gxm[m] = exp2f(-(float)(2 * (m - R) + 1) * cx2);
+        gym[m] = exp2f(-(float)(2 * (m - R) + 1) * cy2);
     }
 
-    // Pre-pass: the tile's reference age (newest sample of its source region) and the deepest slot.
+    // Items: this lane's source pixels of its tile region; address and depth are loop invariant.
+    int iq[ITEMS], icnt[ITEMS];
     float amin = INFINITY;
     int kmax = 0;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const int pix = sub + it * LPT;
         const int qx = qx_org + pix % RW, qy = qy_org + pix / RW;
+        iq[it] = 0;
+        icnt[it] = 0;
         if (pix < NP && qx >= 0 && qx < W && qy >= 0 && qy < H) {
-            const size_t q = (size_t)qy * W + qx;
-            const int n = v.count[q];
-            kmax = max(kmax, n);
-            if (n > 0) amin = fminf(amin, Codec<S>::age(v.ta[q], p.t_now, p.dt_ref));
+            iq[it] = qy * W + qx;
+            icnt[it] = v.count[iq[it]];
         }
+    }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        kmax = max(kmax, icnt[it]);
+        // slot 0 is each pixel's newest sample: the region's smallest age is among them
+        if (icnt[it] > 0) amin = fminf(amin, Codec<S>::age(v.ta[iq[it]], p.t_now, p.dt_ref));
     }
     kmax = wave_max_int(kmax);
     amin = group_min<LPT>(amin);
     if (amin == INFINITY) amin = 0.0f;  // empty region: any shift works
 
-    float acc[ROWS][4];
+    // Two-level sum: each slot plane's <= (2R+1)^2 terms go into a partial, and the partials of
+    // the K planes are added with Kahan compensation.
+    float acc[ROWS][4], cmp[ROWS][4];
 #pragma unroll
     for (int u = 0; u < ROWS; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[u][c] = 0.0f;
+        for (int c = 0; c < 4; ++c) acc[u][c] = cmp[u][c] = 0.0f;
+
+    // Raw slot data of one plane, prefetched one plane ahead.
+    S rox[ITEMS], roy[ITEMS], rta[ITEMS], rr[ITEMS], rg[ITEMS], rb[ITEMS];
+    auto load_plane = [&](int k) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const size_t s = (size_t)min(k, v.k - 1) * hw + iq[it];
+            rox[it] = v.ox[s];
+            roy[it] = v.oy[s];
+            rta[it] = v.ta[s];
+            rr[it] = v.r[s];
+            rg[it] = v.g[s];
+            rb[it] = v.b[s];
+        }
+    };
+    if (kmax > 0) load_plane(0);
 
     float4 *tP = sP + my_t * PS;
     float *tX = sX + my_t * NM * PS;
@@ -185,34 +212,27 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, Tiled
         for (int it = 0; it < ITEMS; ++it) {
             const int pix = sub + it * LPT;
             if (pix < NP) {
-                const int qx = qx_org + pix % RW, qy = qy_org + pix / RW;
                 float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
                 float X[NM], Y[NM];
 #pragma unroll
                 for (int m = 0; m < NM; ++m) X[m] = Y[m] = 0.0f;
-                if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-                    const size_t q = (size_t)qy * W + qx;
-                    if (k < (int)v.count[q]) {
-                        const size_t s = (size_t)k * hw + q;
-                        const float dx = Codec<S>::dec(v.ox[s]) - 0.5f;
-                        const float dy = Codec<S>::dec(v.oy[s]) - 0.5f;
-                        const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
-                        const float tm = exp2f(-((a - amin) * (a + amin)) * ct2);
-                        P = make_float4(tm, tm * Codec<S>::dec(v.r[s]), tm * Codec<S>::dec(v.g[s]),
-                                        tm * Codec<S>::dec(v.b[s]));
-                        // X[R + m] = exp2(-(m + dx)^2 cx2), m = -R..R, by the Gaussian recurrence
-                        X[R] = exp2f(-dx * dx * cx2);
-                        Y[R] = exp2f(-dy * dy * cy2);
-                        if (R > 0) {
-                            const float rxp = exp2f(-2.0f * dx * cx2), rxm = exp2f(2.0f * dx * cx2);
-                            const float ryp = exp2f(-2.0f * dy * cy2), rym = exp2f(2.0f * dy * cy2);
+                if (k < icnt[it]) {
+                    const float dx = Codec<S>::dec(rox[it]) - 0.5f;
+                    const float dy = Codec<S>::dec(roy[it]) - 0.5f;
+                    const float a = Codec<S>::age(rta[it], p.t_now, p.dt_ref);
+                    const float tm = exp2f(-((a - amin) * (a + amin)) * ct2);
+                    P = make_float4(tm, tm * Codec<S>::dec(rr[it]), tm * Codec<S>::dec(rg[it]),
+                                    tm * Codec<S>::dec(rb[it]));
+                    // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
+                    const float ex = dx - (float)R, ey = dy - (float)R;
+                    X[0] = exp2f(-ex * ex * cx2);
+                    Y[0] = exp2f(-ey * ey * cy2);
+                    if (R > 0) {
+                        const float rhox = exp2f(-2.0f * dx * cx2), rhoy = exp2f(-2.0f * dy * cy2);
 #pragma unroll
-                            for (int m = 0; m < R; ++m) {
-                                X[R + m + 1] = X[R + m] * rxp * gxm[m];
-                                X[R - m - 1] = X[R - m] * rxm * gxm[m];
-                                Y[R + m + 1] = Y[R + m] * ryp * gym[m];
-                                Y[R - m - 1] = Y[R - m] * rym * gym[m];
-                            }
+                        for (int m = 0; m < 2 * R; ++m) {
+                            X[m + 1] = X[m] * rhox * gxm[m];
+                            Y[m + 1] = Y[m] * rhoy * gym[m];
                         }
                     }
                 }
@@ -224,9 +244,15 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, Tiled
                 }
             }
         }
+        if (k + 1 < kmax) load_plane(k + 1);  // in flight while plane k is accumulated
         __syncthreads();
         // Lane owns rows my_h*ROWS + u of column my_c. Source row (region coordinates)
         // my_h*ROWS + vv, source column my_c + w; offsets m = w - R, n = vv - u - R.
+        float part[ROWS][4];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) part[u][c] = 0.0f;
 #pragma unroll
         for (int vv = 0; vv < ROWS + 2 * R; ++vv) {
 #pragma unroll
@@ -239,14 +265,23 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, Tiled
                     const int nn = vv - u;  // n + R
                     if (nn >= 0 && nn <= 2 * R) {
                         const float wgt = x * tY[nn * PS + pix];
-                        acc[u][0] += wgt * P.x;
-                        acc[u][1] += wgt * P.y;
-                        acc[u][2] += wgt * P.z;
-                        acc[u][3] += wgt * P.w;
+                        part[u][0] += wgt * P.x;
+                        part[u][1] += wgt * P.y;
+                        part[u][2] += wgt * P.z;
+                        part[u][3] += wgt * P.w;
                     }
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float y = part[u][c] - cmp[u][c];
+                const float t = acc[u][c] + y;
+                cmp[u][c] = (t - acc[u][c]) - y;
+                acc[u][c] = t;
+            }
         __syncthreads();
     }
 
@@ -275,11 +310,9 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, Tiled
     }
 }
 
-template <typename S, int R>
-hipError_t launch_r(const afr_deep_buffer &buf, const afr_tile_stats &stats, const TiledParams &p,
-                    float *rgb, float *aux, hipStream_t st) {
-    // Four tiles per wave while the LDS footprint stays small; two at R = 4.
-    constexpr int TPW = R <= 3 ? 4 : 2;
+template <typename S, int R, int TPW>
+hipError_t launch_rt(const afr_deep_buffer &buf, const afr_tile_stats &stats, const TiledParams &p,
+                     float *rgb, float *aux, hipStream_t st) {
     const TileGeom tg = geom_of(stats);
     const int gx = (tg.tiles_x + TPW - 1) / TPW;
     const int nblocks = gx * tg.tiles_y;
@@ -288,28 +321,38 @@ hipError_t launch_r(const afr_deep_buffer &buf, const afr_tile_stats &stats, con
     return hipGetLastError();
 }
 
+template <typename S, int R>
+hipError_t launch_r(const afr_deep_buffer &buf, const afr_tile_stats &stats, const TiledParams &p,
+                    int tpw, float *rgb, float *aux, hipStream_t st) {
+    // Four tiles per wave would exceed the static LDS budget at R = 4.
+    if (tpw >= 4 && R <= 3) return launch_rt<S, R, (R <= 3 ? 4 : 2)>(buf, stats, p, rgb, aux, st);
+    if (tpw >= 2) return launch_rt<S, R, 2>(buf, stats, p, rgb, aux, st);
+    return launch_rt<S, R, 1>(buf, stats, p, rgb, aux, st);
+}
+
 template <typename S>
 hipError_t launch_s(const afr_deep_buffer &buf, const afr_tile_stats &stats, const TiledParams &p,
-                    int R, float *rgb, float *aux, hipStream_t st) {
+                    int R, int tpw, float *rgb, float *aux, hipStream_t st) {
     switch (R) {
-        case 0: return launch_r<S, 0>(buf, stats, p, rgb, aux, st);
-        case 1: return launch_r<S, 1>(buf, stats, p, rgb, aux, st);
-        case 2: return launch_r<S, 2>(buf, stats, p, rgb, aux, st);
-        case 3: return launch_r<S, 3>(buf, stats, p, rgb, aux, st);
-        default: return launch_r<S, 4>(buf, stats, p, rgb, aux, st);
+        case 0: return launch_r<S, 0>(buf, stats, p, tpw, rgb, aux, st);
+        case 1: return launch_r<S, 1>(buf, stats, p, tpw, rgb, aux, st);
+        case 2: return launch_r<S, 2>(buf, stats, p, tpw, rgb, aux, st);
+        case 3: return launch_r<S, 3>(buf, stats, p, tpw, rgb, aux, st);
+        default: return launch_r<S, 4>(buf, stats, p, tpw, rgb, aux, st);
     }
 }
 
 }  // namespace
 
 hipError_t launch_reconstruct_tiled(const afr_deep_buffer &buf, const afr_tile_stats &stats,
-                                    const afr_params &prm, float *rgb, float *aux,
-                                    hipStream_t st) {
+                                    const afr_params &prm, int tiles_per_wave, float *rgb,
+                                    float *aux, hipStream_t st) {
     // The tiled form is specialised for 8 px statistics tiles; other tile sizes take the direct form.
     if (stats.tile != kB) return launch_reconstruct_plain(buf, stats, prm, rgb, aux, st);
     const TiledParams p{prm.t_now, prm.t_now - buf.t_ref};
-    if (buf.precision == AFR_FP16) return launch_s<__half>(buf, stats, p, prm.radius, rgb, aux, st);
-    return launch_s<float>(buf, stats, p, prm.radius, rgb, aux, st);
+    if (buf.precision == AFR_FP16)
+        return launch_s<__half>(buf, stats, p, prm.radius, tiles_per_wave, rgb, aux, st);
+    return launch_s<float>(buf, stats, p, prm.radius, tiles_per_wave, rgb, aux, st);
 }
 
 }  // namespace afr
