@@ -187,6 +187,14 @@ afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_sta
                                   const afr_params *params, int32_t tiles_per_wave, float *rgb,
                                   float *aux, hipStream_t stream);
 
+/* Launch-shape tuner for afr_reconstruct: times every supported tiles_per_wave on these inputs
+ * (writes rgb; blocking: synchronises the stream), records the fastest for the buffer class
+ * (width, height, K, precision, radius) in a process-wide, thread-safe table that afr_reconstruct
+ * and afr_reconstruct_launch(..., 0, ...) consult, and reports it. */
+afr_status afr_reconstruct_tune(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                const afr_params *params, float *rgb, int32_t *best_tiles_per_wave,
+                                float *best_ms, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Adjoint of afr_reconstruct with the tile statistics held fixed (they are inputs of the gather,
  * as the paper's tile information is, Sec. 4.2). With pi_s(p) = exp(E_s - E_max)/W':
@@ -206,6 +214,52 @@ afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_s
                                     const afr_params *params, const float *rgb, const float *aux,
                                     const float *grad_rgb, float *grad_slot, float *grad_params,
                                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched reconstruction: many independent estimate + gather pipelines of uneven size in one
+ * persistent launch. Work items are (item, group of tiles_per_wave tiles); each work item
+ * estimates its own tiles' statistics and then gathers them, so items never wait on each other.
+ * Workgroups take items from a counter in the workspace (reset by a small kernel in the same
+ * submission), larger items first. Outputs are bit-identical to afr_estimate_gradients followed by
+ * afr_reconstruct on each item, for every tiles_per_wave.
+ *
+ * Restrictions: every item uses 8 px statistics tiles, the same radius and the same precision;
+ * other batches return AFR_E_UNSUPPORTED. Items must not share output memory.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct afr_batch_item {
+    afr_deep_buffer buf;   /* a built deep buffer                                               */
+    afr_tile_stats stats;  /* receives the item's statistics                                    */
+    afr_params params;     /* per item (t_now, sigma, tau, ...); radius and tile shared         */
+    float *rgb;            /* [3][H][W] output                                                  */
+    float *aux;            /* [2][H][W] output or NULL                                          */
+} afr_batch_item;
+
+typedef struct afr_batch afr_batch; /* opaque host-side plan */
+
+/* Device workspace for a batch of n items (item table, work offsets, counter). */
+size_t afr_batch_workspace_bytes(int32_t n_items);
+
+/* Validates the items, orders them by work, uploads the item table to ws (a blocking host-to-device
+ * copy) and returns a host-side plan. Not capturable; call once per batch layout. tiles_per_wave:
+ * 1, 2 or 4, or 0 for the library default. The items' device memory must stay valid while the plan
+ * is used; ws must not be shared with another plan. */
+afr_status afr_batch_create(const afr_batch_item *items, int32_t n_items, int32_t tiles_per_wave,
+                            void *ws, size_t ws_bytes, afr_batch **plan);
+
+/* Enqueues the whole batch (counter reset + persistent kernel) on the stream. Performs no host
+ * synchronisation, allocation, memset or copy, so it can be captured into a HIP graph and replayed;
+ * replays of one plan must not overlap. */
+afr_status afr_batch_run(const afr_batch *plan, hipStream_t stream);
+
+/* Times every supported tiles_per_wave on the plan (blocking: synchronises the stream), keeps the
+ * fastest in the plan, and reports it. The outputs are overwritten by the timing runs. */
+afr_status afr_batch_tune(afr_batch *plan, hipStream_t stream, int32_t *best_tiles_per_wave,
+                          float *best_ms);
+
+/* Current launch shape of a plan. */
+int32_t afr_batch_tiles_per_wave(const afr_batch *plan);
+
+void afr_batch_destroy(afr_batch *plan);
 
 #ifdef __cplusplus
 }

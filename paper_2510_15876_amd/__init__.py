@@ -21,6 +21,7 @@ __all__ = [
     "AfrError", "Params", "DeepBuffer", "STAT_NAMES", "NSTAT", "STAT", "library", "lib_path",
     "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
+    "reconstruct_tune", "Batch",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +66,11 @@ class _Params(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("t_now", ctypes.c_float)]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("buf", _DeepBuffer), ("stats", _TileStats), ("params", _Params),
+                ("rgb", ctypes.c_void_p), ("aux", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -97,6 +103,22 @@ def library():
         f = getattr(lib, name)
         f.restype = st
         f.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp, vp, vp]
+    lib.afr_reconstruct_tune.restype = st
+    lib.afr_reconstruct_tune.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp,
+                                         P(ctypes.c_int32), P(ctypes.c_float), vp]
+    lib.afr_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_batch_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.afr_batch_create.restype = st
+    lib.afr_batch_create.argtypes = [P(_BatchItem), ctypes.c_int32, ctypes.c_int32, vp,
+                                     ctypes.c_size_t, P(vp)]
+    lib.afr_batch_run.restype = st
+    lib.afr_batch_run.argtypes = [vp, vp]
+    lib.afr_batch_tune.restype = st
+    lib.afr_batch_tune.argtypes = [vp, vp, P(ctypes.c_int32), P(ctypes.c_float)]
+    lib.afr_batch_tiles_per_wave.restype = ctypes.c_int32
+    lib.afr_batch_tiles_per_wave.argtypes = [vp]
+    lib.afr_batch_destroy.restype = None
+    lib.afr_batch_destroy.argtypes = [vp]
     lib.afr_reconstruct_launch.restype = st
     lib.afr_reconstruct_launch.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), ctypes.c_int32,
                                            vp, vp, vp]
@@ -306,6 +328,78 @@ def reconstruct_launch(buf: DeepBuffer, stats: torch.Tensor, params: Params, til
                                       int(tiles_per_wave), _ptr(rgb), _ptr(aux), _stream(stream)),
            "afr_reconstruct_launch")
     return rgb, aux
+
+
+def reconstruct_tune(buf: DeepBuffer, stats: torch.Tensor, params: Params, stream=None):
+    """Time every launch shape of the tiled gather on these inputs (blocking), record the fastest
+    for this buffer class, and return ``(tiles_per_wave, ms)``."""
+    lib = library()
+    rgb = torch.empty((3, buf.height, buf.width), dtype=torch.float32, device=buf.planes.device)
+    best, ms = ctypes.c_int32(0), ctypes.c_float(0.0)
+    bc, pc, sc = buf._c(), params._c(), _stats_c(stats, params.tile)
+    _check(lib.afr_reconstruct_tune(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc), _ptr(rgb),
+                                    ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+           "afr_reconstruct_tune")
+    return int(best.value), float(ms.value)
+
+
+class Batch:
+    """Many independent estimate + gather pipelines in one persistent launch (``afr_batch_*``).
+
+    ``items`` is a list of ``(DeepBuffer, Params)``; every item must use 8 px tiles, one radius and
+    one storage precision. Outputs (``rgb``, ``aux``, ``stats`` per item) are allocated here. ``run``
+    enqueues the whole batch on the current stream and can be captured in a CUDA/HIP graph."""
+
+    def __init__(self, items, tiles_per_wave: int = 0, want_aux: bool = True):
+        lib = library()
+        if not items:
+            raise AfrError("empty batch")
+        self.items = list(items)
+        self.rgb, self.aux, self.stats = [], [], []
+        arr = (_BatchItem * len(items))()
+        for i, (buf, p) in enumerate(self.items):
+            dev = buf.planes.device
+            ty, tx = tiles_shape(buf.width, buf.height, p.tile)
+            st = torch.empty((NSTAT, ty, tx), dtype=torch.float32, device=dev)
+            rgb = torch.empty((3, buf.height, buf.width), dtype=torch.float32, device=dev)
+            aux = (torch.empty((2, buf.height, buf.width), dtype=torch.float32, device=dev)
+                   if want_aux else None)
+            self.stats.append(st)
+            self.rgb.append(rgb)
+            self.aux.append(aux)
+            arr[i] = _BatchItem(buf._c(), _stats_c(st, p.tile), p._c(), _ptr(rgb).value,
+                                None if aux is None else _ptr(aux).value)
+        n = len(items)
+        nbytes = lib.afr_batch_workspace_bytes(n)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.items[0][0].planes.device)
+        plan = ctypes.c_void_p()
+        _check(lib.afr_batch_create(arr, n, int(tiles_per_wave), _ptr(self.ws), nbytes,
+                                    ctypes.byref(plan)), "afr_batch_create")
+        self._plan = plan
+
+    def run(self, stream=None):
+        _check(library().afr_batch_run(self._plan, _stream(stream)), "afr_batch_run")
+
+    def tune(self, stream=None):
+        best, ms = ctypes.c_int32(0), ctypes.c_float(0.0)
+        _check(library().afr_batch_tune(self._plan, _stream(stream), ctypes.byref(best),
+                                        ctypes.byref(ms)), "afr_batch_tune")
+        return int(best.value), float(ms.value)
+
+    @property
+    def tiles_per_wave(self) -> int:
+        return int(library().afr_batch_tiles_per_wave(self._plan))
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            library().afr_batch_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def reconstruct_plain(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, aux=None,

@@ -10,44 +10,6 @@ using namespace afr;
 
 afr_status from_hip(hipError_t e) { return e == hipSuccess ? AFR_OK : AFR_E_DEVICE; }
 
-bool finite(float v) { return std::isfinite(v); }
-
-afr_status check_buffer(const afr_deep_buffer *b) {
-    if (!b) return AFR_E_INVALID;
-    if (b->width < 1 || b->height < 1) return AFR_E_RANGE;
-    if (b->k < 1 || b->k > 255) return AFR_E_RANGE;
-    if (b->precision != AFR_FP32 && b->precision != AFR_FP16) return AFR_E_RANGE;
-    // every flat slot index must fit in int32 arithmetic on the device
-    if ((int64_t)b->width * b->height * b->k >= (int64_t(1) << 31)) return AFR_E_RANGE;
-    if (!finite(b->t_ref)) return AFR_E_RANGE;
-    if (!b->ox || !b->oy || !b->tage || !b->r || !b->g || !b->b || !b->count) return AFR_E_INVALID;
-    return AFR_OK;
-}
-
-afr_status check_params(const afr_params *p, const afr_deep_buffer *b) {
-    if (!p) return AFR_E_INVALID;
-    const float vals[] = {p->sigma, p->tau, p->alpha, p->e_min, p->g_floor, p->dt_floor,
-                          p->age_floor, p->t_now};
-    for (float v : vals)
-        if (!finite(v)) return AFR_E_RANGE;
-    if (p->sigma < 0.0f || p->tau < 0.0f || p->alpha < 0.0f || p->g_floor < 0.0f) return AFR_E_RANGE;
-    if (!(p->e_min > 0.0f) || !(p->e_max > 0.0f) || std::isnan(p->e_max)) return AFR_E_RANGE;
-    if (!(p->dt_floor > 0.0f) || !(p->age_floor > 0.0f)) return AFR_E_RANGE;
-    if (p->radius < 0 || p->radius > kMaxRadius) return AFR_E_RANGE;
-    if (p->tile < 1 || p->tile > kMaxTile) return AFR_E_RANGE;
-    if (b && !(p->t_now >= b->t_ref)) return AFR_E_RANGE;
-    return AFR_OK;
-}
-
-afr_status check_stats(const afr_tile_stats *s, const afr_deep_buffer *b, const afr_params *p) {
-    if (!s || !s->data) return AFR_E_INVALID;
-    if (s->tile != p->tile) return AFR_E_INVALID;
-    if (s->tiles_x != (b->width + s->tile - 1) / s->tile ||
-        s->tiles_y != (b->height + s->tile - 1) / s->tile)
-        return AFR_E_INVALID;
-    return AFR_OK;
-}
-
 #define AFR_TRY(expr)                         \
     do {                                      \
         const afr_status _st = (expr);        \
@@ -106,7 +68,53 @@ afr_status afr_reconstruct(const afr_deep_buffer *buf, const afr_tile_stats *sta
     AFR_TRY(check_params(params, buf));
     AFR_TRY(check_stats(stats, buf, params));
     if (!rgb) return AFR_E_INVALID;
-    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, 2, rgb, aux, stream));
+    const int tuned = tuned_tiles_per_wave(*buf, params->radius);
+    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, tuned ? tuned : 2, rgb, aux,
+                                             stream));
+}
+
+afr_status afr_reconstruct_tune(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                const afr_params *params, float *rgb, int32_t *best_tiles_per_wave,
+                                float *best_ms, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!rgb) return AFR_E_INVALID;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return AFR_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return AFR_E_DEVICE;
+    }
+    int best = 0;
+    float best_t = 1e30f;
+    afr_status st = AFR_OK;
+    const int shapes[3] = {1, 2, 4};
+    for (int s = 0; s < 3 && st == AFR_OK; ++s) {
+        if (shapes[s] == 4 && params->radius > 3) continue;
+        constexpr int kReps = 5;
+        st = from_hip(launch_reconstruct_tiled(*buf, *stats, *params, shapes[s], rgb, nullptr, stream));
+        if (st == AFR_OK && hipEventRecord(e0, stream) != hipSuccess) st = AFR_E_DEVICE;
+        for (int r = 0; r < kReps && st == AFR_OK; ++r)
+            st = from_hip(launch_reconstruct_tiled(*buf, *stats, *params, shapes[s], rgb, nullptr,
+                                                   stream));
+        float ms = 0.0f;
+        if (st == AFR_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = AFR_E_DEVICE;
+        if (st == AFR_OK && ms / kReps < best_t) {
+            best_t = ms / kReps;
+            best = shapes[s];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != AFR_OK) return st;
+    record_tiles_per_wave(*buf, params->radius, best);
+    if (best_tiles_per_wave) *best_tiles_per_wave = best;
+    if (best_ms) *best_ms = best_t;
+    return AFR_OK;
 }
 
 afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_stats *stats,
@@ -117,7 +125,8 @@ afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_sta
     AFR_TRY(check_stats(stats, buf, params));
     if (!rgb) return AFR_E_INVALID;
     if (tiles_per_wave < 0 || tiles_per_wave > 4) return AFR_E_RANGE;
-    const int tpw = tiles_per_wave == 0 ? 2 : tiles_per_wave;
+    const int tuned = tuned_tiles_per_wave(*buf, params->radius);
+    const int tpw = tiles_per_wave == 0 ? (tuned ? tuned : 2) : tiles_per_wave;
     return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, tpw, rgb, aux, stream));
 }
 

@@ -1,0 +1,317 @@
+// Batched reconstruction in one persistent launch, and the launch-shape tuner.
+//
+// A work item is (batch item, group of TPW statistics tiles in one tile row). The workgroup that
+// takes it first evaluates the statistics of its own tiles (est::estimate_tile, the code of
+// afr_estimate_gradients) and then gathers them (gat::gather_group, the code of afr_reconstruct), so
+// no work item depends on another and nothing spins. The grid is sized to the number of resident
+// workgroups; each workgroup loops taking the next item from a counter until the counter passes
+// the last item, which every wave reaches. A one-thread kernel resets the counter before each run,
+// so a run is two kernel launches and nothing else: capturable and replayable.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "afr_tile_estimate.h"
+#include "afr_tile_gather.h"
+
+namespace afr {
+namespace {
+
+struct DevItem {
+    const void *ox, *oy, *ta, *r, *g, *b;
+    const uint8_t *count;
+    int32_t width, height, k;
+    float t_ref;
+    TileGeom tg;
+    float *stats, *rgb, *aux;
+    est::EstParams ep;
+    gat::TiledParams tp;
+};
+
+constexpr int kShapes[3] = {1, 2, 4};
+
+template <typename S>
+__device__ inline BufView<S> item_view(const DevItem &d) {
+    BufView<S> v;
+    v.ox = static_cast<const S *>(d.ox);
+    v.oy = static_cast<const S *>(d.oy);
+    v.ta = static_cast<const S *>(d.ta);
+    v.r = static_cast<const S *>(d.r);
+    v.g = static_cast<const S *>(d.g);
+    v.b = static_cast<const S *>(d.b);
+    v.count = d.count;
+    v.width = d.width;
+    v.height = d.height;
+    v.k = d.k;
+    v.t_ref = d.t_ref;
+    return v;
+}
+
+__global__ void k_batch_reset(int *counter) { *counter = 0; }
+
+template <typename S, int R, int TPW>
+__global__ __launch_bounds__(kWave) void k_batch(const DevItem *__restrict__ items, int n,
+                                                const int *__restrict__ first,
+                                                int *__restrict__ counter) {
+    constexpr size_t kEst = sizeof(est::Smem), kGat = sizeof(gat::Smem<R, TPW>);
+    __shared__ __align__(16) unsigned char raw[kEst > kGat ? kEst : kGat];
+    __shared__ float tparam[3 * TPW];
+    __shared__ int s_item;
+    est::Smem &esm = *reinterpret_cast<est::Smem *>(raw);
+    gat::Smem<R, TPW> &gsm = *reinterpret_cast<gat::Smem<R, TPW> *>(raw);
+    const int total = first[n];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int w = s_item;
+        __syncthreads();  // every lane has read s_item before lane 0 may overwrite it
+        if (w >= total) break;
+        int lo = 0, hi = n - 1;  // the item b with first[b] <= w < first[b + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (first[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const DevItem &d = items[lo];
+        const BufView<S> v = item_view<S>(d);
+        const int gx = (d.tg.tiles_x + TPW - 1) / TPW;
+        const int local = w - first[lo];
+        const int tx0 = (local % gx) * TPW, ty = local / gx;
+        for (int t = 0; t < TPW; ++t) {
+            if (tx0 + t < d.tg.tiles_x) {
+                est::estimate_tile<S>(v, d.ep, d.tg, ty * d.tg.tiles_x + tx0 + t, d.stats, esm,
+                                      tparam + 3 * t);
+            } else if (threadIdx.x == 0) {  // lanes of a missing tile write nothing
+                tparam[3 * t] = 1.0f;
+                tparam[3 * t + 1] = 1.0f;
+                tparam[3 * t + 2] = 0.0f;
+            }
+        }
+        __syncthreads();
+        gat::gather_group<S, R, TPW>(v, d.tp, d.tg, tx0, ty, gsm, tparam, d.rgb, d.aux);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+using KernelFn = void (*)(const DevItem *, int, const int *, int *);
+
+template <typename S, int R>
+KernelFn kernel_for(int tpw) {
+    if (tpw == 4 && R <= 3) return k_batch<S, R, (R <= 3 ? 4 : 2)>;
+    if (tpw >= 2) return k_batch<S, R, 2>;
+    return k_batch<S, R, 1>;
+}
+
+template <typename S>
+KernelFn kernel_for_r(int R, int tpw) {
+    switch (R) {
+        case 0: return kernel_for<S, 0>(tpw);
+        case 1: return kernel_for<S, 1>(tpw);
+        case 2: return kernel_for<S, 2>(tpw);
+        case 3: return kernel_for<S, 3>(tpw);
+        default: return kernel_for<S, 4>(tpw);
+    }
+}
+
+KernelFn batch_kernel(int precision, int R, int tpw) {
+    return precision == AFR_FP16 ? kernel_for_r<__half>(R, tpw) : kernel_for_r<float>(R, tpw);
+}
+
+int shape_index(int tpw) { return tpw == 1 ? 0 : (tpw == 2 ? 1 : 2); }
+
+bool shape_supported(int tpw, int R) { return tpw == 1 || tpw == 2 || (tpw == 4 && R <= 3); }
+
+size_t table_bytes(int n) { return align_up((size_t)n * sizeof(DevItem)); }
+size_t first_bytes(int n) { return align_up((size_t)(n + 1) * sizeof(int)); }
+
+// ---- single-frame tuner cache: (width, height, k, precision, radius) -> tiles per wave ---------
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+
+}  // namespace
+
+int tuned_tiles_per_wave(const afr_deep_buffer &b, int radius) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(std::make_tuple(b.width, b.height, b.k, b.precision, radius));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+void record_tiles_per_wave(const afr_deep_buffer &b, int radius, int tpw) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[std::make_tuple(b.width, b.height, b.k, b.precision, radius)] = tpw;
+}
+
+}  // namespace afr
+
+struct afr_batch {
+    int n = 0;
+    int precision = 0, radius = 0;
+    int tpw = 2;
+    int total[3] = {0, 0, 0};
+    int grid[3] = {0, 0, 0};
+    afr::DevItem *d_items = nullptr;
+    int *d_first[3] = {nullptr, nullptr, nullptr};
+    int *d_counter = nullptr;
+};
+
+using namespace afr;
+
+extern "C" {
+
+size_t afr_batch_workspace_bytes(int32_t n) {
+    if (n < 1) return 0;
+    return table_bytes(n) + 3 * first_bytes(n) + align_up(sizeof(int));
+}
+
+afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tiles_per_wave,
+                            void *ws, size_t ws_bytes, afr_batch **plan) {
+    if (!items || n < 1 || !ws || !plan) return AFR_E_INVALID;
+    *plan = nullptr;
+    if (ws_bytes < afr_batch_workspace_bytes(n)) return AFR_E_NOMEM;
+    if (tiles_per_wave != 0 && tiles_per_wave != 1 && tiles_per_wave != 2 && tiles_per_wave != 4)
+        return AFR_E_RANGE;
+    const int R = items[0].params.radius, prec = items[0].buf.precision;
+    for (int i = 0; i < n; ++i) {
+        const afr_batch_item &it = items[i];
+        afr_status st = check_buffer(&it.buf);
+        if (st == AFR_OK) st = check_params(&it.params, &it.buf);
+        if (st == AFR_OK) st = check_stats(&it.stats, &it.buf, &it.params);
+        if (st != AFR_OK) return st;
+        if (!it.rgb) return AFR_E_INVALID;
+        if (it.params.tile != 8 || it.params.radius != R || it.buf.precision != prec)
+            return AFR_E_UNSUPPORTED;
+    }
+    const int tpw = tiles_per_wave == 0 ? 2 : tiles_per_wave;
+    if (!shape_supported(tpw, R)) return AFR_E_RANGE;
+
+    // Larger items first: the last items taken are the smallest, which evens the tail.
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double wa = (double)items[a].buf.width * items[a].buf.height * items[a].buf.k;
+        const double wb = (double)items[b].buf.width * items[b].buf.height * items[b].buf.k;
+        return wa > wb;
+    });
+    std::vector<DevItem> table(n);
+    std::vector<int> first[3];
+    for (int s = 0; s < 3; ++s) first[s].assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) {
+        const afr_batch_item &it = items[order[j]];
+        DevItem &d = table[j];
+        d.ox = it.buf.ox;
+        d.oy = it.buf.oy;
+        d.ta = it.buf.tage;
+        d.r = it.buf.r;
+        d.g = it.buf.g;
+        d.b = it.buf.b;
+        d.count = it.buf.count;
+        d.width = it.buf.width;
+        d.height = it.buf.height;
+        d.k = it.buf.k;
+        d.t_ref = it.buf.t_ref;
+        d.tg = geom_of(it.stats);
+        d.stats = it.stats.data;
+        d.rgb = it.rgb;
+        d.aux = it.aux;
+        d.ep = est_params(it.buf, it.params);
+        d.tp = gat::TiledParams{it.params.t_now, it.params.t_now - it.buf.t_ref};
+        for (int s = 0; s < 3; ++s) {
+            const int gx = (d.tg.tiles_x + kShapes[s] - 1) / kShapes[s];
+            const int64_t next = (int64_t)first[s][j] + (int64_t)gx * d.tg.tiles_y;
+            if (next >= (int64_t(1) << 31)) return AFR_E_RANGE;
+            first[s][j + 1] = (int)next;
+        }
+    }
+    char *p = static_cast<char *>(ws);
+    afr_batch *b = new (std::nothrow) afr_batch;
+    if (!b) return AFR_E_NOMEM;
+    b->n = n;
+    b->precision = prec;
+    b->radius = R;
+    b->tpw = tpw;
+    b->d_items = reinterpret_cast<DevItem *>(p);
+    p += table_bytes(n);
+    for (int s = 0; s < 3; ++s) {
+        b->d_first[s] = reinterpret_cast<int *>(p);
+        p += first_bytes(n);
+        b->total[s] = first[s][n];
+    }
+    b->d_counter = reinterpret_cast<int *>(p);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int s = 0; s < 3 && e == hipSuccess; ++s) {
+        if (!shape_supported(kShapes[s], R)) continue;
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])), kWave, 0);
+        b->grid[s] = std::max(1, std::min(b->total[s], std::max(1, per_cu) * cus));
+    }
+    if (e == hipSuccess) e = hipMemcpy(b->d_items, table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
+    for (int s = 0; s < 3 && e == hipSuccess; ++s)
+        e = hipMemcpy(b->d_first[s], first[s].data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete b;
+        return AFR_E_DEVICE;
+    }
+    *plan = b;
+    return AFR_OK;
+}
+
+afr_status afr_batch_run(const afr_batch *b, hipStream_t stream) {
+    if (!b) return AFR_E_INVALID;
+    const int s = shape_index(b->tpw);
+    k_batch_reset<<<1, 1, 0, stream>>>(b->d_counter);
+    KernelFn fn = batch_kernel(b->precision, b->radius, b->tpw);
+    hipLaunchKernelGGL(fn, dim3(b->grid[s]), dim3(kWave), 0, stream, b->d_items, b->n,
+                       b->d_first[s], b->d_counter);
+    return hipGetLastError() == hipSuccess ? AFR_OK : AFR_E_DEVICE;
+}
+
+afr_status afr_batch_tune(afr_batch *b, hipStream_t stream, int32_t *best_tpw, float *best_ms) {
+    if (!b) return AFR_E_INVALID;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return AFR_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return AFR_E_DEVICE;
+    }
+    const int keep = b->tpw;
+    int best = keep;
+    float best_t = 1e30f;
+    afr_status st = AFR_OK;
+    for (int s = 0; s < 3 && st == AFR_OK; ++s) {
+        if (!shape_supported(kShapes[s], b->radius)) continue;
+        b->tpw = kShapes[s];
+        st = afr_batch_run(b, stream);  // warm-up
+        constexpr int kReps = 3;
+        if (st == AFR_OK && hipEventRecord(e0, stream) != hipSuccess) st = AFR_E_DEVICE;
+        for (int r = 0; r < kReps && st == AFR_OK; ++r) st = afr_batch_run(b, stream);
+        float ms = 0.0f;
+        if (st == AFR_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = AFR_E_DEVICE;
+        if (st == AFR_OK && ms / kReps < best_t) {
+            best_t = ms / kReps;
+            best = kShapes[s];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tpw = st == AFR_OK ? best : keep;
+    if (st == AFR_OK) {
+        if (best_tpw) *best_tpw = best;
+        if (best_ms) *best_ms = best_t;
+    }
+    return st;
+}
+
+int32_t afr_batch_tiles_per_wave(const afr_batch *b) { return b ? b->tpw : 0; }
+
+void afr_batch_destroy(afr_batch *b) { delete b; }
+
+}  // extern "C"

@@ -5,6 +5,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -84,6 +85,50 @@ inline TileGeom geom_of(const afr_tile_stats &s) {
 }
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// ---- host-side argument validation shared by the entry points ----------------------------------
+inline bool finite(float v) { return std::isfinite(v); }
+
+
+inline afr_status check_buffer(const afr_deep_buffer *b) {
+    if (!b) return AFR_E_INVALID;
+    if (b->width < 1 || b->height < 1) return AFR_E_RANGE;
+    if (b->k < 1 || b->k > 255) return AFR_E_RANGE;
+    if (b->precision != AFR_FP32 && b->precision != AFR_FP16) return AFR_E_RANGE;
+    // every flat slot index must fit in int32 arithmetic on the device
+    if ((int64_t)b->width * b->height * b->k >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    if (!finite(b->t_ref)) return AFR_E_RANGE;
+    if (!b->ox || !b->oy || !b->tage || !b->r || !b->g || !b->b || !b->count) return AFR_E_INVALID;
+    return AFR_OK;
+}
+
+inline afr_status check_params(const afr_params *p, const afr_deep_buffer *b) {
+    if (!p) return AFR_E_INVALID;
+    const float vals[] = {p->sigma, p->tau, p->alpha, p->e_min, p->g_floor, p->dt_floor,
+                          p->age_floor, p->t_now};
+    for (float v : vals)
+        if (!finite(v)) return AFR_E_RANGE;
+    if (p->sigma < 0.0f || p->tau < 0.0f || p->alpha < 0.0f || p->g_floor < 0.0f) return AFR_E_RANGE;
+    if (!(p->e_min > 0.0f) || !(p->e_max > 0.0f) || std::isnan(p->e_max)) return AFR_E_RANGE;
+    if (!(p->dt_floor > 0.0f) || !(p->age_floor > 0.0f)) return AFR_E_RANGE;
+    if (p->radius < 0 || p->radius > kMaxRadius) return AFR_E_RANGE;
+    if (p->tile < 1 || p->tile > kMaxTile) return AFR_E_RANGE;
+    if (b && !(p->t_now >= b->t_ref)) return AFR_E_RANGE;
+    return AFR_OK;
+}
+
+inline afr_status check_stats(const afr_tile_stats *s, const afr_deep_buffer *b, const afr_params *p) {
+    if (!s || !s->data) return AFR_E_INVALID;
+    if (s->tile != p->tile) return AFR_E_INVALID;
+    if (s->tiles_x != (b->width + s->tile - 1) / s->tile ||
+        s->tiles_y != (b->height + s->tile - 1) / s->tile)
+        return AFR_E_INVALID;
+    return AFR_OK;
+}
+
+// Launch shape chosen by afr_reconstruct_tune for a buffer class (0 when none was recorded).
+int tuned_tiles_per_wave(const afr_deep_buffer &b, int radius);
+void record_tiles_per_wave(const afr_deep_buffer &b, int radius, int tpw);
 
 // ---- launchers (each returns hipGetLastError() of its launches) ---------------------------------
 struct BuildWs {

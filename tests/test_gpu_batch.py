@@ -1,0 +1,123 @@
+"""Batched persistent launch (many uneven reconstructions in one launch, capturable in a graph).
+
+Checks: every item equals afr_estimate_gradients + afr_reconstruct on that item bit for bit (the
+batch runs the same per-tile code), every item matches the FP64 reference to 1e-5 on its FP16
+buffer, the launch shape chosen by the tuner changes no output bit, and a captured graph replays to
+the eager result every time, with eager work and synchronisation between replays.
+"""
+import numpy as np
+import pytest
+
+import afr_scenes as S
+import oracle as O
+from helpers import DEV, afr_mod, gpu_build, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+SIZES = ((64, 64), (96, 80), (128, 128), (200, 120), (37, 53))
+KS = (4, 8, 16)
+
+
+def _items(n=10, seed=7, precision="fp16"):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        w, h = SIZES[int(rng.integers(len(SIZES)))]
+        k = KS[int(rng.integers(len(KS)))]
+        srng = np.random.default_rng(100 + i)
+        scene = S.DiscScene(w, h, srng, 12, 64.0, highlights=bool(i % 2))
+        stream = S.stratified_stream(scene, w, h, k, 64.0, 64.0, srng)
+        out.append((stream, w, h, k))
+    return out
+
+
+def _build_all(items, precision="fp16"):
+    afr = afr_mod()
+    bufs = []
+    for stream, w, h, k in items:
+        buf, _ = gpu_build(stream, w, h, k, precision, 64.0)
+        bufs.append((buf, afr.Params(t_now=64.0 + 0.25 * (k % 3))))
+    return bufs
+
+
+def test_batch_equals_separate_calls_and_reference():
+    torch = torch_mod()
+    afr = afr_mod()
+    items = _items()
+    bufs = _build_all(items)
+    batch = afr.Batch(bufs)
+    batch.run()
+    torch.cuda.synchronize()
+    for i, ((buf, p), (stream, w, h, k)) in enumerate(zip(bufs, items)):
+        print(f"batch item {i}: {w}x{h} K={k}", flush=True)
+        st = afr.estimate_gradients(buf, p)
+        rgb, aux = afr.reconstruct(buf, st, p)
+        assert torch.equal(batch.stats[i], st)
+        assert torch.equal(batch.rgb[i], rgb)
+        assert torch.equal(batch.aux[i], aux)
+        ob, _ = O.build_buffer(stream, w, h, k, "fp16", 64.0)
+        orgb, _, _ = O.forward(ob, O.Params(t_now=p.t_now))
+        assert np.abs(batch.rgb[i].cpu().numpy() - orgb).max() <= 1e-5
+    batch.close()
+
+
+def test_launch_shapes_and_tuner_change_no_bit():
+    torch = torch_mod()
+    afr = afr_mod()
+    bufs = _build_all(_items(n=6, seed=11))
+    ref = None
+    for tpw in (1, 2, 4):
+        batch = afr.Batch(bufs, tiles_per_wave=tpw)
+        batch.run()
+        torch.cuda.synchronize()
+        outs = [r.clone() for r in batch.rgb]
+        if ref is None:
+            ref = outs
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(ref, outs)), f"tiles_per_wave={tpw}"
+        batch.close()
+    batch = afr.Batch(bufs)
+    best, ms = batch.tune()
+    assert best in (1, 2, 4) and ms > 0 and batch.tiles_per_wave == best
+    batch.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ref, batch.rgb))
+    # single-frame tuner: recorded shape, same output
+    buf, p = bufs[0]
+    st = afr.estimate_gradients(buf, p)
+    a, _ = afr.reconstruct(buf, st, p)
+    tpw, _ = afr.reconstruct_tune(buf, st, p)
+    b, _ = afr.reconstruct(buf, st, p)
+    assert tpw in (1, 2, 4) and torch.equal(a, b)
+    batch.close()
+
+
+def test_graph_capture_replays_match_eager():
+    torch = torch_mod()
+    afr = afr_mod()
+    bufs = _build_all(_items(n=8, seed=23))
+    batch = afr.Batch(bufs)
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [r.clone() for r in batch.rgb]
+    eager_stats = [s.clone() for s in batch.stats]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm the capture stream
+        batch.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run()
+    for rep in range(4):
+        for r in batch.rgb:  # eager work between replays
+            r.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(eager, batch.rgb)):
+            assert torch.equal(a, b), f"replay {rep} item {i}"
+        for a, b in zip(eager_stats, batch.stats):
+            assert torch.equal(a, b)
+    batch.close()

@@ -134,12 +134,13 @@ def test_reference_statistics_round_trip_and_constants():
     const = torch.tensor([0.25, 0.5, 0.75], device=DEV)[:, None, None, None] * filled
     stats = afr.estimate_gradients(gbuf, gp)
     u = 2.0 ** -24
-    for fn, bound in ((afr.reconstruct, (25 + 8) * u), (afr.reconstruct_plain, 1e-5)):
+    for fn, tol in ((afr.reconstruct, lambda v: (25 + 8) * u * v),
+                    (afr.reconstruct_plain, lambda v: 1e-5)):
         rgb, _ = fn(gbuf, stats, gp, colours=const.float().contiguous())
         for c, v in enumerate((0.25, 0.5, 0.75)):
             err = float((rgb[c] - v).abs().max())
-            print(f"  constant {v}: max error {err:.3g} (bound {bound * max(v, 1e-30 if bound == 1e-5 else v):.3g})")
-            assert err <= (bound * v if bound != 1e-5 else bound)
+            print(f"  constant {v}: max error {err:.3g} (bound {tol(v):.3g})", flush=True)
+            assert err <= tol(v)
     a, _ = afr.reconstruct(gbuf, stats, gp)
     b, _ = afr.reconstruct_plain(gbuf, stats, gp)
     assert float((a - b).abs().max()) <= 2e-6
