@@ -47,6 +47,7 @@ afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, voi
     if (s->n >= (int64_t(1) << 31)) return AFR_E_RANGE;
     if (s->n > 0 && (!s->x || !s->y || !s->t || !s->r || !s->g || !s->b)) return AFR_E_INVALID;
     if (!ws) return AFR_E_INVALID;
+    if (!build_supported(out->width, out->height)) return AFR_E_UNSUPPORTED;
     if (ws_bytes < build_ws_bytes(s->n, out->width, out->height)) return AFR_E_NOMEM;
     const BuildWs w = build_ws_carve(ws, s->n, out->width, out->height);
     unsigned long long *dropped =

@@ -3,17 +3,21 @@
 // The paper's reconstructor receives samples as one stream (Sec. 4.2, Sec. 5.2) and each pixel keeps
 // a queue of its newest samples (Sec. 4). Replaying queue insertions one sample at a time is serial
 // per pixel; the same final state is the top-K by key (t, stream index) of the samples binned to the
-// pixel, which this file computes with a counting sort:
-//   1. k_build_clear   zero the per-pixel arrival counters and the dropped counter
-//   2. k_build_count   read x, y; samples inside the image take an arrival rank in their home pixel
-//                      (the return value of an integer atomic), others are dropped
-//   3. scan            exclusive prefix sum of the counts -> bucket offsets
-//   4. k_build_scatter read the whole sample and write one 32-byte record (order key, ox, oy, t, r,
-//                      g, b) to bucket[offset + rank]; a sample that fails the remaining validity
-//                      checks writes key 0 and is dropped (no atomics in this pass)
-//   5. k_build_select  per pixel: register top-K over its contiguous records, then store the slots
+// pixel. This file computes it with a two-level partition that keeps random accesses in LDS and L2:
+//   1. k_bin_count    per chunk of the stream: LDS histogram over bins of 64 x 4 px;
+//                     samples outside the image are dropped here
+//   2. scan           exclusive prefix sum of the (bin, chunk) counts, bin-major -> write offsets
+//   3. k_bin_scatter  per chunk: coalesced loads of every field, an LDS counting sort by bin, and
+//                     32-byte records (order key, x, y, t, r, g, b) staged in LDS in bin order, a
+//                     window at a time, so that consecutive lanes store consecutive records of a
+//                     bin's run; invalid time or colour writes key 0
+//   4. k_bin_select   per bin: its records' keys are counting-sorted by pixel into an LDS list
+//                     (in one sweep that holds the keys in registers when the bin fits the list,
+//                     else in passes over groups of rows), each pixel takes a register top-K over
+//                     its keys, and the selected records are stored to the slot planes
 // Every decision is integer or an exact comparison of stored float32 inputs, so the result is
-// bit-exact and independent of launch shape and atomic order (the rank only orders a bucket).
+// bit-exact and independent of launch shape and atomic order (atomics only order records inside a
+// group that is sorted by key afterwards).
 #include "afr_internal.h"
 
 namespace afr {
@@ -22,6 +26,16 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = kScanThreads * kScanItems;
+constexpr int kChunkThreads = 1024;
+constexpr int kChunkPer = 8;
+constexpr int kChunk = kChunkThreads * kChunkPer;  // samples per chunk
+constexpr int kWin = 1024;                         // records staged in LDS per scatter window
+constexpr int kBinW = 64;                          // bin width, px
+constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
+constexpr int kMaxBinPx = 2048;                    // pixels per bin (rows grow from 4 to 32)
+constexpr int kSelThreads = 256;
+constexpr int kSelPer = 20;
+constexpr int kListCap = kSelThreads * kSelPer;    // records sorted in LDS per select pass
 
 struct ValidCtx {
     int32_t w, h;
@@ -29,8 +43,12 @@ struct ValidCtx {
     int32_t fp16;
 };
 
-// Validity: the position decides the home pixel (checked in the count pass); time, colour and the
-// binary16 range are checked in the scatter pass. Together they are the rule of afr.h.
+struct BinGeom {
+    int32_t bw, bh, nbx, nby, nb;
+};
+
+// Validity: the position decides the home pixel (checked when binning); time, colour and the
+// binary16 range are checked when the record is written. Together they are the rule of afr.h.
 __device__ inline bool position_valid(float x, float y, const ValidCtx &c) {
     return isfinite(x) && isfinite(y) && x >= 0.0f && x < (float)c.w && y >= 0.0f && y < (float)c.h;
 }
@@ -51,34 +69,54 @@ __device__ inline int wave_sum_int(int v) {
     return v;
 }
 
-__global__ void k_build_clear(int32_t *cnt, int32_t hw, unsigned long long *dropped) {
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hw; i += stride) cnt[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *dropped = 0ull;
+__device__ inline int bin_of(float x, float y, const BinGeom &g) {
+    return ((int)floorf(y) / g.bh) * g.nbx + (int)floorf(x) / g.bw;
 }
 
-__global__ void k_build_count(afr_samples s, ValidCtx c, int32_t *cnt, int32_t *rank,
-                              unsigned long long *dropped) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) {
-        const float x = s.x[i], y = s.y[i];
-        int rk = -1;
-        if (position_valid(x, y, c)) {
-            const int p = (int)floorf(y) * c.w + (int)floorf(x);
-            rk = atomicAdd(&cnt[p], 1);
-        } else {
-            ++bad;
-        }
-        rank[i] = rk;
+// Order key of a sample: the float time mapped to an unsigned integer with the same order (-0 is
+// folded onto +0 so that equal times tie), in the high word; the stream index in the low word. A
+// larger key is a newer sample; 0 is below every valid key and marks an invalid record.
+__device__ inline unsigned long long order_key(float t, int i) {
+    if (t == 0.0f) t = 0.0f;
+    const unsigned u = __float_as_uint(t);
+    const unsigned k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((unsigned long long)k << 32) | (unsigned)i;
+}
+
+__device__ inline int key_index(unsigned long long key) { return (int)(unsigned)(key & 0xffffffffu); }
+
+__global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, ValidCtx c, BinGeom g,
+                                                             int32_t *ht, int nchunks,
+                                                             unsigned long long *dropped) {
+    __shared__ int hist[kMaxBins];
+    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) hist[b] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    float xs[kChunkPer], ys[kChunkPer];
+#pragma unroll
+    for (int j = 0; j < kChunkPer; ++j) {  // all loads first
+        const int64_t i = min(base + (int64_t)j * kChunkThreads + threadIdx.x, s.n - 1);
+        xs[j] = s.x[i];
+        ys[j] = s.y[i];
     }
-    bad = wave_sum_int(bad);  // every lane reaches this point: no early exit above
+    __syncthreads();
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < kChunkPer; ++j) {
+        if (base + (int64_t)j * kChunkThreads + threadIdx.x >= s.n) continue;
+        if (position_valid(xs[j], ys[j], c)) atomicAdd(&hist[bin_of(xs[j], ys[j], g)], 1);
+        else ++bad;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
+        ht[(size_t)b * nchunks + blockIdx.x] = hist[b];
+    bad = wave_sum_int(bad);
     if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
 }
 
-// Block-wide exclusive scan of one int per thread (blockDim = kScanThreads).
+// Block-wide exclusive scan of one int per thread (blockDim = NT).
+template <int NT>
 __device__ inline int block_exclusive_scan(int v, int &total) {
-    __shared__ int wave_tot[kScanThreads / kWave];
+    __shared__ int wave_tot[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int incl = v;
 #pragma unroll
@@ -91,7 +129,7 @@ __device__ inline int block_exclusive_scan(int v, int &total) {
     int base = 0;
     total = 0;
 #pragma unroll
-    for (int w = 0; w < kScanThreads / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
         if (w < wid) base += wave_tot[w];
         total += wave_tot[w];
     }
@@ -99,22 +137,37 @@ __device__ inline int block_exclusive_scan(int v, int &total) {
     return base + incl - v;
 }
 
-// Per-block exclusive scan of cnt into off; block totals into bsum.
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t *cnt, int32_t hw,
+// Exclusive scan of n ints in LDS into out (may alias), by a block of NT threads; returns the total.
+template <int NT>
+__device__ inline int block_scan_lds(const int *in, int *out, int n) {
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += NT) {
+        const int q = c0 + threadIdx.x;
+        const int v = q < n ? in[q] : 0;
+        int total;
+        const int ex = block_exclusive_scan<NT>(v, total);
+        if (q < n) out[q] = carry + ex;
+        carry += total;
+    }
+    return carry;
+}
+
+// Per-block exclusive scan of cnt into off (in place allowed); block totals into bsum.
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t *cnt, int64_t len,
                                                              int32_t *off, int32_t *bsum) {
-    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     int v[kScanItems];
     int sum = 0;
 #pragma unroll
     for (int e = 0; e < kScanItems; ++e) {
-        v[e] = (base + e < hw) ? cnt[base + e] : 0;
+        v[e] = (base + e < len) ? cnt[base + e] : 0;
         sum += v[e];
     }
     int total;
-    int run = block_exclusive_scan(sum, total);
+    int run = block_exclusive_scan<kScanThreads>(sum, total);
 #pragma unroll
     for (int e = 0; e < kScanItems; ++e) {
-        if (base + e < hw) off[base + e] = run;
+        if (base + e < len) off[base + e] = run;
         run += v[e];
     }
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -122,67 +175,85 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t *cnt
 
 // Exclusive scan of the block sums in place (one block, chunked), bsum[nb] = grand total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int32_t *bsum, int32_t nb) {
-    int carry = 0;
-    for (int c0 = 0; c0 < nb; c0 += kScanThreads) {
-        const int i = c0 + threadIdx.x;
-        const int v = i < nb ? bsum[i] : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, total);
-        if (i < nb) bsum[i] = carry + ex;
-        carry += total;
-    }
-    if (threadIdx.x == 0) bsum[nb] = carry;
+    const int total = block_scan_lds<kScanThreads>(bsum, bsum, nb);
+    if (threadIdx.x == 0) bsum[nb] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *off, int32_t hw,
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *off, int64_t len,
                                                           const int32_t *bsum, int32_t nb) {
-    const int base = blockIdx.x * kScanBlock;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
     const int add = bsum[blockIdx.x];
     for (int e = threadIdx.x; e < kScanBlock; e += kScanThreads)
-        if (base + e < hw) off[base + e] += add;
-    if (blockIdx.x == 0 && threadIdx.x == 0) off[hw] = bsum[nb];
+        if (base + e < len) off[base + e] += add;
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[len] = bsum[nb];
 }
 
-// Order key of a sample: the float time mapped to an unsigned integer with the same order (-0 is
-// folded onto +0 so that equal times tie), in the high word; the stream index in the low word. A
-// larger key is a newer sample; 0 is below every valid key and marks an empty list entry.
-__device__ inline unsigned long long order_key(float t, int i) {
-    if (t == 0.0f) t = 0.0f;
-    const unsigned u = __float_as_uint(t);
-    const unsigned k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return ((unsigned long long)k << 32) | (unsigned)i;
-}
-
-__device__ inline int key_index(unsigned long long key) { return (int)(unsigned)(key & 0xffffffffu); }
-
-// One bucket record per sample routed to a pixel: order key (0 = invalid) and the stored fields.
 struct alignas(16) Record {
     unsigned long long key;
-    float ox, oy, t, r, g, b;
+    float x, y, t, r, g, b;
 };
 static_assert(sizeof(Record) == 32, "bucket record is 32 bytes");
 
-__global__ void k_build_scatter(afr_samples s, ValidCtx c, const int32_t *off, const int32_t *rank,
-                                Record *bucket, unsigned long long *dropped) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
+// position minus that offset), the staged records [kWin] and their global positions [kWin].
+__global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
+                                                               const int32_t *ot, int nchunks,
+                                                               Record *bucket,
+                                                               unsigned long long *dropped) {
+    extern __shared__ uint4 scat_lds[];  // 16-byte aligned for the staged records
+    int *scat_sm = reinterpret_cast<int *>(scat_lds);
+    int *tab = scat_sm;                                                  // [nb]
+    Record *stage = reinterpret_cast<Record *>(scat_sm + ((g.nb + 3) & ~3));  // [kWin]
+    int *sdst = reinterpret_cast<int *>(stage + kWin);                  // [kWin]
+    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) tab[b] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    Record rec[kChunkPer];
+#pragma unroll
+    for (int j = 0; j < kChunkPer; ++j) {  // coalesced loads of every field
+        const int64_t i = min(base + (int64_t)j * kChunkThreads + threadIdx.x, s.n - 1);
+        rec[j].x = s.x[i];
+        rec[j].y = s.y[i];
+        rec[j].t = s.t[i];
+        rec[j].r = s.r[i];
+        rec[j].g = s.g[i];
+        rec[j].b = s.b[i];
+    }
+    __syncthreads();
+    int bin[kChunkPer], sp[kChunkPer];
     int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) {
-        const int rk = rank[i];
-        if (rk < 0) continue;
-        const float x = s.x[i], y = s.y[i], t = s.t[i], r = s.r[i], g = s.g[i], b = s.b[i];
-        const float fx = floorf(x), fy = floorf(y);
-        const int p = (int)fy * c.w + (int)fx;
-        Record rec;
-        const bool ok = payload_valid(t, r, g, b, c);
-        bad += ok ? 0 : 1;
-        rec.key = ok ? order_key(t, (int)i) : 0ull;
-        rec.ox = x - fx;
-        rec.oy = y - fy;
-        rec.t = t;
-        rec.r = r;
-        rec.g = g;
-        rec.b = b;
-        bucket[off[p] + rk] = rec;
+#pragma unroll
+    for (int j = 0; j < kChunkPer; ++j) {
+        const int64_t i = base + (int64_t)j * kChunkThreads + threadIdx.x;
+        const bool in = i < s.n && position_valid(rec[j].x, rec[j].y, c);
+        const bool ok = in && payload_valid(rec[j].t, rec[j].r, rec[j].g, rec[j].b, c);
+        bad += (in && !ok) ? 1 : 0;
+        rec[j].key = ok ? order_key(rec[j].t, (int)i) : 0ull;
+        bin[j] = in ? bin_of(rec[j].x, rec[j].y, g) : -1;
+        sp[j] = in ? atomicAdd(&tab[bin[j]], 1) : 0;  // rank inside the bin
+    }
+    __syncthreads();
+    const int nvalid = block_scan_lds<kChunkThreads>(tab, tab, g.nb);  // bin offsets, in place
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kChunkPer; ++j)
+        if (bin[j] >= 0) sp[j] += tab[bin[j]];  // position in the chunk's bin-sorted order
+    __syncthreads();
+    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
+        tab[b] = ot[(size_t)b * nchunks + blockIdx.x] - tab[b];
+    __syncthreads();
+    for (int w0 = 0; w0 < nvalid; w0 += kWin) {
+#pragma unroll
+        for (int j = 0; j < kChunkPer; ++j) {
+            const int q = sp[j] - w0;
+            if (bin[j] >= 0 && q >= 0 && q < kWin) {
+                stage[q] = rec[j];
+                sdst[q] = tab[bin[j]] + sp[j];
+            }
+        }
+        __syncthreads();
+        const int nw = min(kWin, nvalid - w0);
+        for (int q = threadIdx.x; q < nw; q += kChunkThreads) bucket[sdst[q]] = stage[q];
+        __syncthreads();
     }
     bad = wave_sum_int(bad);
     if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
@@ -195,8 +266,8 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Re
     S *g = static_cast<S *>(out.g), *b = static_cast<S *>(out.b);
     if (rec) {
         const Record e = *rec;
-        ox[o] = Codec<S>::enc(e.ox);
-        oy[o] = Codec<S>::enc(e.oy);
+        ox[o] = Codec<S>::enc(e.x - floorf(e.x));
+        oy[o] = Codec<S>::enc(e.y - floorf(e.y));
         ta[o] = Codec<S>::enc_time(e.t, out.t_ref);
         r[o] = Codec<S>::enc(e.r);
         g[o] = Codec<S>::enc(e.g);
@@ -208,118 +279,274 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Re
     }
 }
 
+// Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: insertion into a
+// descending register list (one unsigned compare and selects per entry, the same instruction stream
+// in every lane). Larger K: repeated maximum scans. The selected records are then loaded together.
 template <typename S, int KMAX>
-__global__ void k_build_select(afr_deep_buffer out, const int32_t *off, const Record *bucket) {
-    const int hw = out.width * out.height;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= hw) return;
+__device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t hw,
+                                    const Record *recs, const unsigned long long *keys,
+                                    const unsigned short *pos, int l0, int l1) {
     const int K = out.k;
-    const int b0 = off[p], b1 = off[p + 1];
-    unsigned long long top[KMAX];
-    int pos[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        top[k] = 0ull;
-        pos[k] = -1;
-    }
     int nvalid = 0;
-    for (int e = b0; e < b1; ++e) {
-        // insertion into a descending register list: one unsigned compare and selects per entry,
-        // so every lane runs the same instruction stream
-        unsigned long long c = bucket[e].key;
-        int ce = e;
-        nvalid += c != 0ull;
+    if constexpr (KMAX <= 64) {
+        unsigned long long top[KMAX];
+        int tp[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            const unsigned long long a = top[k];
-            const int ae = pos[k];
-            const bool gt = c > a;
-            top[k] = gt ? c : a;
-            pos[k] = gt ? ce : ae;
-            c = gt ? a : c;
-            ce = gt ? ae : ce;
+            top[k] = 0ull;
+            tp[k] = 0;
         }
-    }
-    const int n = min(nvalid, K);
+        for (int l = l0; l < l1; ++l) {
+            unsigned long long c = keys[l];
+            int ce = pos[l];
+            nvalid += c != 0ull;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-        if (k < K) store_slot<S>(out, (size_t)k * hw + p, k < n ? bucket + pos[k] : nullptr);
-    out.count[p] = (uint8_t)n;
+            for (int k = 0; k < KMAX; ++k) {
+                const unsigned long long a = top[k];
+                const int ae = tp[k];
+                const bool gt = c > a;
+                top[k] = gt ? c : a;
+                tp[k] = gt ? ce : ae;
+                c = gt ? a : c;
+                ce = gt ? ae : ce;
+            }
+        }
+        const int n = min(nvalid, K);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K) store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + tp[k] : nullptr);
+        out.count[p] = (uint8_t)n;
+    } else {
+        for (int l = l0; l < l1; ++l) nvalid += keys[l] != 0ull;
+        const int n = min(nvalid, K);
+        unsigned long long prev = ~0ull;
+        for (int k = 0; k < K; ++k) {
+            unsigned long long best = 0ull;
+            int be = 0;
+            if (k < n) {
+                for (int l = l0; l < l1; ++l) {
+                    const unsigned long long c = keys[l];
+                    const bool take = c < prev && c > best;
+                    best = take ? c : best;
+                    be = take ? (int)pos[l] : be;
+                }
+                prev = best;
+            }
+            store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + be : nullptr);
+        }
+        out.count[p] = (uint8_t)n;
+    }
 }
 
-// Depths above 64: rank by repeated maximum scans over the records (O(arrivals * K), no lists).
+// Same selection straight from the bin's records, for passes whose records exceed the LDS list.
 template <typename S>
-__global__ void k_build_select_scan(afr_deep_buffer out, const int32_t *off, const Record *bucket) {
-    const int hw = out.width * out.height;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= hw) return;
+__device__ inline void select_pixel_scan(const afr_deep_buffer &out, size_t p, size_t hw,
+                                         const Record *recs, int nrec, int px, int py) {
     const int K = out.k;
-    const int b0 = off[p], b1 = off[p + 1];
+    auto mine = [&](int e) { return (int)floorf(recs[e].x) == px && (int)floorf(recs[e].y) == py; };
     int nvalid = 0;
-    for (int e = b0; e < b1; ++e) nvalid += bucket[e].key != 0ull;
+    for (int e = 0; e < nrec; ++e) nvalid += mine(e) && recs[e].key != 0ull;
     const int n = min(nvalid, K);
     unsigned long long prev = ~0ull;
     for (int k = 0; k < K; ++k) {
         unsigned long long best = 0ull;
-        int be = -1;
+        int be = 0;
         if (k < n) {
-            for (int e = b0; e < b1; ++e) {
-                const unsigned long long c = bucket[e].key;
-                const bool take = c < prev && c > best;
+            for (int e = 0; e < nrec; ++e) {
+                const unsigned long long c = recs[e].key;
+                const bool take = mine(e) && c < prev && c > best;
                 best = take ? c : best;
                 be = take ? e : be;
             }
             prev = best;
         }
-        store_slot<S>(out, (size_t)k * hw + p, k < n ? bucket + be : nullptr);
+        store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + be : nullptr);
     }
     out.count[p] = (uint8_t)n;
 }
 
+// Key, x and y of a record in one 16-byte load.
+struct KeyXY {
+    unsigned long long key;
+    float x, y;
+};
+__device__ inline KeyXY load_key_xy(const Record *r) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(r);
+    return {(unsigned long long)v.x | ((unsigned long long)v.y << 32), __uint_as_float(v.z),
+            __uint_as_float(v.w)};
+}
+
+// One workgroup per bin. LDS: per-pixel offsets [npx + 1], then the key list [kListCap] (u64)
+// and the records' positions in the bin [kListCap] (u16).
+template <typename S, int KMAX>
+__global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out, BinGeom g,
+                                                            const int32_t *ot, int nchunks,
+                                                            const Record *bucket) {
+    extern __shared__ uint4 sel_lds[];  // 16-byte aligned for the key list
+    int *sel_sm = reinterpret_cast<int *>(sel_lds);
+    const int npx = g.bw * g.bh;
+    int *poff = sel_sm;  // [npx + 1]
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(sel_sm + ((npx + 2) & ~1));
+    unsigned short *pos = reinterpret_cast<unsigned short *>(keys + kListCap);
+    const int b = blockIdx.x;
+    const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
+    const int nrec = s1 - s0;
+    const Record *recs = bucket + s0;
+    const int bx0 = (b % g.nbx) * g.bw, by0 = (b / g.nbx) * g.bh;
+    const int W = out.width, H = out.height;
+    const size_t hw = (size_t)W * H;
+    const int rows = min(g.bh, H - by0);
+    auto local_id = [&](float x, float y) {
+        return ((int)floorf(y) - by0) * g.bw + ((int)floorf(x) - bx0);
+    };
+    for (int q = threadIdx.x; q <= npx; q += kSelThreads) poff[q] = 0;
+    __syncthreads();
+    if (nrec <= kListCap) {
+        // One sweep: each thread keeps its records' keys, pixels and ranks in registers.
+        unsigned long long kk[kSelPer];
+        int id[kSelPer], rk[kSelPer];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            const int e = j * kSelThreads + threadIdx.x;
+            if (e < nrec) {
+                const KeyXY r = load_key_xy(recs + e);
+                kk[j] = r.key;
+                id[j] = local_id(r.x, r.y);
+                rk[j] = atomicAdd(&poff[id[j]], 1);
+            }
+        }
+        __syncthreads();
+        const int total = block_scan_lds<kSelThreads>(poff, poff, npx);
+        if (threadIdx.x == 0) poff[npx] = total;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            const int e = j * kSelThreads + threadIdx.x;
+            if (e < nrec) {
+                const int l = poff[id[j]] + rk[j];
+                keys[l] = kk[j];
+                pos[l] = (unsigned short)e;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < rows * g.bw; q += kSelThreads) {
+            const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+            if (px < W)
+                select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, poff[q],
+                                      poff[q + 1]);
+        }
+        return;
+    }
+    // Larger bins: count per pixel, then passes over groups of whole rows whose records fit the
+    // list. During a pass's fill the offsets of its pixels advance to their ends, so a pixel's
+    // list is [end of the previous pixel, own end). A single row beyond the list (or a bin beyond
+    // u16 positions) takes the direct scan.
+    for (int e = threadIdx.x; e < nrec; e += kSelThreads) {
+        const KeyXY r = load_key_xy(recs + e);
+        atomicAdd(&poff[local_id(r.x, r.y)], 1);
+    }
+    __syncthreads();
+    const int total = block_scan_lds<kSelThreads>(poff, poff, npx);
+    if (threadIdx.x == 0) poff[npx] = total;
+    __syncthreads();
+    for (int r0 = 0; r0 < rows;) {
+        int r1 = r0 + 1;
+        while (r1 < rows && poff[(r1 + 1) * g.bw] - poff[r0 * g.bw] <= kListCap) ++r1;
+        const int q0 = r0 * g.bw, q1 = r1 * g.bw;
+        const int lo = poff[q0], hi = poff[q1];
+        __syncthreads();  // every thread has read the bounds before the fill moves them
+        if (hi - lo <= kListCap && nrec <= 65536) {
+            for (int e = threadIdx.x; e < nrec; e += kSelThreads) {
+                const KeyXY r = load_key_xy(recs + e);
+                const int q = local_id(r.x, r.y);
+                if (q >= q0 && q < q1) {
+                    const int l = atomicAdd(&poff[q], 1) - lo;
+                    keys[l] = r.key;
+                    pos[l] = (unsigned short)e;
+                }
+            }
+            __syncthreads();
+            for (int q = q0 + threadIdx.x; q < q1; q += kSelThreads) {
+                const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+                if (px < W)
+                    select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos,
+                                          q == q0 ? 0 : poff[q - 1] - lo, poff[q] - lo);
+            }
+        } else {
+            for (int q = q0 + threadIdx.x; q < q1; q += kSelThreads) {
+                const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+                if (px < W) select_pixel_scan<S>(out, (size_t)py * W + px, hw, recs, nrec, px, py);
+            }
+        }
+        __syncthreads();  // the list is rewritten by the next pass
+        r0 = r1;
+    }
+}
+
+size_t select_shmem(const BinGeom &g) {
+    return (size_t)((g.bw * g.bh + 2) & ~1) * sizeof(int) +
+           kListCap * (sizeof(unsigned long long) + sizeof(unsigned short));
+}
+
 template <typename S>
-hipError_t launch_select(const afr_deep_buffer &out, const BuildWs &ws, hipStream_t st) {
-    const Record *bucket = static_cast<const Record *>(ws.bucket);
-    const int hw = out.width * out.height;
-    const int threads = 256, blocks = (hw + threads - 1) / threads;
-    if (out.k <= 4)
-        k_build_select<S, 4><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
-    else if (out.k <= 8)
-        k_build_select<S, 8><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
-    else if (out.k <= 16)
-        k_build_select<S, 16><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
-    else if (out.k <= 32)
-        k_build_select<S, 32><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
-    else if (out.k <= 64)
-        k_build_select<S, 64><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
-    else
-        k_build_select_scan<S><<<blocks, threads, 0, st>>>(out, ws.off, bucket);
+hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *ot,
+                         int nchunks, const Record *bucket, hipStream_t st) {
+    const size_t shmem = select_shmem(g);
+    const dim3 grid(g.nb), block(kSelThreads);
+    if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    else if (out.k <= 8) k_bin_select<S, 8><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    else if (out.k <= 16) k_bin_select<S, 16><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    else if (out.k <= 32) k_bin_select<S, 32><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    else if (out.k <= 64) k_bin_select<S, 64><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    else k_bin_select<S, 256><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
     return hipGetLastError();
 }
 
+__global__ void k_zero_dropped(unsigned long long *dropped) { *dropped = 0ull; }
+
+__global__ void k_fill_zero(int32_t *p, int64_t len) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
+}
+
+BinGeom bin_geom(int32_t w, int32_t h) {
+    BinGeom g;
+    g.bw = kBinW;
+    g.nbx = (w + g.bw - 1) / g.bw;
+    g.bh = 4;
+    while ((size_t)g.nbx * ((h + g.bh - 1) / g.bh) > (size_t)kMaxBins && g.bw * g.bh < kMaxBinPx)
+        g.bh *= 2;
+    g.nby = (h + g.bh - 1) / g.bh;
+    g.nb = g.nbx * g.nby;
+    return g;
+}
+
+int64_t n_chunks(int64_t n) { return std::max<int64_t>(1, (n + kChunk - 1) / kChunk); }
+
 }  // namespace
 
+bool build_supported(int32_t w, int32_t h) { return bin_geom(w, h).nb <= kMaxBins; }
+
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
-    const size_t hw = (size_t)w * h;
-    const size_t nb = (hw + kScanBlock - 1) / kScanBlock;
+    const BinGeom g = bin_geom(w, h);
+    const int64_t len = (int64_t)g.nb * n_chunks(n);
+    const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    return align_up(hw * 4) + align_up((hw + 1) * 4) + align_up((nb + 1) * 4) + align_up(nn * 4) +
+    return align_up((size_t)(len + 1) * 4) + align_up((size_t)(nsb + 1) * 4) +
            align_up(nn * sizeof(Record)) + align_up(8);
 }
 
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
-    const size_t hw = (size_t)w * h;
-    const size_t nb = (hw + kScanBlock - 1) / kScanBlock;
+    const BinGeom g = bin_geom(w, h);
+    const int64_t len = (int64_t)g.nb * n_chunks(n);
+    const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
     char *p = static_cast<char *>(ws);
     BuildWs o;
-    o.cnt = reinterpret_cast<int32_t *>(p);
-    p += align_up(hw * 4);
-    o.off = reinterpret_cast<int32_t *>(p);
-    p += align_up((hw + 1) * 4);
-    const size_t nn = (size_t)(n > 0 ? n : 1);
+    o.offsets = reinterpret_cast<int32_t *>(p);
+    p += align_up((size_t)(len + 1) * 4);
     o.bsum = reinterpret_cast<int32_t *>(p);
-    p += align_up((nb + 1) * 4);
-    o.rank = reinterpret_cast<int32_t *>(p);
-    p += align_up(nn * 4);
+    p += align_up((size_t)(nsb + 1) * 4);
     o.bucket = p;
     p += align_up(nn * sizeof(Record));
     o.dropped_internal = reinterpret_cast<unsigned long long *>(p);
@@ -328,22 +555,31 @@ BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
 
 hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const BuildWs &ws,
                         unsigned long long *dropped, hipStream_t st) {
-    const int hw = out.width * out.height;
     const ValidCtx c{out.width, out.height, out.t_ref, out.precision == AFR_FP16 ? 1 : 0};
-    const int nb = (hw + kScanBlock - 1) / kScanBlock;
-    const int sblocks = (int)std::min<int64_t>((s.n + 255) / 256, 8192);
-    k_build_clear<<<std::max(1, std::min((hw + 255) / 256, 4096)), 256, 0, st>>>(ws.cnt, hw, dropped);
-    if (s.n > 0) k_build_count<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.cnt, ws.rank, dropped);
-    k_scan_blocks<<<nb, kScanThreads, 0, st>>>(ws.cnt, hw, ws.off, ws.bsum);
-    k_scan_sums<<<1, kScanThreads, 0, st>>>(ws.bsum, nb);
-    k_scan_add<<<nb, kScanThreads, 0, st>>>(ws.off, hw, ws.bsum, nb);
+    const BinGeom g = bin_geom(out.width, out.height);
+    const int64_t nch = n_chunks(s.n);
+    const int64_t len = (int64_t)g.nb * nch;
+    const int nsb = (int)((len + kScanBlock - 1) / kScanBlock);
     Record *bucket = static_cast<Record *>(ws.bucket);
+    k_zero_dropped<<<1, 1, 0, st>>>(dropped);
     if (s.n > 0)
-        k_build_scatter<<<std::max(1, sblocks), 256, 0, st>>>(s, c, ws.off, ws.rank, bucket, dropped);
+        k_bin_count<<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch, dropped);
+    else  // no samples: every (bin, chunk) count of the single empty chunk is zero
+        k_fill_zero<<<std::max(1, std::min((int)((len + 255) / 256), 1024)), 256, 0, st>>>(ws.offsets,
+                                                                                       len);
+    k_scan_blocks<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.offsets, ws.bsum);
+    k_scan_sums<<<1, kScanThreads, 0, st>>>(ws.bsum, nsb);
+    k_scan_add<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.bsum, nsb);
+    const size_t scat_shmem =
+        (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * (sizeof(Record) + sizeof(int));
+    if (s.n > 0)
+        k_bin_scatter<<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets, (int)nch,
+                                                                   bucket, dropped);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return out.precision == AFR_FP16 ? launch_select<__half>(out, ws, st)
-                                     : launch_select<float>(out, ws, st);
+    return out.precision == AFR_FP16
+               ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, st)
+               : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, st);
 }
 
 }  // namespace afr

@@ -132,13 +132,13 @@ void record_tiles_per_wave(const afr_deep_buffer &b, int radius, int tpw);
 
 // ---- launchers (each returns hipGetLastError() of its launches) ---------------------------------
 struct BuildWs {
-    int32_t *cnt;       // [HW]       arrivals per pixel
-    int32_t *off;       // [HW + 1]   bucket offsets (exclusive scan of cnt)
-    int32_t *bsum;      // [nblk + 1] scan block sums
-    int32_t *rank;      // [n]        arrival rank of each sample in its home pixel, -1 if dropped
-    void *bucket;       // [n]        32-byte records grouped by home pixel
+    int32_t *offsets;   // [bins * chunks + 1] (bin, chunk) counts, then their exclusive scan
+    int32_t *bsum;      // scan block sums
+    void *bucket;       // [n] 32-byte records grouped by bin
     unsigned long long *dropped_internal;
 };
+// Images whose bin table fits the build's LDS histogram (up to ~16.7 M pixels).
+bool build_supported(int32_t w, int32_t h);
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h);
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h);
 hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const BuildWs &ws,

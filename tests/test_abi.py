@@ -51,7 +51,7 @@ def test_status_strings_and_sizes(afr):
     assert lib.afr_version().startswith(b"afr")
     a = lib.afr_build_workspace_bytes(1000, 64, 64, 4)
     b = lib.afr_build_workspace_bytes(2000, 64, 64, 4)
-    assert b - a >= 7680 and a > 64 * 64 * 8
+    assert b - a >= 1000 * 32 - 256 and a >= 1000 * 32  # one 32-byte record per sample
     assert lib.afr_build_workspace_bytes(-1, 64, 64, 4) == 0
     assert lib.afr_backward_workspace_bytes(512, 512) >= 3 * 512 * 512 * 4
     assert lib.afr_backward_workspace_bytes(0, 5) == 0
