@@ -7,13 +7,14 @@ stratified over 64 ms (seeded, synthetic: the paper's BART animations are not av
 One step = the whole forward path on one frame's worth of samples already resident in HBM:
 afr_build_deep_buffer (stream -> per-pixel deep buffer), afr_estimate_gradients (tile statistics),
 afr_reconstruct (adaptive gather). Six independent copies of the inputs rotate between steps so the
-~240 MB a step touches is not served from the 256 MB Infinity Cache.
+~0.5 GB the steps touch is not served from the 256 MB Infinity Cache.
 
 Printed: one JSON line. ``value`` is reconstructed Mpixel/s of whole steps; extra keys give the
-stage times, samples filtered per second, the forward-plus-adjoint time per frame on the 512x512,
-K = 8, FP32 frame sequence, the plain direct gather timed on the same data, the roofline of the
-dominant kernel (measured with HIP events on the launch stream), and the FP64 reference timed on
-the host as the CPU baseline.
+per-kernel stage times (HIP events recorded on the launch stream, the build's four stages through
+afr_build_deep_buffer_staged), samples filtered per second by the forward (estimate + gather), the
+forward-plus-adjoint time per frame on the 512x512, K = 8, FP32 frame sequence, the plain direct
+gather timed on the same data, the roofline of the dominant kernel, a measured device-copy
+bandwidth, and the FP64 reference timed on the host as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -41,15 +42,157 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-fwdbwd", action="store_true", help="skip the forward+adjoint frames")
     ap.add_argument("--frames", type=int, default=32, help="frames in the forward+adjoint leg")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
+                    help="print a text summary of a rocprofv3 --stats kernel table and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs and exit")
     return ap.parse_args()
 
 
-def _stage_events(torch, n):
-    return [[torch.cuda.Event(enable_timing=True) for _ in range(n)] for _ in range(4)]
+def _short(name):
+    """Kernel name without return type, namespaces and parameter list; template arguments kept,
+    without spaces (k_bin_select<__half,16>)."""
+    for tok in ("void ", "afr::", "(anonymous namespace)::"):
+        name = name.replace(tok, "")
+    return name.split("(")[0].replace(" ", "").strip()
+
+
+def stats_summary(csv_path, command):
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["# rocprofv3 kernel statistics", "# command: " + command,
+           "# kernel | calls | avg us | min us | max us | total %"]
+    for r in rows:
+        out.append("%-44s %6d %10.2f %10.2f %10.2f %7.2f" % (
+            _short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def pmc_summary(fetch_csv, write_csv, command, copy_kib=262144):
+    """Per-kernel average FETCH_SIZE and WRITE_SIZE (KiB per dispatch), and the scale of each counter
+    from the largest device copies of the run (the 256 MiB copies of copy_bandwidth)."""
+    import csv
+    import collections
+
+    def per_dispatch(path, counter):
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    f = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = per_dispatch(write_csv, "WRITE_SIZE")
+    copy = [k for k in w if "copyBuffer" in k]
+    wc = sorted(v for k in copy for v in w[k])[-3:]
+    fc = sorted(v for k in copy for v in f[k])[-3:]
+    f_fetch, f_write = copy_kib / float(np.median(fc)), copy_kib / float(np.median(wc))
+    out = ["# HBM traffic per dispatch, 640x480 K=16 FP16 workload (bench.py)",
+           "# fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE"),
+           "# write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace("/fetch ", "/write "),
+           "# scale = %d KiB / counter reading of the 256 MiB device copy (median of the 3 largest)"
+           % copy_kib,
+           "digest=" + csrc_digest(),
+           "scale %.4f %.4f" % (f_fetch, f_write),
+           "# kernel <name> <FETCH_SIZE KiB> <WRITE_SIZE KiB>   (raw averages; bytes = KiB*scale*1024)"]
+    for k in sorted(set(f) & set(w)):
+        name = _short(k)
+        if name.startswith("k_"):
+            out.append("kernel %s %.3f %.3f" % (name, float(np.mean(f[k])), float(np.mean(w[k]))))
+    return "\n".join(out)
+
+
+STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gather")
+
+
+def kernel_of(stage, k, radius, tpw):
+    """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name)."""
+    return {"bin_count": "k_bin_count", "bin_scan": "k_scan_blocks+k_scan_sums+k_scan_add",
+            "bin_scatter": "k_bin_scatter",
+            "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
+                                                       k <= 16 else 32 if k <= 32 else 64),
+            "estimate": "k_estimate<__half>",
+            "gather": "k_reconstruct_tiled<__half,%d,%d>" % (radius, tpw)}[stage]
+SINGLE_KERNEL = ("bin_scatter", "bin_select", "estimate", "gather")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_k16_fp16.txt")
+
+
+def csrc_digest():
+    """Digest of every kernel source; a traffic figure is valid only for the sources it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2510_15876_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed PMC summary: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) scaled by what the same counters read for a device copy of known size.
+    None when there is no summary for it or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals, rows = {}, {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line.startswith("digest="):
+            vals["digest"] = line.split("=", 1)[1]
+        elif line.startswith("scale "):
+            _, f, w = line.split()
+            vals["f_fetch"], vals["f_write"] = float(f), float(w)
+        elif line.startswith("kernel "):
+            _, name, fk, wk = line.split()
+            rows[name] = (float(fk), float(wk))
+    if vals.get("digest") != csrc_digest() or kernel not in rows or "f_fetch" not in vals:
+        return None
+    fk, wk = rows[kernel]
+    return int(round((fk * vals["f_fetch"] + wk * vals["f_write"]) * 1024))
+
+
+def copy_bandwidth(torch, dev, mib=256, reps=5):
+    """Device-to-device copy of ``mib`` MiB: achieved GB/s (read + write) and the per-copy size,
+    the known-size reference for the PMC byte counters."""
+    a = torch.empty(mib << 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2 * a.numel() * 4 / (ms * 1e-3) / 1e9
+
+
+def algorithmic_bytes(stage, n, n_binned, occupied, W, H, K, nt):
+    """Bytes a kernel must move by its own inputs and outputs (FP16 storage: 2 B per field). The
+    build's (bin, chunk) offset table (< 1% of the scatter's bytes) is left out."""
+    e = 2
+    if stage == "bin_scatter":   # every field of every sample; one 32 B record per binned sample
+        return 24 * n + 32 * n_binned
+    if stage == "bin_select":    # every record once; all K slot planes, src and count written
+        return 32 * n_binned + K * W * H * (6 * e + 4) + W * H
+    if stage == "estimate":      # count, colour and age of every occupied slot; 11 stats planes
+        return W * H + occupied * 4 * e + 11 * 4 * nt
+    if stage == "gather":        # every occupied slot once, count, 3-channel float image
+        return W * H + occupied * 6 * e + 12 * W * H
+    return None
 
 
 def main():
     args = _args()
+    if args.stats_summary:
+        print(stats_summary(*args.stats_summary))
+        return
+    if args.pmc_summary:
+        print(pmc_summary(*args.pmc_summary))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU layout "
               "is a design note, not part of this build)", file=sys.stderr)
@@ -76,39 +219,61 @@ def main():
     stats = [torch.empty((afr.NSTAT,) + afr.tiles_shape(W, H, p.tile), device=dev) for _ in range(ROTATE)]
     rgbs = [torch.empty((3, H, W), device=dev) for _ in range(ROTATE)]
     drop = torch.zeros(1, dtype=torch.int64, device=dev)
+    nst = afr.build_stage_count()
 
     def step(r, ev=None, i=0):
         s = streams[r]
-        if ev: ev[0][i].record()
-        afr.build_deep_buffer(*s, W, H, K, "fp16", wl.t_ref, out=bufs[r], dropped=drop)
-        if ev: ev[1][i].record()
+        if ev is None:
+            afr.build_deep_buffer(*s, W, H, K, "fp16", wl.t_ref, out=bufs[r], dropped=drop)
+            afr.estimate_gradients(bufs[r], p, out=stats[r])
+            afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
+            return
+        ev[0][i].record()
+        afr.build_deep_buffer(*s, W, H, K, "fp16", wl.t_ref, out=bufs[r], dropped=drop,
+                              stage_events=[ev[1 + j][i] for j in range(nst)])
         afr.estimate_gradients(bufs[r], p, out=stats[r])
-        if ev: ev[2][i].record()
+        ev[nst + 1][i].record()
         afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
-        if ev: ev[3][i].record()
+        ev[nst + 2][i].record()
 
+    # launch shape of the gather: the tuner's choice for this geometry (output is identical for
+    # every shape)
+    for r in range(ROTATE):
+        step(r)
+    torch.cuda.synchronize()
+    tpw, _ = afr.reconstruct_tune(bufs[0], stats[0], p)
     for i in range(args.warmup):
         step(i % ROTATE)
     torch.cuda.synchronize()
-    ev = _stage_events(torch, args.steps)
-    end = torch.cuda.Event(enable_timing=True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(args.steps)] for _ in range(nst + 3)]
+    for row in ev:  # create every event before the timed region
+        for e in row:
+            e.record()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i % ROTATE, ev, i)
-    end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = ev[0][0].elapsed_time(end)
-    build_ms = np.mean([ev[0][i].elapsed_time(ev[1][i]) for i in range(args.steps)])
-    est_ms = np.mean([ev[1][i].elapsed_time(ev[2][i]) for i in range(args.steps)])
-    rec_ms = np.mean([ev[2][i].elapsed_time(ev[3][i]) for i in range(args.steps)])
+    total_ms = ev[0][0].elapsed_time(ev[nst + 2][args.steps - 1])
     ms_step = total_ms / args.steps
+    stage_ms = {}
+    for j, name in enumerate(STAGES):
+        stage_ms[name] = float(np.mean([ev[j][i].elapsed_time(ev[j + 1][i])
+                                        for i in range(args.steps)]))
+    build_ms = sum(stage_ms[s] for s in STAGES[:4])
 
     occupied = int(bufs[0].count.sum().item())
-    # algorithmic bytes of the gather: every stored slot once (12 B in FP16), the count plane and
-    # the 3-channel float image written once; tile statistics are < 0.1 MB
-    rec_bytes = occupied * 12 + W * H * (1 + 12)
-    rec_gbs = rec_bytes / (rec_ms * 1e-3) / 1e9
+    n = len(wl.stream)
+    xs = wl.stream.arrays()
+    n_binned = int(np.count_nonzero((xs[0] >= 0) & (xs[0] < W) & (xs[1] >= 0) & (xs[1] < H)))
+    nt = int(np.prod(afr.tiles_shape(W, H, p.tile)))
+    dom = max(SINGLE_KERNEL, key=lambda s: stage_ms[s])
+    dom_bytes = algorithmic_bytes(dom, n, n_binned, occupied, W, H, K, nt)
+    dom_gbs = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    dom_kernel = kernel_of(dom, K, args.radius, tpw)
+    traffic = read_traffic(dom_kernel)
+    copy_gbs = copy_bandwidth(torch, dev)
 
     # plain direct gather on the same buffers, for the plain-vs-tiled comparison
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -121,6 +286,7 @@ def main():
     pe[1].record()
     torch.cuda.synchronize()
     plain_ms = pe[0].elapsed_time(pe[1]) / n_plain
+    fwd_ms = stage_ms["estimate"] + stage_ms["gather"]
 
     out = {
         "metric": "reconstructed Mpixel/s (build + estimate + gather per frame)",
@@ -137,15 +303,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "640x480 K=16 FP16-storage, 64 discs + highlights, R=%d, 8px tiles"
                    % args.radius, "width": W, "height": H, "k": K, "radius": args.radius,
-                   "samples": len(wl.stream), "occupied_slots": occupied},
-        "stages_ms": {"build": round(build_ms, 5), "estimate": round(est_ms, 5),
-                      "reconstruct": round(rec_ms, 5)},
-        "forward_mpixel_per_s": round(W * H / ((est_ms + rec_ms) * 1e-3) / 1e6, 3),
-        "samples_filtered_per_s": round(occupied / ((est_ms + rec_ms) * 1e-3), 1),
+                   "samples": n, "occupied_slots": occupied, "gather_tiles_per_wave": tpw},
+        "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "build_ms": round(build_ms, 5),
+        "forward_ms": round(fwd_ms, 5),
+        "forward_mpixel_per_s": round(W * H / (fwd_ms * 1e-3) / 1e6, 3),
+        "samples_filtered_per_s": round(occupied / (fwd_ms * 1e-3), 1),
+        "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
         "plain_reconstruct_ms": round(plain_ms, 5),
-        "roofline": {"bound": "hbm", "kernel": "k_reconstruct_tiled", "achieved": round(rec_gbs, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(rec_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes": rec_bytes},
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": round(dom_gbs, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": dom_bytes,
+                     "ms_per_launch": round(stage_ms[dom], 5)},
+        "copy_gbs_measured": round(copy_gbs, 1),
         "wall_s_timed": round(wall, 4),
     }
 

@@ -140,6 +140,17 @@ size_t afr_build_workspace_bytes(int64_t n, int32_t width, int32_t height, int32
 afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, void *ws,
                                  size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream);
 
+/* The same build with per-stage timing: stage_end[0 .. afr_build_stage_count()-1] are caller-owned
+ * events (created by the caller) that are recorded on `stream` after the bin-count, offset-scan,
+ * record-scatter and per-pixel-select stages, in that order, so that each stage's duration is the
+ * time between consecutive events (the first measured from an event the caller records before the
+ * call). Results are identical to afr_build_deep_buffer. AFR_E_INVALID if stage_end or any of its
+ * events is NULL. */
+int32_t afr_build_stage_count(void);
+afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                        size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream,
+                                        hipEvent_t *stage_end);
+
 /* ---------------------------------------------------------------------------------------------
  * Gradient, density and filter-extent estimation per tile (Sec. 4, 4.1, 5.1).
  *

@@ -97,6 +97,11 @@ def library():
                                               ctypes.c_int32]
     lib.afr_build_deep_buffer.restype = st
     lib.afr_build_deep_buffer.argtypes = [P(_Samples), P(_DeepBuffer), vp, ctypes.c_size_t, vp, vp]
+    lib.afr_build_stage_count.restype = ctypes.c_int32
+    lib.afr_build_stage_count.argtypes = []
+    lib.afr_build_deep_buffer_staged.restype = st
+    lib.afr_build_deep_buffer_staged.argtypes = [P(_Samples), P(_DeepBuffer), vp, ctypes.c_size_t,
+                                                 vp, vp, P(vp)]
     lib.afr_estimate_gradients.restype = st
     lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
     for name in ("afr_reconstruct", "afr_reconstruct_plain"):
@@ -254,9 +259,11 @@ def _workspace(nbytes: int, device, key: str) -> torch.Tensor:
 
 def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precision: str = "fp32",
                       t_ref: Optional[float] = None, out: Optional[DeepBuffer] = None,
-                      stream=None, dropped: Optional[torch.Tensor] = None):
+                      stream=None, dropped: Optional[torch.Tensor] = None, stage_events=None):
     """Build the per-pixel deep buffer from a device sample stream (float32 SoA).
 
+    ``stage_events``: optional list of ``build_stage_count()`` timing-enabled ``torch.cuda.Event``
+    objects, recorded on the stream after the count, scan, scatter and select stages.
     Returns ``(buffer, dropped)`` where ``dropped`` is a device int64 tensor of one element."""
     lib = library()
     xs = [x, y, t, r, g, b]
@@ -277,9 +284,27 @@ def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precisi
     wsb = lib.afr_build_workspace_bytes(n, width, height, k)
     ws = _workspace(wsb, dev, "build")
     bc = out._c()
-    _check(lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(bc), _ptr(ws), wsb,
-                                     _ptr(dropped), _stream(stream)), "afr_build_deep_buffer")
+    if stage_events is None:
+        _check(lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(bc), _ptr(ws), wsb,
+                                         _ptr(dropped), _stream(stream)), "afr_build_deep_buffer")
+        return out, dropped
+    ns = lib.afr_build_stage_count()
+    if len(stage_events) != ns:
+        raise AfrError(f"stage_events needs {ns} events")
+    handles = []
+    for ev in stage_events:
+        if not ev.cuda_event:  # torch creates the event at its first record
+            ev.record()
+        handles.append(ev.cuda_event)
+    arr = (ctypes.c_void_p * ns)(*handles)
+    _check(lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(bc), _ptr(ws), wsb,
+                                            _ptr(dropped), _stream(stream), arr),
+           "afr_build_deep_buffer_staged")
     return out, dropped
+
+
+def build_stage_count() -> int:
+    return int(library().afr_build_stage_count())
 
 
 def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tensor] = None,

@@ -40,8 +40,9 @@ size_t afr_build_workspace_bytes(int64_t n, int32_t width, int32_t height, int32
     return build_ws_bytes(n, width, height);
 }
 
-afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, void *ws,
-                                 size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream) {
+static afr_status build_checked(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream,
+                                hipEvent_t *stage_end) {
     AFR_TRY(check_buffer(out));
     if (!s || s->n < 0) return AFR_E_INVALID;
     if (s->n >= (int64_t(1) << 31)) return AFR_E_RANGE;
@@ -52,7 +53,23 @@ afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, voi
     const BuildWs w = build_ws_carve(ws, s->n, out->width, out->height);
     unsigned long long *dropped =
         dropped_dev ? reinterpret_cast<unsigned long long *>(dropped_dev) : w.dropped_internal;
-    return from_hip(launch_build(*s, *out, w, dropped, stream));
+    return from_hip(launch_build(*s, *out, w, dropped, stream, stage_end));
+}
+
+afr_status afr_build_deep_buffer(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                 size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream) {
+    return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, nullptr);
+}
+
+int32_t afr_build_stage_count(void) { return kBuildStages; }
+
+afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *out, void *ws,
+                                        size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream,
+                                        hipEvent_t *stage_end) {
+    if (!stage_end) return AFR_E_INVALID;
+    for (int i = 0; i < kBuildStages; ++i)
+        if (!stage_end[i]) return AFR_E_INVALID;
+    return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, stage_end);
 }
 
 afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *params,

@@ -56,11 +56,11 @@ template <typename S, int R, int TPW>
 __global__ __launch_bounds__(kWave) void k_batch(const DevItem *__restrict__ items, int n,
                                                 const int *__restrict__ first,
                                                 int *__restrict__ counter) {
-    constexpr size_t kEst = sizeof(est::Smem), kGat = sizeof(gat::Smem<R, TPW>);
+    constexpr size_t kEst = sizeof(est::Smem<8>), kGat = sizeof(gat::Smem<R, TPW>);
     __shared__ __align__(16) unsigned char raw[kEst > kGat ? kEst : kGat];
     __shared__ float tparam[3 * TPW];
     __shared__ int s_item;
-    est::Smem &esm = *reinterpret_cast<est::Smem *>(raw);
+    est::Smem<8> &esm = *reinterpret_cast<est::Smem<8> *>(raw);
     gat::Smem<R, TPW> &gsm = *reinterpret_cast<gat::Smem<R, TPW> *>(raw);
     const int total = first[n];
     for (;;) {
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kWave) void k_batch(const DevItem *__restrict__ ite
         const int tx0 = (local % gx) * TPW, ty = local / gx;
         for (int t = 0; t < TPW; ++t) {
             if (tx0 + t < d.tg.tiles_x) {
-                est::estimate_tile<S>(v, d.ep, d.tg, ty * d.tg.tiles_x + tx0 + t, d.stats, esm,
+                est::estimate_tile<S, 8>(v, d.ep, d.tg, ty * d.tg.tiles_x + tx0 + t, d.stats, esm,
                                       tparam + 3 * t);
             } else if (threadIdx.x == 0) {  // lanes of a missing tile write nothing
                 tparam[3 * t] = 1.0f;

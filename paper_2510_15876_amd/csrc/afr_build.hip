@@ -29,7 +29,7 @@ constexpr int kScanBlock = kScanThreads * kScanItems;
 constexpr int kChunkThreads = 1024;
 constexpr int kChunkPer = 8;
 constexpr int kChunk = kChunkThreads * kChunkPer;  // samples per chunk
-constexpr int kWin = 1024;                         // records staged in LDS per scatter window
+constexpr int kWin = 4096;  // records staged in LDS per scatter window (128 KiB of gfx950's 160 KiB)
 constexpr int kBinW = 64;                          // bin width, px
 constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
 constexpr int kMaxBinPx = 2048;                    // pixels per bin (rows grow from 4 to 32)
@@ -192,19 +192,35 @@ struct alignas(16) Record {
     unsigned long long key;
     float x, y, t, r, g, b;
 };
-static_assert(sizeof(Record) == 32, "bucket record is 32 bytes");
+static_assert(sizeof(Record) == 32, "staged record is 32 bytes");
+
+// The bucket holds each record as two 16-byte halves in separate arrays: (key, x, y), read by the
+// selection's sweep, and (t, r, g, b), read only for the records a pixel keeps.
+struct alignas(16) KeyXY {
+    unsigned long long key;
+    float x, y;
+};
+static_assert(sizeof(KeyXY) == 16, "record half is 16 bytes");
+struct Bucket {
+    KeyXY *a;
+    float4 *b;
+};
+struct BinRecs {
+    const KeyXY *a;
+    const float4 *b;
+};
 
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
-// position minus that offset), the staged records [kWin] and their global positions [kWin].
+// position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
+// destination, is recomputed from its own x, y.
 __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
                                                                const int32_t *ot, int nchunks,
-                                                               Record *bucket,
+                                                               Bucket bucket,
                                                                unsigned long long *dropped) {
     extern __shared__ uint4 scat_lds[];  // 16-byte aligned for the staged records
     int *scat_sm = reinterpret_cast<int *>(scat_lds);
     int *tab = scat_sm;                                                  // [nb]
     Record *stage = reinterpret_cast<Record *>(scat_sm + ((g.nb + 3) & ~3));  // [kWin]
-    int *sdst = reinterpret_cast<int *>(stage + kWin);                  // [kWin]
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) tab[b] = 0;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     Record rec[kChunkPer];
@@ -245,38 +261,53 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
 #pragma unroll
         for (int j = 0; j < kChunkPer; ++j) {
             const int q = sp[j] - w0;
-            if (bin[j] >= 0 && q >= 0 && q < kWin) {
-                stage[q] = rec[j];
-                sdst[q] = tab[bin[j]] + sp[j];
-            }
+            if (bin[j] >= 0 && q >= 0 && q < kWin) stage[q] = rec[j];
         }
         __syncthreads();
         const int nw = min(kWin, nvalid - w0);
-        for (int q = threadIdx.x; q < nw; q += kChunkThreads) bucket[sdst[q]] = stage[q];
+        for (int q = threadIdx.x; q < nw; q += kChunkThreads) {
+            const Record e = stage[q];
+            const int d = tab[bin_of(e.x, e.y, g)] + w0 + q;
+            bucket.a[d] = KeyXY{e.key, e.x, e.y};
+            bucket.b[d] = make_float4(e.t, e.r, e.g, e.b);
+        }
         __syncthreads();
     }
     bad = wave_sum_int(bad);
     if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
 }
 
+// Stores a record (key, x, y | t, r, g, b) or, when e < 0, an empty slot at slot-plane offset o.
 template <typename S>
-__device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Record *rec) {
+__device__ inline void store_record(const afr_deep_buffer &out, size_t o, int e, const KeyXY &a,
+                                    const float4 &c) {
     S *ox = static_cast<S *>(out.ox), *oy = static_cast<S *>(out.oy);
     S *ta = static_cast<S *>(out.tage), *r = static_cast<S *>(out.r);
     S *g = static_cast<S *>(out.g), *b = static_cast<S *>(out.b);
-    if (rec) {
-        const Record e = *rec;
-        ox[o] = Codec<S>::enc(e.x - floorf(e.x));
-        oy[o] = Codec<S>::enc(e.y - floorf(e.y));
-        ta[o] = Codec<S>::enc_time(e.t, out.t_ref);
-        r[o] = Codec<S>::enc(e.r);
-        g[o] = Codec<S>::enc(e.g);
-        b[o] = Codec<S>::enc(e.b);
-        if (out.src) out.src[o] = key_index(e.key);
+    if (e >= 0) {
+        ox[o] = Codec<S>::enc(a.x - floorf(a.x));
+        oy[o] = Codec<S>::enc(a.y - floorf(a.y));
+        ta[o] = Codec<S>::enc_time(c.x, out.t_ref);
+        r[o] = Codec<S>::enc(c.y);
+        g[o] = Codec<S>::enc(c.z);
+        b[o] = Codec<S>::enc(c.w);
+        if (out.src) out.src[o] = key_index(a.key);
     } else {
         ox[o] = oy[o] = ta[o] = r[o] = g[o] = b[o] = Codec<S>::enc(0.0f);
         if (out.src) out.src[o] = -1;
     }
+}
+
+// Stores record e of the bin (or an empty slot when e < 0) at slot-plane offset o.
+template <typename S>
+__device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const BinRecs &rs, int e) {
+    KeyXY a{0ull, 0.0f, 0.0f};
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e >= 0) {
+        a = rs.a[e];
+        c = rs.b[e];
+    }
+    store_record<S>(out, o, e, a, c);
 }
 
 // Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: insertion into a
@@ -284,7 +315,7 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Re
 // in every lane). Larger K: repeated maximum scans. The selected records are then loaded together.
 template <typename S, int KMAX>
 __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t hw,
-                                    const Record *recs, const unsigned long long *keys,
+                                    const BinRecs &recs, const unsigned long long *keys,
                                     const unsigned short *pos, int l0, int l1) {
     const int K = out.k;
     int nvalid = 0;
@@ -312,9 +343,27 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
             }
         }
         const int n = min(nvalid, K);
+        // The kept records are fetched four at a time, all loads before the stores, so that a
+        // lane waits for memory once per group instead of once per slot.
+        constexpr int kG = KMAX < 4 ? KMAX : 4;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (k < K) store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + tp[k] : nullptr);
+        for (int k0 = 0; k0 < KMAX; k0 += kG) {
+            KeyXY a[kG];
+            float4 c[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                a[j] = KeyXY{0ull, 0.0f, 0.0f};
+                c[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k0 + j < n) {
+                    a[j] = recs.a[tp[k0 + j]];
+                    c[j] = recs.b[tp[k0 + j]];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (k0 + j < K)
+                    store_record<S>(out, (size_t)(k0 + j) * hw + p, k0 + j < n ? 0 : -1, a[j], c[j]);
+        }
         out.count[p] = (uint8_t)n;
     } else {
         for (int l = l0; l < l1; ++l) nvalid += keys[l] != 0ull;
@@ -332,7 +381,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
                 }
                 prev = best;
             }
-            store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + be : nullptr);
+            store_slot<S>(out, (size_t)k * hw + p, recs, k < n ? be : -1);
         }
         out.count[p] = (uint8_t)n;
     }
@@ -341,11 +390,13 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
 // Same selection straight from the bin's records, for passes whose records exceed the LDS list.
 template <typename S>
 __device__ inline void select_pixel_scan(const afr_deep_buffer &out, size_t p, size_t hw,
-                                         const Record *recs, int nrec, int px, int py) {
+                                         const BinRecs &recs, int nrec, int px, int py) {
     const int K = out.k;
-    auto mine = [&](int e) { return (int)floorf(recs[e].x) == px && (int)floorf(recs[e].y) == py; };
+    auto mine = [&](int e) {
+        return (int)floorf(recs.a[e].x) == px && (int)floorf(recs.a[e].y) == py;
+    };
     int nvalid = 0;
-    for (int e = 0; e < nrec; ++e) nvalid += mine(e) && recs[e].key != 0ull;
+    for (int e = 0; e < nrec; ++e) nvalid += mine(e) && recs.a[e].key != 0ull;
     const int n = min(nvalid, K);
     unsigned long long prev = ~0ull;
     for (int k = 0; k < K; ++k) {
@@ -353,35 +404,27 @@ __device__ inline void select_pixel_scan(const afr_deep_buffer &out, size_t p, s
         int be = 0;
         if (k < n) {
             for (int e = 0; e < nrec; ++e) {
-                const unsigned long long c = recs[e].key;
+                const unsigned long long c = recs.a[e].key;
                 const bool take = mine(e) && c < prev && c > best;
                 best = take ? c : best;
                 be = take ? e : be;
             }
             prev = best;
         }
-        store_slot<S>(out, (size_t)k * hw + p, k < n ? recs + be : nullptr);
+        store_slot<S>(out, (size_t)k * hw + p, recs, k < n ? be : -1);
     }
     out.count[p] = (uint8_t)n;
 }
 
 // Key, x and y of a record in one 16-byte load.
-struct KeyXY {
-    unsigned long long key;
-    float x, y;
-};
-__device__ inline KeyXY load_key_xy(const Record *r) {
-    const uint4 v = *reinterpret_cast<const uint4 *>(r);
-    return {(unsigned long long)v.x | ((unsigned long long)v.y << 32), __uint_as_float(v.z),
-            __uint_as_float(v.w)};
-}
+__device__ inline KeyXY load_key_xy(const KeyXY *r) { return *r; }
 
 // One workgroup per bin. LDS: per-pixel offsets [npx + 1], then the key list [kListCap] (u64)
 // and the records' positions in the bin [kListCap] (u16).
 template <typename S, int KMAX>
 __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out, BinGeom g,
                                                             const int32_t *ot, int nchunks,
-                                                            const Record *bucket) {
+                                                            Bucket bucket) {
     extern __shared__ uint4 sel_lds[];  // 16-byte aligned for the key list
     int *sel_sm = reinterpret_cast<int *>(sel_lds);
     const int npx = g.bw * g.bh;
@@ -391,7 +434,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     const int b = blockIdx.x;
     const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
     const int nrec = s1 - s0;
-    const Record *recs = bucket + s0;
+    const BinRecs recs{bucket.a + s0, bucket.b + s0};
     const int bx0 = (b % g.nbx) * g.bw, by0 = (b / g.nbx) * g.bh;
     const int W = out.width, H = out.height;
     const size_t hw = (size_t)W * H;
@@ -409,7 +452,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
         for (int j = 0; j < kSelPer; ++j) {
             const int e = j * kSelThreads + threadIdx.x;
             if (e < nrec) {
-                const KeyXY r = load_key_xy(recs + e);
+                const KeyXY r = load_key_xy(recs.a + e);
                 kk[j] = r.key;
                 id[j] = local_id(r.x, r.y);
                 rk[j] = atomicAdd(&poff[id[j]], 1);
@@ -442,7 +485,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     // list is [end of the previous pixel, own end). A single row beyond the list (or a bin beyond
     // u16 positions) takes the direct scan.
     for (int e = threadIdx.x; e < nrec; e += kSelThreads) {
-        const KeyXY r = load_key_xy(recs + e);
+        const KeyXY r = load_key_xy(recs.a + e);
         atomicAdd(&poff[local_id(r.x, r.y)], 1);
     }
     __syncthreads();
@@ -457,7 +500,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
         __syncthreads();  // every thread has read the bounds before the fill moves them
         if (hi - lo <= kListCap && nrec <= 65536) {
             for (int e = threadIdx.x; e < nrec; e += kSelThreads) {
-                const KeyXY r = load_key_xy(recs + e);
+                const KeyXY r = load_key_xy(recs.a + e);
                 const int q = local_id(r.x, r.y);
                 if (q >= q0 && q < q1) {
                     const int l = atomicAdd(&poff[q], 1) - lo;
@@ -490,7 +533,7 @@ size_t select_shmem(const BinGeom &g) {
 
 template <typename S>
 hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *ot,
-                         int nchunks, const Record *bucket, hipStream_t st) {
+                         int nchunks, Bucket bucket, hipStream_t st) {
     const size_t shmem = select_shmem(g);
     const dim3 grid(g.nb), block(kSelThreads);
     if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
@@ -533,7 +576,7 @@ size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
     const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     return align_up((size_t)(len + 1) * 4) + align_up((size_t)(nsb + 1) * 4) +
-           align_up(nn * sizeof(Record)) + align_up(8);
+           2 * align_up(nn * sizeof(KeyXY)) + align_up(8);
 }
 
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
@@ -548,38 +591,43 @@ BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     o.bsum = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)(nsb + 1) * 4);
     o.bucket = p;
-    p += align_up(nn * sizeof(Record));
+    p += 2 * align_up(nn * sizeof(KeyXY));
     o.dropped_internal = reinterpret_cast<unsigned long long *>(p);
     return o;
 }
 
 hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const BuildWs &ws,
-                        unsigned long long *dropped, hipStream_t st) {
+                        unsigned long long *dropped, hipStream_t st, hipEvent_t *stage_end) {
+    auto mark = [&](int i) { return stage_end ? hipEventRecord(stage_end[i], st) : hipSuccess; };
     const ValidCtx c{out.width, out.height, out.t_ref, out.precision == AFR_FP16 ? 1 : 0};
     const BinGeom g = bin_geom(out.width, out.height);
     const int64_t nch = n_chunks(s.n);
     const int64_t len = (int64_t)g.nb * nch;
     const int nsb = (int)((len + kScanBlock - 1) / kScanBlock);
-    Record *bucket = static_cast<Record *>(ws.bucket);
+    const size_t half = align_up((size_t)(s.n > 0 ? s.n : 1) * sizeof(KeyXY));
+    const Bucket bucket{static_cast<KeyXY *>(ws.bucket),
+                        reinterpret_cast<float4 *>(static_cast<char *>(ws.bucket) + half)};
     k_zero_dropped<<<1, 1, 0, st>>>(dropped);
     if (s.n > 0)
         k_bin_count<<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch, dropped);
     else  // no samples: every (bin, chunk) count of the single empty chunk is zero
         k_fill_zero<<<std::max(1, std::min((int)((len + 255) / 256), 1024)), 256, 0, st>>>(ws.offsets,
                                                                                        len);
+    hipError_t e = mark(0);
+    if (e != hipSuccess) return e;
     k_scan_blocks<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.offsets, ws.bsum);
     k_scan_sums<<<1, kScanThreads, 0, st>>>(ws.bsum, nsb);
     k_scan_add<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.bsum, nsb);
+    if ((e = mark(1)) != hipSuccess) return e;
     const size_t scat_shmem =
-        (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * (sizeof(Record) + sizeof(int));
+        (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
     if (s.n > 0)
         k_bin_scatter<<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets, (int)nch,
                                                                    bucket, dropped);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return out.precision == AFR_FP16
-               ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, st)
-               : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, st);
+    if ((e = hipGetLastError()) != hipSuccess || (e = mark(2)) != hipSuccess) return e;
+    e = out.precision == AFR_FP16 ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, st)
+                                  : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, st);
+    return e != hipSuccess ? e : mark(3);
 }
 
 }  // namespace afr

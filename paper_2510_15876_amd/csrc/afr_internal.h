@@ -137,12 +137,45 @@ struct BuildWs {
     void *bucket;       // [n] 32-byte records grouped by bin
     unsigned long long *dropped_internal;
 };
-// Images whose bin table fits the build's LDS histogram (up to ~16.7 M pixels).
+// Buffer-resource loads of one slot plane: the descriptor (SGPRs) holds the plane's base address
+// and byte size, each lane passes only a 32-bit byte offset, and a load at or past the size returns
+// zero instead of touching memory. Plane sizes are < 2^31 bytes (width * height < 2^29).
+constexpr int kBufferWord3 = 0x00020000;  // gfx9 family: raw (untyped) 32-bit data
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+template <typename S>
+__device__ inline S plane_load(__amdgpu_buffer_rsrc_t r, unsigned byte_off);
+template <>
+__device__ inline float plane_load<float>(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+template <>
+__device__ inline __half plane_load<__half>(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs (physical id b runs on XCD b % 8). Give XCD x the
+// logical ids x*per .. x*per+per-1 so that each XCD's L2 serves a contiguous band of the image and
+// the halo rows neighbouring workgroups share stay in one L2. The last nblocks % 8 ids map to
+// themselves, so the mapping is a bijection for every grid size.
+__device__ inline int xcd_remap(int b, int nblocks) {
+    constexpr int kXcd = 8;
+    const int per = nblocks / kXcd;
+    const int x = b % kXcd, local = b / kXcd;
+    return local < per ? x * per + local : b;
+}
+
+// Images whose bin table fits the build's LDS tables (up to 4096 bins of 64 x 32 px, ~8.4 M pixels).
 bool build_supported(int32_t w, int32_t h);
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h);
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h);
+// stage_end (nullable) receives, in order, an event record after the count, scan, scatter and
+// select kernels (kBuildStages events).
+constexpr int kBuildStages = 4;
 hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const BuildWs &ws,
-                        unsigned long long *dropped, hipStream_t st);
+                        unsigned long long *dropped, hipStream_t st, hipEvent_t *stage_end);
 
 hipError_t launch_estimate(const afr_deep_buffer &buf, const afr_params &p, const afr_tile_stats &out,
                            hipStream_t st);

@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, gat::
                                                             float *__restrict__ aux, int gx) {
     __shared__ gat::Smem<R, TPW> sm;
     __shared__ float tparam[3 * TPW];
-    const int bid = gat::xcd_remap(blockIdx.x, gridDim.x);
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx0 = (bid % gx) * TPW, ty = bid / gx;
     if (threadIdx.x < 3 * TPW) {
         const int t = threadIdx.x / 3, f = threadIdx.x % 3;

@@ -25,7 +25,6 @@ struct EstParams {
 
 // Rec. 709 luminance weights of linear RGB.
 constexpr double kLumR = 0.2126, kLumG = 0.7152, kLumB = 0.0722;
-constexpr int kHaloMax = (kMaxTile + 2) * (kMaxTile + 2);
 
 struct Acc {
     double gx, wx, gy, wy, gt, wt;  // sums of Omega_p G(p) and Omega_p over defined pixels
@@ -107,19 +106,21 @@ __device__ inline void extents(double gx, double gy, double gt, double vol, cons
     }
 }
 
-// LDS scratch of one tile evaluation.
+// LDS scratch of one tile evaluation for tiles of edge <= TB (the tile and its one-pixel halo).
+template <int TB>
 struct Smem {
-    double lbar[kHaloMax], om[kHaloMax], gt[kHaloMax], sa[kHaloMax], m2[kHaloMax];
-    int n[kHaloMax];
+    static constexpr int kHalo = (TB + 2) * (TB + 2);
+    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
+    int n[kHalo];
     Acc wave[256 / kWave];
 };
 
-// Evaluates tile T with the calling workgroup (blockDim.x threads, a multiple of 64, <= 256) and
-// writes its statistics. If tparams is not NULL, thread 0 also stores (sx2, sy2, kt2) there (LDS),
+// Evaluates tile T (edge tg.tile <= TB) with the calling workgroup (blockDim.x threads, a multiple
+// of 64, <= 256, with 2 * blockDim.x >= (tile + 2)^2) and writes its statistics. If tparams is not NULL, thread 0 also stores (sx2, sy2, kt2) there (LDS),
 // visible to the workgroup after the caller's next barrier.
-template <typename S>
+template <typename S, int TB>
 __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int T,
-                              float *stats, Smem &sm, float *tparams) {
+                              float *stats, Smem<TB> &sm, float *tparams) {
     double *s_lbar = sm.lbar, *s_om = sm.om, *s_gt = sm.gt, *s_sa = sm.sa, *s_m2 = sm.m2;
     int *s_n = sm.n;
     Acc *s_wave = sm.wave;
@@ -129,50 +130,95 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
     const int rw = bw + 2, rh = bh + 2;
     const size_t hw = (size_t)v.width * v.height;
 
-    // Phase 1: per-pixel moments over the tile and its one-pixel halo.
-    for (int h = threadIdx.x; h < rw * rh; h += blockDim.x) {
+    // Phase 1: per-pixel moments over the tile and its one-pixel halo. Each lane takes up to
+    // kItems pixels of the region; the slot planes are visited in chunks of kChunk, and every load
+    // of a chunk (all items, all planes of the chunk) is issued before any of them is used, so a
+    // lane waits for memory once per chunk instead of once per slot. Per pixel the slots are still
+    // added in rank order, so the sums do not depend on the chunking.
+    constexpr int kItems = 2, kChunk = 8;
+    const int nh = rw * rh;
+    int px_[kItems], n_[kItems];
+    int kmax = 0;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int h = threadIdx.x + it * blockDim.x;
         const int x = i0 - 1 + h % rw, y = j0 - 1 + h / rw;
-        int n = 0;
-        double om = 0.0, lb = 0.0, gt = -1.0, sa = 0.0, m2 = 0.0;
-        if (x >= 0 && x < v.width && y >= 0 && y < v.height) {
-            const size_t px = (size_t)y * v.width + x;
-            n = v.count[px];
-            const int half = (n + 1) / 2;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, ln = 0.0, lo = 0.0, an = 0.0, ao = 0.0;
-            for (int k = 0; k < n; ++k) {
-                const size_t s = (size_t)k * hw + px;
-                const double L = kLumR * (double)Codec<S>::dec(v.r[s]) +
-                                 kLumG * (double)Codec<S>::dec(v.g[s]) +
-                                 kLumB * (double)Codec<S>::dec(v.b[s]);
-                const double a = Codec<S>::age64(v.ta[s], p.t_now, p.dt_ref);
-                const double w = (double)expf((float)(-p.alpha * a));
-                s0 += w;
-                s1 += w * L;
-                s2 += w * L * L;
-                sa += a;
-                if (k < half) {
-                    ln += L;
-                    an += a;
-                } else {
-                    lo += L;
-                    ao += a;
+        const bool live = h < nh && x >= 0 && x < v.width && y >= 0 && y < v.height;
+        px_[it] = live ? y * v.width + x : 0;
+        n_[it] = live ? v.count[px_[it]] : 0;
+        kmax = max(kmax, n_[it]);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+    const size_t bytes = hw * sizeof(S);
+    double s0[kItems], s1[kItems], s2[kItems], ln[kItems], lo[kItems], an[kItems], ao[kItems],
+        sa_[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+        s0[it] = s1[it] = s2[it] = ln[it] = lo[it] = an[it] = ao[it] = sa_[it] = 0.0;
+    for (int k0 = 0; k0 < kmax; k0 += kChunk) {
+        S cr[kChunk][kItems], cg[kChunk][kItems], cb[kChunk][kItems], ct[kChunk][kItems];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            const int k = min(k0 + j, v.k - 1);  // planes past K are never used
+            const size_t base = (size_t)k * hw;
+            const auto rr = plane_rsrc(v.r + base, bytes), rg = plane_rsrc(v.g + base, bytes);
+            const auto rb = plane_rsrc(v.b + base, bytes), rt = plane_rsrc(v.ta + base, bytes);
+#pragma unroll
+            for (int it = 0; it < kItems; ++it) {
+                const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
+                cr[j][it] = plane_load<S>(rr, off);
+                cg[j][it] = plane_load<S>(rg, off);
+                cb[j][it] = plane_load<S>(rb, off);
+                ct[j][it] = plane_load<S>(rt, off);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            const int k = k0 + j;
+#pragma unroll
+            for (int it = 0; it < kItems; ++it) {
+                if (k < n_[it]) {
+                    const double L = kLumR * (double)Codec<S>::dec(cr[j][it]) +
+                                     kLumG * (double)Codec<S>::dec(cg[j][it]) +
+                                     kLumB * (double)Codec<S>::dec(cb[j][it]);
+                    const double a = Codec<S>::age64(ct[j][it], p.t_now, p.dt_ref);
+                    const double w = (double)expf((float)(-p.alpha * a));
+                    s0[it] += w;
+                    s1[it] += w * L;
+                    s2[it] += w * L * L;
+                    sa_[it] += a;
+                    if (k < (n_[it] + 1) / 2) {
+                        ln[it] += L;
+                        an[it] += a;
+                    } else {
+                        lo[it] += L;
+                        ao[it] += a;
+                    }
                 }
             }
-            if (n > 0) {
-                om = s0;
-                lb = s1 / s0;
-                m2 = fmax(s2 - s1 * lb, 0.0);
-            }
-            if (n >= 2) {
-                const double dn = half, dd = n - half;
-                gt = fabs(ln / dn - lo / dd) / fmax(ao / dd - an / dn, p.dt_floor);
-            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int h = threadIdx.x + it * blockDim.x;
+        if (h >= nh) continue;
+        const int n = n_[it];
+        double om = 0.0, lb = 0.0, gt = -1.0, m2 = 0.0;
+        if (n > 0) {
+            om = s0[it];
+            lb = s1[it] / s0[it];
+            m2 = fmax(s2[it] - s1[it] * lb, 0.0);
+        }
+        if (n >= 2) {
+            const int half = (n + 1) / 2;
+            const double dn = half, dd = n - half;
+            gt = fabs(ln[it] / dn - lo[it] / dd) / fmax(ao[it] / dd - an[it] / dn, p.dt_floor);
         }
         s_n[h] = n;
         s_om[h] = om;
         s_lbar[h] = lb;
         s_gt[h] = gt;
-        s_sa[h] = sa;
+        s_sa[h] = sa_[it];
         s_m2[h] = m2;
     }
     __syncthreads();

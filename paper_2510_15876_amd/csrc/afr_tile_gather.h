@@ -30,19 +30,37 @@ namespace afr {
 namespace gat {
 
 constexpr float kLog2e = 1.4426950408889634f;
+
+// 2^x by the hardware instruction: results below the smallest normal flush to zero (such weights
+// are < 2^-126 of the largest and cannot move a normalised sum).
+__device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 constexpr int kB = 8;  // statistics tile edge handled by this kernel
 
 struct TiledParams {
     float t_now, dt_ref;
 };
 
-// LDS of one group evaluation.
+// LDS of one group evaluation. P: one float4 per source pixel of each tile's region (row pitch RW).
+// XY: per tile and offset m, the region's X values in columns [0, RW) and its Y values in columns
+// [RW, 2 RW) of rows with pitch XP. XP is 8 times an odd number, so an 8 x 8 block of lanes reading
+// (row + h, col + c) hits 64 distinct banks (and each half-wave 32), and tiles are XYS apart with
+// XYS = 8 (mod 64), which puts the lane blocks of up to four tiles on disjoint banks.
+template <int R>
+struct XYLayout {
+    static constexpr int RW = 8 + 2 * R, NM = 2 * R + 1;
+    static constexpr int XP = (2 * RW <= 24) ? 24 : 40;
+    static constexpr int XYM = RW * XP;                                 // one offset m
+    static constexpr int XYS = (NM * XYM + 55) / 64 * 64 + 8;           // one tile
+};
+// P: with one tile per wave, (P.x, P.y) and (P.z, P.w) of region (row, col) are float2s at
+// row * XP + col and row * XP + RW + col, so the 64-bit reads of an 8 x 8 lane block hit distinct
+// banks; with more tiles per wave, one float4 per pixel with row pitch RW and tile pitch PS.
 template <int R, int TPW>
 struct Smem {
-    static constexpr int RW = 8 + 2 * R, NP = RW * RW, PS = NP + 5, NM = 2 * R + 1;
-    float4 P[TPW * PS];
-    float X[TPW * NM * PS];
-    float Y[TPW * NM * PS];
+    static constexpr int RW = 8 + 2 * R, NP = RW * RW, PS = NP + 5;
+    static constexpr int NP4 = TPW == 1 ? RW * XYLayout<R>::XP / 2 : TPW * PS;
+    float4 P[NP4];
+    float XY[TPW * XYLayout<R>::XYS];
 };
 
 // Exact two-pass evaluation of one pixel (the direct form), used when the shared shift underflows.
@@ -110,17 +128,6 @@ __device__ inline int wave_max_int(int v) {
     return v;
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (physical id b runs on XCD b % 8). Give XCD x the
-// logical ids x*per .. x*per+per-1 so that each XCD's L2 serves a contiguous band of the image and
-// the halo rows neighbouring workgroups share stay in one L2. The last nblocks % 8 ids map to
-// themselves, so the mapping is a bijection for every grid size.
-__device__ inline int xcd_remap(int b, int nblocks) {
-    constexpr int kXcd = 8;
-    const int per = nblocks / kXcd;
-    const int x = b % kXcd, local = b / kXcd;
-    return local < per ? x * per + local : b;
-}
-
 // One wave per TPW horizontally adjacent tiles; LPT = 64 / TPW lanes per tile, each lane owning
 // ROWS = 8 * 8 / LPT output rows of one tile column. TPW only changes how work is spread over lanes;
 // every pixel sums the same terms in the same order, so the output is identical for every TPW.
@@ -137,8 +144,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     constexpr int PS = NP + 5;              // padded plane stride (spreads tiles over LDS banks)
     constexpr int NM = 2 * R + 1;           // offsets per axis
     constexpr int ITEMS = (NP + LPT - 1) / LPT;
+    constexpr int XP = XYLayout<R>::XP, XYM = XYLayout<R>::XYM;
     float4 *sP = sm.P;
-    float *sX = sm.X, *sY = sm.Y;
 
     const int W = v.width, H = v.height;
     const size_t hw = (size_t)W * H;
@@ -157,8 +164,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     float gxm[NM], gym[NM];
 #pragma unroll
     for (int m = 0; m < 2 * R; ++m) {
-        gxm[m] = exp2f(-(float)(2 * (m - R) + 1) * cx2);
-        gym[m] = exp2f(-(float)(2 * (m - R) + 1) * cy2);
+        gxm[m] = fast_exp2(-(float)(2 * (m - R) + 1) * cx2);
+        gym[m] = fast_exp2(-(float)(2 * (m - R) + 1) * cy2);
     }
 
     // Items: this lane's source pixels of its tile region; address and depth are loop invariant.
@@ -194,65 +201,81 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[u][c] = cmp[u][c] = 0.0f;
 
-    // Raw slot data of one plane, prefetched one plane ahead.
+    // Raw slot data of one plane, prefetched one plane ahead: buffer loads with the plane's base in
+    // scalar registers and this lane's loop-invariant byte offset.
+    unsigned ioff[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) ioff[it] = (unsigned)iq[it] * (unsigned)sizeof(S);
     S rox[ITEMS], roy[ITEMS], rta[ITEMS], rr[ITEMS], rg[ITEMS], rb[ITEMS];
     auto load_plane = [&](int k) {
+        const size_t base = (size_t)k * hw, bytes = hw * sizeof(S);
+        const auto rox_ = plane_rsrc(v.ox + base, bytes), roy_ = plane_rsrc(v.oy + base, bytes);
+        const auto rta_ = plane_rsrc(v.ta + base, bytes), rr_ = plane_rsrc(v.r + base, bytes);
+        const auto rg_ = plane_rsrc(v.g + base, bytes), rb_ = plane_rsrc(v.b + base, bytes);
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const size_t s = (size_t)min(k, v.k - 1) * hw + iq[it];
-            rox[it] = v.ox[s];
-            roy[it] = v.oy[s];
-            rta[it] = v.ta[s];
-            rr[it] = v.r[s];
-            rg[it] = v.g[s];
-            rb[it] = v.b[s];
+            rox[it] = plane_load<S>(rox_, ioff[it]);
+            roy[it] = plane_load<S>(roy_, ioff[it]);
+            rta[it] = plane_load<S>(rta_, ioff[it]);
+            rr[it] = plane_load<S>(rr_, ioff[it]);
+            rg[it] = plane_load<S>(rg_, ioff[it]);
+            rb[it] = plane_load<S>(rb_, ioff[it]);
         }
     };
     if (kmax > 0) load_plane(0);
 
     float4 *tP = sP + my_t * PS;
-    float *tX = sX + my_t * NM * PS;
-    float *tY = sY + my_t * NM * PS;
+    float2 *tPP = reinterpret_cast<float2 *>(sP);  // split layout (one tile per wave)
+    float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col) at row * XP + col
+    float *tY = tX + RW;                          // Y at row * XP + RW + col
     for (int k = 0; k < kmax; ++k) {
-        // Separable factors of plane k for this tile's source region.
+        // Separable factors of plane k for this tile's source region. A slot beyond its pixel's
+        // count (or a pixel outside the image) gets P = 0 and finite dummy factors.
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int pix = sub + it * LPT;
             if (pix < NP) {
-                float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
+                const bool on = k < icnt[it];
+                const float dx = on ? Codec<S>::dec(rox[it]) - 0.5f : 0.0f;
+                const float dy = on ? Codec<S>::dec(roy[it]) - 0.5f : 0.0f;
+                const float a = on ? Codec<S>::age(rta[it], p.t_now, p.dt_ref) : amin;
+                const float tm = fast_exp2(-((a - amin) * (a + amin)) * ct2);
+                const float4 P =
+                    on ? make_float4(tm, tm * Codec<S>::dec(rr[it]), tm * Codec<S>::dec(rg[it]),
+                                     tm * Codec<S>::dec(rb[it]))
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
                 float X[NM], Y[NM];
+                const float ex = dx - (float)R, ey = dy - (float)R;
+                X[0] = fast_exp2(-ex * ex * cx2);
+                Y[0] = fast_exp2(-ey * ey * cy2);
+                if (R > 0) {
+                    const float rhox = fast_exp2(-2.0f * dx * cx2), rhoy = fast_exp2(-2.0f * dy * cy2);
 #pragma unroll
-                for (int m = 0; m < NM; ++m) X[m] = Y[m] = 0.0f;
-                if (k < icnt[it]) {
-                    const float dx = Codec<S>::dec(rox[it]) - 0.5f;
-                    const float dy = Codec<S>::dec(roy[it]) - 0.5f;
-                    const float a = Codec<S>::age(rta[it], p.t_now, p.dt_ref);
-                    const float tm = exp2f(-((a - amin) * (a + amin)) * ct2);
-                    P = make_float4(tm, tm * Codec<S>::dec(rr[it]), tm * Codec<S>::dec(rg[it]),
-                                    tm * Codec<S>::dec(rb[it]));
-                    // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
-                    const float ex = dx - (float)R, ey = dy - (float)R;
-                    X[0] = exp2f(-ex * ex * cx2);
-                    Y[0] = exp2f(-ey * ey * cy2);
-                    if (R > 0) {
-                        const float rhox = exp2f(-2.0f * dx * cx2), rhoy = exp2f(-2.0f * dy * cy2);
-#pragma unroll
-                        for (int m = 0; m < 2 * R; ++m) {
-                            X[m + 1] = X[m] * rhox * gxm[m];
-                            Y[m + 1] = Y[m] * rhoy * gym[m];
-                        }
+                    for (int m = 0; m < 2 * R; ++m) {
+                        X[m + 1] = X[m] * rhox * gxm[m];
+                        Y[m + 1] = Y[m] * rhoy * gym[m];
                     }
                 }
-                tP[pix] = P;
+                const int xy = (pix / RW) * XP + pix % RW;
+                if constexpr (TPW == 1) {
+                    tPP[xy] = make_float2(P.x, P.y);
+                    tPP[xy + RW] = make_float2(P.z, P.w);
+                } else {
+                    tP[pix] = P;
+                }
 #pragma unroll
                 for (int m = 0; m < NM; ++m) {
-                    tX[m * PS + pix] = X[m];
-                    tY[m * PS + pix] = Y[m];
+                    tX[m * XYM + xy] = X[m];
+                    tY[m * XYM + xy] = Y[m];
                 }
             }
         }
-        if (k + 1 < kmax) load_plane(k + 1);  // in flight while plane k is accumulated
         __syncthreads();
+        // Plane k+1 is loaded in the same scheduling region as plane k's accumulation (no branch
+        // around it: after the last plane it reloads plane K-1, unused), so the accumulation
+        // covers the load latency.
+        load_plane(min(k + 1, v.k - 1));
         // Lane owns rows my_h*ROWS + u of column my_c. Source row (region coordinates)
         // my_h*ROWS + vv, source column my_c + w; offsets m = w - R, n = vv - u - R.
         float part[ROWS][4];
@@ -265,13 +288,20 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
 #pragma unroll
             for (int w = 0; w < NM; ++w) {
                 const int pix = (my_h * ROWS + vv) * RW + my_c + w;
-                const float4 P = tP[pix];
-                const float x = tX[w * PS + pix];
+                const int xy = (my_h * ROWS + vv) * XP + my_c + w;
+                float4 P;
+                if constexpr (TPW == 1) {
+                    const float2 a = tPP[xy], b = tPP[xy + RW];
+                    P = make_float4(a.x, a.y, b.x, b.y);
+                } else {
+                    P = tP[pix];
+                }
+                const float x = tX[w * XYM + xy];
 #pragma unroll
                 for (int u = 0; u < ROWS; ++u) {
                     const int nn = vv - u;  // n + R
                     if (nn >= 0 && nn <= 2 * R) {
-                        const float wgt = x * tY[nn * PS + pix];
+                        const float wgt = x * tY[nn * XYM + xy];
                         part[u][0] += wgt * P.x;
                         part[u][1] += wgt * P.y;
                         part[u][2] += wgt * P.z;

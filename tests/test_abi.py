@@ -117,3 +117,9 @@ def test_stats_geometry_and_workspace_checks(afr):
     assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 16, None, None) == 4
     s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1 << 31)
     assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 40, None, None) == 2
+    # staged build: four stage events, none of them NULL
+    assert lib.afr_build_stage_count() == 4
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000)
+    evs = (ctypes.c_void_p * 4)(0x10, 0x20, None, 0x40)
+    assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, evs) == 1
+    assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, None) == 1

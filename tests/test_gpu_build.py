@@ -59,3 +59,61 @@ def test_build_drops_invalid_samples_and_handles_empty_streams():
     gbuf, gd = gpu_build(empty, w, h, 3, "fp32", 4.0)
     assert gd == 0 and int(gbuf.count.sum().item()) == 0
     assert bool((gbuf.src == -1).all().item()) and bool((gbuf.planes == 0).all().item())
+
+
+def _dense_stream(rng, w, h, per_px):
+    """Stratified positions with per-pixel multiplicity ``per_px`` (an [h, w] int array), distinct
+    times drawn from a coarse grid (ties) and uniform colours."""
+    ys, xs = np.nonzero(per_px >= 0)
+    reps = per_px[ys, xs]
+    px = np.repeat(xs, reps).astype(np.float64)
+    py = np.repeat(ys, reps).astype(np.float64)
+    n = px.size
+    x = (px + rng.random(n)).astype(np.float32)
+    y = (py + rng.random(n)).astype(np.float32)
+    t = rng.choice(np.arange(0, 500, 0.25, dtype=np.float32), n)
+    c = rng.random((3, n)).astype(np.float32)
+    perm = rng.permutation(n)
+    return S.Stream(x[perm], y[perm], t[perm], c[0][perm], c[1][perm], c[2][perm])
+
+
+@pytest.mark.parametrize("case", ["row_passes", "dense_row_scan", "huge_bin_scan"])
+def test_build_select_paths_for_large_bins(case):
+    """Bins beyond the register sweep: passes over row groups, a single row beyond the LDS list
+    (direct scan of that row) and a bin beyond 16-bit record positions (direct scan of the bin)."""
+    rng = np.random.default_rng({"row_passes": 1, "dense_row_scan": 2, "huge_bin_scan": 3}[case])
+    if case == "row_passes":
+        w, h, k = 64, 8, 16
+        per = np.full((h, w), 50)
+    elif case == "dense_row_scan":
+        w, h, k = 64, 4, 8
+        per = np.full((h, w), 6)
+        per[1] = 120
+    else:
+        w, h, k = 16, 4, 3
+        per = np.full((h, w), 1100)
+    s = _dense_stream(rng, w, h, per)
+    print(f"build select path {case}: {w}x{h} K={k} n={len(s)}", flush=True)
+    for precision in ("fp32", "fp16"):
+        gbuf, gd = gpu_build(s, w, h, k, precision, 500.0)
+        obuf, od = O.build_buffer(s, w, h, k, precision, 500.0)
+        assert gd == od == 0
+        assert_buffers_equal(gbuf, obuf)
+
+
+def test_staged_build_equals_build_and_times_every_stage():
+    import torch
+    import paper_2510_15876_amd as afr
+    wl = workload("c2")
+    dev = torch.device("cuda:0")
+    arrs = [torch.from_numpy(a).to(dev) for a in wl.stream.arrays()]
+    a, da = afr.build_deep_buffer(*arrs, wl.width, wl.height, wl.k, "fp16", wl.t_ref)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(afr.build_stage_count() + 1)]
+    evs[0].record()
+    b, db = afr.build_deep_buffer(*arrs, wl.width, wl.height, wl.k, "fp16", wl.t_ref,
+                                  stage_events=evs[1:])
+    torch.cuda.synchronize()
+    assert torch.equal(a.planes, b.planes) and torch.equal(a.count, b.count)
+    assert torch.equal(a.src, b.src) and int(da.item()) == int(db.item())
+    times = [evs[i].elapsed_time(evs[i + 1]) for i in range(len(evs) - 1)]
+    assert all(t >= 0.0 for t in times) and sum(times) > 0.0
