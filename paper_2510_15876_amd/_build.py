@@ -25,7 +25,7 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fno-gpu-rdc", "-ffp-contract=fast",
+    "-fno-gpu-rdc", "-ffp-contract=on",
 ]
 
 

@@ -1,5 +1,6 @@
-// afr_estimate_gradients: one workgroup per statistics tile (see afr_tile_estimate.h), tiles dealt
-// to XCDs in contiguous bands so that the one-pixel halos neighbouring tiles share hit one L2.
+// afr_estimate_gradients (see afr_tile_estimate.h): for tiles of edge <= 8 one 256-thread workgroup
+// per 64-pixel-wide strip of tiles, else one workgroup per tile. Workgroups are dealt to XCDs in
+// contiguous bands so that the one-pixel halos neighbouring workgroups share hit one L2.
 #include "afr_tile_estimate.h"
 
 namespace afr {
@@ -10,6 +11,16 @@ __global__ __launch_bounds__(TB <= 8 ? 64 : 256) void k_estimate(BufView<S> v, e
                                                                  TileGeom tg, float *stats) {
     __shared__ est::Smem<TB> sm;
     est::estimate_tile<S, TB>(v, p, tg, xcd_remap(blockIdx.x, gridDim.x), stats, sm, nullptr);
+}
+
+template <typename S>
+__global__ __launch_bounds__(est::kStripThreads) void k_estimate_strip(BufView<S> v,
+                                                                        est::EstParams p,
+                                                                        TileGeom tg, int sx,
+                                                                        float *stats) {
+    __shared__ est::StripSmem sm;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    est::estimate_strip<S>(v, p, tg, (b % sx) * est::strip_tiles(tg.tile), b / sx, stats, sm);
 }
 
 }  // namespace
@@ -33,13 +44,19 @@ hipError_t launch_estimate(const afr_deep_buffer &buf, const afr_params &prm,
                            const afr_tile_stats &out, hipStream_t st) {
     const est::EstParams p = est_params(buf, prm);
     const TileGeom tg = geom_of(out);
-    const bool small = tg.tile <= 8;  // one wave per tile, scratch for a 10 x 10 halo region
-    if (buf.precision == AFR_FP16) {
-        if (small) k_estimate<__half, 8><<<tg.nt, 64, 0, st>>>(view_of<__half>(buf), p, tg, out.data);
-        else k_estimate<__half, kMaxTile><<<tg.nt, 256, 0, st>>>(view_of<__half>(buf), p, tg, out.data);
+    if (tg.tile <= 8) {  // strips of 64 / tile tiles
+        const int sx = (tg.tiles_x + est::strip_tiles(tg.tile) - 1) / est::strip_tiles(tg.tile);
+        const int grid = sx * tg.tiles_y;
+        if (buf.precision == AFR_FP16)
+            k_estimate_strip<__half><<<grid, est::kStripThreads, 0, st>>>(view_of<__half>(buf), p, tg,
+                                                                         sx, out.data);
+        else
+            k_estimate_strip<float><<<grid, est::kStripThreads, 0, st>>>(view_of<float>(buf), p, tg,
+                                                                        sx, out.data);
+    } else if (buf.precision == AFR_FP16) {
+        k_estimate<__half, kMaxTile><<<tg.nt, 256, 0, st>>>(view_of<__half>(buf), p, tg, out.data);
     } else {
-        if (small) k_estimate<float, 8><<<tg.nt, 64, 0, st>>>(view_of<float>(buf), p, tg, out.data);
-        else k_estimate<float, kMaxTile><<<tg.nt, 256, 0, st>>>(view_of<float>(buf), p, tg, out.data);
+        k_estimate<float, kMaxTile><<<tg.nt, 256, 0, st>>>(view_of<float>(buf), p, tg, out.data);
     }
     return hipGetLastError();
 }

@@ -1,14 +1,20 @@
-// Per-tile statistics (Sec. 4, 4.1, 5.1) as a device routine shared by afr_estimate_gradients and the
-// batched persistent kernel: one 64-lane wave evaluates one statistics tile.
+// Per-tile statistics (Sec. 4, 4.1, 5.1): device routines shared by afr_estimate_gradients and the
+// batched persistent kernel.
 //
-// Phase 1 visits every pixel of the tile and its one-pixel halo once, reading the pixel's slots a
-// single time and accumulating in FP64: the age-weighted mean luminance (needed by the neighbours'
-// spatial differences), the weighted second moment, the new-half / old-half means that give the
-// temporal difference quotient, and the age sum. Results go to LDS. Phase 2 gives each tile pixel
-// its spatial gradients from the LDS neighbours and folds all per-pixel terms into one accumulator
-// per lane; lanes are combined by a fixed-shape butterfly within the wave and in wave order across
-// waves, so the statistics are deterministic. Luminance variance merges per-pixel (weight, mean, M2)
-// triples with the pairwise form of Welford's update.
+// Phase 1 visits every pixel of a region (tiles plus a one-pixel halo) once, reading the pixel's
+// slots a single time in rank order and accumulating in FP64: the age-weighted mean luminance
+// (needed by the neighbours' spatial differences), the weighted second moment, the new-half /
+// old-half means that give the temporal difference quotient, and the age sum. Results go to LDS.
+// Phase 2 gives each tile pixel its spatial gradients from the LDS neighbours and folds all
+// per-pixel terms of a tile into one accumulator per lane (pixel e on lane e mod 64); lanes are
+// combined by a fixed-shape butterfly within the wave and in wave order across waves. Luminance
+// variance merges per-pixel (weight, mean, M2) triples with the pairwise form of Welford's update.
+//
+// Two drivers share these routines: a strip kernel (afr_estimate_gradients, tiles of edge <= 8)
+// where a workgroup covers a 64-pixel-wide strip of tiles, so that each wave reads whole image rows
+// per slot plane, and a per-tile routine (tiles up to 16 px, and the batched kernel). Floating-point
+// contraction is off in every routine here, so a pixel's moments and a tile's reduction round the
+// same way in either driver and the statistics are identical bit for bit.
 //
 // FP64 here is a precision choice: spatial gradients are differences of neighbouring means, and in
 // flat regions FP32 rounding of those means would move the filter widths by ~1e-4 relative. The
@@ -35,6 +41,7 @@ struct Acc {
 __device__ inline Acc acc_zero() { return Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; }
 
 __device__ inline Acc acc_combine(const Acc &a, const Acc &b) {
+#pragma clang fp contract(off)
     Acc c;
     c.gx = a.gx + b.gx;
     c.wx = a.wx + b.wx;
@@ -82,6 +89,7 @@ __device__ inline Acc acc_shfl_xor(const Acc &a, int m) {
 // Filter extents from tile gradients and volume; see afr_estimate_gradients in afr.h.
 __device__ inline void extents(double gx, double gy, double gt, double vol, const EstParams &p,
                                double &ex2, double &ey2, double &sx2, double &sy2, double &kt2) {
+#pragma clang fp contract(off)
     const double hx = sqrt(gx * gx + p.g_floor * p.g_floor);
     const double hy = sqrt(gy * gy + p.g_floor * p.g_floor);
     const double u = p.tau * gt;
@@ -106,156 +114,108 @@ __device__ inline void extents(double gx, double gy, double gt, double vol, cons
     }
 }
 
-// LDS scratch of one tile evaluation for tiles of edge <= TB (the tile and its one-pixel halo).
-template <int TB>
-struct Smem {
-    static constexpr int kHalo = (TB + 2) * (TB + 2);
-    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
-    int n[kHalo];
-    Acc wave[256 / kWave];
+// ---- per-pixel moments (phase 1) ---------------------------------------------------------------
+
+struct PixAcc {
+    double s0, s1, s2, ln, lo, an, ao, sa;
 };
 
-// Evaluates tile T (edge tg.tile <= TB) with the calling workgroup (blockDim.x threads, a multiple
-// of 64, <= 256, with 2 * blockDim.x >= (tile + 2)^2) and writes its statistics. If tparams is not NULL, thread 0 also stores (sx2, sy2, kt2) there (LDS),
-// visible to the workgroup after the caller's next barrier.
-template <typename S, int TB>
-__device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int T,
-                              float *stats, Smem<TB> &sm, float *tparams) {
-    double *s_lbar = sm.lbar, *s_om = sm.om, *s_gt = sm.gt, *s_sa = sm.sa, *s_m2 = sm.m2;
-    int *s_n = sm.n;
-    Acc *s_wave = sm.wave;
-    const int B = tg.tile;
-    const int i0 = (T % tg.tiles_x) * B, j0 = (T / tg.tiles_x) * B;
-    const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
-    const int rw = bw + 2, rh = bh + 2;
-    const size_t hw = (size_t)v.width * v.height;
+__device__ inline PixAcc pix_zero() { return PixAcc{0, 0, 0, 0, 0, 0, 0, 0}; }
 
-    // Phase 1: per-pixel moments over the tile and its one-pixel halo. Each lane takes up to
-    // kItems pixels of the region; the slot planes are visited in chunks of kChunk, and every load
-    // of a chunk (all items, all planes of the chunk) is issued before any of them is used, so a
-    // lane waits for memory once per chunk instead of once per slot. Per pixel the slots are still
-    // added in rank order, so the sums do not depend on the chunking.
-    constexpr int kItems = 2, kChunk = 8;
-    const int nh = rw * rh;
-    int px_[kItems], n_[kItems];
-    int kmax = 0;
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int h = threadIdx.x + it * blockDim.x;
-        const int x = i0 - 1 + h % rw, y = j0 - 1 + h / rw;
-        const bool live = h < nh && x >= 0 && x < v.width && y >= 0 && y < v.height;
-        px_[it] = live ? y * v.width + x : 0;
-        n_[it] = live ? v.count[px_[it]] : 0;
-        kmax = max(kmax, n_[it]);
+// Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta.
+template <typename S>
+__device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S ta, int k, int n) {
+#pragma clang fp contract(off)
+    const double L = kLumR * (double)Codec<S>::dec(r) + kLumG * (double)Codec<S>::dec(g) +
+                     kLumB * (double)Codec<S>::dec(b);
+    const double a = Codec<S>::age64(ta, p.t_now, p.dt_ref);
+    const double w = (double)expf((float)(-p.alpha * a));
+    m.s0 += w;
+    m.s1 += w * L;
+    m.s2 += w * L * L;
+    m.sa += a;
+    if (k < (n + 1) / 2) {
+        m.ln += L;
+        m.an += a;
+    } else {
+        m.lo += L;
+        m.ao += a;
     }
-    for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
-    const size_t bytes = hw * sizeof(S);
-    double s0[kItems], s1[kItems], s2[kItems], ln[kItems], lo[kItems], an[kItems], ao[kItems],
-        sa_[kItems];
-#pragma unroll
-    for (int it = 0; it < kItems; ++it)
-        s0[it] = s1[it] = s2[it] = ln[it] = lo[it] = an[it] = ao[it] = sa_[it] = 0.0;
-    for (int k0 = 0; k0 < kmax; k0 += kChunk) {
-        S cr[kChunk][kItems], cg[kChunk][kItems], cb[kChunk][kItems], ct[kChunk][kItems];
-#pragma unroll
-        for (int j = 0; j < kChunk; ++j) {
-            const int k = min(k0 + j, v.k - 1);  // planes past K are never used
-            const size_t base = (size_t)k * hw;
-            const auto rr = plane_rsrc(v.r + base, bytes), rg = plane_rsrc(v.g + base, bytes);
-            const auto rb = plane_rsrc(v.b + base, bytes), rt = plane_rsrc(v.ta + base, bytes);
-#pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
-                cr[j][it] = plane_load<S>(rr, off);
-                cg[j][it] = plane_load<S>(rg, off);
-                cb[j][it] = plane_load<S>(rb, off);
-                ct[j][it] = plane_load<S>(rt, off);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kChunk; ++j) {
-            const int k = k0 + j;
-#pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                if (k < n_[it]) {
-                    const double L = kLumR * (double)Codec<S>::dec(cr[j][it]) +
-                                     kLumG * (double)Codec<S>::dec(cg[j][it]) +
-                                     kLumB * (double)Codec<S>::dec(cb[j][it]);
-                    const double a = Codec<S>::age64(ct[j][it], p.t_now, p.dt_ref);
-                    const double w = (double)expf((float)(-p.alpha * a));
-                    s0[it] += w;
-                    s1[it] += w * L;
-                    s2[it] += w * L * L;
-                    sa_[it] += a;
-                    if (k < (n_[it] + 1) / 2) {
-                        ln[it] += L;
-                        an[it] += a;
-                    } else {
-                        lo[it] += L;
-                        ao[it] += a;
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int h = threadIdx.x + it * blockDim.x;
-        if (h >= nh) continue;
-        const int n = n_[it];
-        double om = 0.0, lb = 0.0, gt = -1.0, m2 = 0.0;
-        if (n > 0) {
-            om = s0[it];
-            lb = s1[it] / s0[it];
-            m2 = fmax(s2[it] - s1[it] * lb, 0.0);
-        }
-        if (n >= 2) {
-            const int half = (n + 1) / 2;
-            const double dn = half, dd = n - half;
-            gt = fabs(ln[it] / dn - lo[it] / dd) / fmax(ao[it] / dd - an[it] / dn, p.dt_floor);
-        }
-        s_n[h] = n;
-        s_om[h] = om;
-        s_lbar[h] = lb;
-        s_gt[h] = gt;
-        s_sa[h] = sa_[it];
-        s_m2[h] = m2;
-    }
-    __syncthreads();
+}
 
-    // Phase 2: per tile pixel, spatial gradients from LDS neighbours, then fold into Acc.
+// Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum, M2)
+// in LDS, row-major with a given pitch.
+struct Region {
+    double *lbar, *om, *gt, *sa, *m2;
+    int *n;
+};
+
+__device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n, double dt_floor) {
+#pragma clang fp contract(off)
+    double om = 0.0, lb = 0.0, gt = -1.0, m2 = 0.0;
+    if (n > 0) {
+        om = m.s0;
+        lb = m.s1 / m.s0;
+        m2 = fmax(m.s2 - m.s1 * lb, 0.0);
+    }
+    if (n >= 2) {
+        const int half = (n + 1) / 2;
+        const double dn = half, dd = n - half;
+        gt = fabs(m.ln / dn - m.lo / dd) / fmax(m.ao / dd - m.an / dn, dt_floor);
+    }
+    rg.n[h] = n;
+    rg.om[h] = om;
+    rg.lbar[h] = lb;
+    rg.gt[h] = gt;
+    rg.sa[h] = m.sa;
+    rg.m2[h] = m2;
+}
+
+// ---- per-tile reduction (phase 2) ---------------------------------------------------------------
+
+// Accumulator of region pixel h (pitch rp) with its spatial gradients from the four neighbours.
+__device__ inline Acc pixel_acc(const Region &rg, int h, int rp) {
+#pragma clang fp contract(off)
+    Acc a = acc_zero();
+    const int n = rg.n[h];
+    if (n == 0) return a;
+    const double lb = rg.lbar[h], om = rg.om[h];
+    double sx = 0.0, sy = 0.0;
+    int nx = 0, ny = 0;
+    if (rg.n[h - 1]) { sx += fabs(lb - rg.lbar[h - 1]); ++nx; }
+    if (rg.n[h + 1]) { sx += fabs(lb - rg.lbar[h + 1]); ++nx; }
+    if (rg.n[h - rp]) { sy += fabs(lb - rg.lbar[h - rp]); ++ny; }
+    if (rg.n[h + rp]) { sy += fabs(lb - rg.lbar[h + rp]); ++ny; }
+    if (nx) { a.gx = om * (sx / nx); a.wx = om; }
+    if (ny) { a.gy = om * (sy / ny); a.wy = om; }
+    if (rg.gt[h] >= 0.0) { a.gt = om * rg.gt[h]; a.wt = om; }
+    a.n = n;
+    a.sa = rg.sa[h];
+    a.w = om;
+    a.mean = lb;
+    a.m2 = rg.m2[h];
+    return a;
+}
+
+// Folds the pixels e = lane, lane + 64, ... of a bw x bh tile whose top-left region pixel is h0
+// into one accumulator per lane, then butterflies them across the wave (every lane ends with the
+// wave's sum).
+__device__ inline Acc wave_tile_acc(const Region &rg, int h0, int rp, int bw, int bh, int lane,
+                                    int stride) {
+#pragma clang fp contract(off)
     Acc acc = acc_zero();
-    for (int e = threadIdx.x; e < bw * bh; e += blockDim.x) {
-        const int h = (e / bw + 1) * rw + (e % bw + 1);
-        const int n = s_n[h];
-        if (n == 0) continue;
-        const double lb = s_lbar[h], om = s_om[h];
-        double sx = 0.0, sy = 0.0;
-        int nx = 0, ny = 0;
-        if (s_n[h - 1]) { sx += fabs(lb - s_lbar[h - 1]); ++nx; }
-        if (s_n[h + 1]) { sx += fabs(lb - s_lbar[h + 1]); ++nx; }
-        if (s_n[h - rw]) { sy += fabs(lb - s_lbar[h - rw]); ++ny; }
-        if (s_n[h + rw]) { sy += fabs(lb - s_lbar[h + rw]); ++ny; }
-        Acc a = acc_zero();
-        if (nx) { a.gx = om * (sx / nx); a.wx = om; }
-        if (ny) { a.gy = om * (sy / ny); a.wy = om; }
-        if (s_gt[h] >= 0.0) { a.gt = om * s_gt[h]; a.wt = om; }
-        a.n = n;
-        a.sa = s_sa[h];
-        a.w = om;
-        a.mean = lb;
-        a.m2 = s_m2[h];
-        acc = acc_combine(acc, a);
-    }
+    for (int e = lane; e < bw * bh; e += stride)
+        acc = acc_combine(acc, pixel_acc(rg, h0 + (e / bw) * rp + e % bw, rp));
 #pragma unroll
     for (int m = kWave / 2; m > 0; m >>= 1) acc = acc_combine(acc, acc_shfl_xor(acc, m));
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (lane == 0) s_wave[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-    Acc t = s_wave[0];
-    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) t = acc_combine(t, s_wave[w]);
+    return acc;
+}
 
+// Tile statistics from the tile's accumulator; writes the stats planes and, if tparams is not NULL,
+// (sx2, sy2, kt2) to tparams.
+__device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileGeom &tg, int T,
+                                   int bw, int bh, float *stats, float *tparams) {
+#pragma clang fp contract(off)
     const double gx = t.wx > 0.0 ? t.gx / t.wx : 0.0;
     const double gy = t.wy > 0.0 ? t.gy / t.wy : 0.0;
     const double gt = t.wt > 0.0 ? t.gt / t.wt : 0.0;
@@ -282,8 +242,135 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
         tparams[1] = (float)sy2;
         tparams[2] = (float)kt2;
     }
+}
+
+// Phase 1 over the region pixels h = threadIdx.x + it * blockDim.x (it < ITEMS, h < nh) of a region
+// with origin (x0, y0) and pitch rp: the slot planes are visited in chunks of KC, and every load of
+// a chunk (all items, all planes of the chunk) is issued before any is used, so a lane waits for
+// memory once per chunk. Per pixel the slots are still added in rank order.
+template <typename S, int ITEMS, int KC>
+__device__ inline void region_moments(const BufView<S> &v, const EstParams &p, const Region &rg,
+                                      int x0, int y0, int rp, int nh) {
+    const size_t hw = (size_t)v.width * v.height;
+    int px_[ITEMS], n_[ITEMS];
+    int kmax = 0;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int h = threadIdx.x + it * blockDim.x;
+        const int x = x0 + h % rp, y = y0 + h / rp;
+        const bool live = h < nh && x >= 0 && x < v.width && y >= 0 && y < v.height;
+        px_[it] = live ? y * v.width + x : 0;
+        n_[it] = live ? v.count[px_[it]] : 0;
+        kmax = max(kmax, n_[it]);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+    const size_t bytes = hw * sizeof(S);
+    PixAcc m[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) m[it] = pix_zero();
+    for (int k0 = 0; k0 < kmax; k0 += KC) {
+        S cr[KC][ITEMS], cg[KC][ITEMS], cb[KC][ITEMS], ct[KC][ITEMS];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = min(k0 + j, v.k - 1);  // planes past K are never used
+            const size_t base = (size_t)k * hw;
+            const auto rr = plane_rsrc(v.r + base, bytes), rg_ = plane_rsrc(v.g + base, bytes);
+            const auto rb = plane_rsrc(v.b + base, bytes), rt = plane_rsrc(v.ta + base, bytes);
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
+                cr[j][it] = plane_load<S>(rr, off);
+                cg[j][it] = plane_load<S>(rg_, off);
+                cb[j][it] = plane_load<S>(rb, off);
+                ct[j][it] = plane_load<S>(rt, off);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (k0 + j < n_[it])
+                    pix_add<S>(m[it], p, cr[j][it], cg[j][it], cb[j][it], ct[j][it], k0 + j, n_[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int h = threadIdx.x + it * blockDim.x;
+        if (h < nh) pix_store(rg, h, m[it], n_[it], p.dt_floor);
+    }
+}
+
+// ---- per-tile driver ----------------------------------------------------------------------------
+
+// LDS scratch of one tile evaluation for tiles of edge <= TB (the tile and its one-pixel halo).
+template <int TB>
+struct Smem {
+    static constexpr int kHalo = (TB + 2) * (TB + 2);
+    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
+    int n[kHalo];
+    Acc wave[256 / kWave];
+};
+
+// Evaluates tile T (edge tg.tile <= TB) with the calling workgroup (blockDim.x threads, a multiple
+// of 64, <= 256, with 2 * blockDim.x >= (tile + 2)^2) and writes its statistics. If tparams is not
+// NULL, thread 0 also stores (sx2, sy2, kt2) there (LDS), visible to the workgroup after the
+// caller's next barrier.
+template <typename S, int TB>
+__device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int T,
+                              float *stats, Smem<TB> &sm, float *tparams) {
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
+    const int B = tg.tile;
+    const int i0 = (T % tg.tiles_x) * B, j0 = (T / tg.tiles_x) * B;
+    const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
+    const int rw = bw + 2, rh = bh + 2;
+    region_moments<S, 2, 8>(v, p, rg, i0 - 1, j0 - 1, rw, rw * rh);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const Acc acc = wave_tile_acc(rg, rw + 1, rw, bw, bh, threadIdx.x, blockDim.x);
+    if (lane == 0) sm.wave[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc t = sm.wave[0];
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) t = acc_combine(t, sm.wave[w]);
+        tile_finish(t, p, tg, T, bw, bh, stats, tparams);
     }
     __syncthreads();  // the LDS scratch may be reused by the caller after this point
+}
+
+// ---- strip driver (tiles of edge <= 8) ----------------------------------------------------------
+
+constexpr int kStripThreads = 256;
+constexpr int kStripW = 64;                                  // pixels
+constexpr int kStripRegion = (kStripW + 2) * (8 + 2);        // region pixels, at most 660
+constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
+
+struct StripSmem {
+    double lbar[kStripRegion], om[kStripRegion], gt[kStripRegion], sa[kStripRegion],
+        m2[kStripRegion];
+    int n[kStripRegion];
+};
+
+// Tiles per strip and strips per tile row for tile edge B <= 8.
+__host__ __device__ inline int strip_tiles(int B) { return kStripW / B; }
+
+// Evaluates the tiles tx0 .. tx0 + strip_tiles(B) - 1 of tile row ty with a 256-thread workgroup.
+// Each tile is reduced by one wave in the per-tile routine's order (pixel e on lane e).
+template <typename S>
+__device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int tx0,
+                               int ty, float *stats, StripSmem &sm) {
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
+    const int B = tg.tile;
+    const int ntile = min(strip_tiles(B), tg.tiles_x - tx0);
+    const int i0 = tx0 * B, j0 = ty * B;
+    const int sw = min(ntile * B, v.width - i0), sh = min(B, v.height - j0);
+    const int rp = sw + 2;
+    region_moments<S, kStripItems, 4>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int t = wid; t < ntile; t += kStripThreads / kWave) {
+        const int bw = min(B, v.width - (i0 + t * B)), bh = sh;
+        const Acc acc = wave_tile_acc(rg, rp + 1 + t * B, rp, bw, bh, lane, kWave);
+        if (lane == 0) tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats, nullptr);
+    }
 }
 
 }  // namespace est
