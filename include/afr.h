@@ -218,9 +218,9 @@ afr_status afr_reconstruct_tune(const afr_deep_buffer *buf, const afr_tile_stats
  *   grad_rgb   [3][H][W] dl/dC
  *   grad_slot  [3][K][H][W] float output (empty slots get 0)
  *   grad_params 2 floats, device
- *   ws         at least afr_backward_workspace_bytes(width, height) bytes
+ *   ws         at least afr_backward_workspace_bytes(width, height, k, radius) bytes
  * ------------------------------------------------------------------------------------------- */
-size_t afr_backward_workspace_bytes(int32_t width, int32_t height);
+size_t afr_backward_workspace_bytes(int32_t width, int32_t height, int32_t k, int32_t radius);
 afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_stats *stats,
                                     const afr_params *params, const float *rgb, const float *aux,
                                     const float *grad_rgb, float *grad_slot, float *grad_params,

@@ -128,7 +128,7 @@ def library():
     lib.afr_reconstruct_launch.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), ctypes.c_int32,
                                            vp, vp, vp]
     lib.afr_backward_workspace_bytes.restype = ctypes.c_size_t
-    lib.afr_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.afr_backward_workspace_bytes.argtypes = [ctypes.c_int32] * 4
     lib.afr_reconstruct_backward.restype = st
     lib.afr_reconstruct_backward.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp, vp, vp,
                                              vp, vp, vp, ctypes.c_size_t, vp]
@@ -443,7 +443,7 @@ def reconstruct_backward(buf: DeepBuffer, stats: torch.Tensor, params: Params, r
         grad_slot = torch.empty((3, buf.k, buf.height, buf.width), dtype=torch.float32, device=dev)
     if grad_params is None:
         grad_params = torch.empty(2, dtype=torch.float32, device=dev)
-    wsb = lib.afr_backward_workspace_bytes(buf.width, buf.height)
+    wsb = lib.afr_backward_workspace_bytes(buf.width, buf.height, buf.k, params.radius)
     ws = _workspace(wsb, dev, "backward")
     bc, pc, sc = buf._c(colours), params._c(), _stats_c(stats, params.tile)
     grad_rgb = grad_rgb.contiguous().float()

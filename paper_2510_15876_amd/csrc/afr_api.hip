@@ -158,9 +158,9 @@ afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stat
     return from_hip(launch_reconstruct_plain(*buf, *stats, *params, rgb, aux, stream));
 }
 
-size_t afr_backward_workspace_bytes(int32_t width, int32_t height) {
-    if (width < 1 || height < 1) return 0;
-    return backward_ws_bytes(width, height);
+size_t afr_backward_workspace_bytes(int32_t width, int32_t height, int32_t k, int32_t radius) {
+    if (width < 1 || height < 1 || k < 1 || k > 255 || radius < 0 || radius > kMaxRadius) return 0;
+    return backward_ws_bytes(width, height, k, radius);
 }
 
 afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_stats *stats,
@@ -172,7 +172,8 @@ afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_s
     AFR_TRY(check_stats(stats, buf, params));
     if (!(params->tau > 0.0f)) return AFR_E_RANGE;
     if (!rgb || !aux || !grad_rgb || !grad_slot || !grad_params || !ws) return AFR_E_INVALID;
-    if (ws_bytes < backward_ws_bytes(buf->width, buf->height)) return AFR_E_NOMEM;
+    if (ws_bytes < backward_ws_bytes(buf->width, buf->height, buf->k, params->radius))
+        return AFR_E_NOMEM;
     return from_hip(launch_backward(*buf, *stats, *params, rgb, aux, grad_rgb, grad_slot,
                                     grad_params, ws, stream));
 }

@@ -5,10 +5,29 @@
 //   colour gradient   dl/dc_{s,ch} = sum_p g(p,ch) pi_s(p)
 //   filter parameters dl/dtheta    = sum_p sum_s pi_s(p) h_s(p) dE_s(p)/dtheta,
 //                     h_s(p) = sum_ch g(p,ch) (c_{s,ch} - C_{p,ch})
-// Pass 1 (k_bwd_pixel) is pixel-parallel: it stores g/W per pixel and reduces the parameter terms
-// per workgroup in FP64. Pass 2 (k_bwd_sample) is slot-parallel: each slot gathers from the pixels
-// whose block contains it, so no atomics are needed. Pass 3 sums the workgroup partials in a fixed
-// order. Per-pair weights are recomputed from the buffer, never stored.
+// Per-pair weights are recomputed from the buffer, never stored, and nothing uses floating-point
+// atomics: every sum runs in a fixed order.
+//
+// Tiled form (8 px statistics tiles, the layout of the tiled gather). The weight of slot s for pixel
+// p of tile T factors as X_T(s, m) Y_T(s, n) Tm_T(s) (see afr_tile_gather.h), and with
+//   s_p = exp(shift_T - m_p) / W_p,  g'_p = g(p, .) s_p,  k'_p = (g(p, .) . C_p) s_p
+// the two sums become, per pair, w = X Y Tm:
+//   colour gradient of s += w g'_p,    parameter terms += w (g'_p . c_s - k'_p) dE/dtheta,
+// where dE/dtheta is dx^2 and dy^2 times per-tile coefficients plus a^2 times one (for tau).
+//   k_bwd_prep   per tile: the tile's shift (the gather's: smallest slot-0 age of the region),
+//                g'_p and k'_p per pixel. A pixel the forward had to evaluate directly (its shifted
+//                weights underflow: shift_T - m_p > 60) is flagged and its parameter terms are
+//                computed exactly here.
+//   k_bwd_tile   per tile: each lane owns source slots of the tile's region, evaluates their factors
+//                once per plane and visits the tile pixels in reach; it writes the slot's colour-
+//                gradient partial for this tile and folds the parameter terms per lane.
+//   k_bwd_slots  per slot: adds the partials of the (at most four) tiles whose region holds it, in
+//                tile order, plus exact terms from flagged pixels in reach.
+//   k_reduce_params  sums the per-tile parameter partials in tile order.
+// Other tile sizes use the direct form: k_bwd_pixel (pixel-parallel: g/W per pixel and the
+// parameter terms) and k_bwd_sample (slot-parallel gather of the colour gradients).
+#include <algorithm>
+
 #include "afr_internal.h"
 
 namespace afr {
@@ -181,11 +200,399 @@ __global__ __launch_bounds__(kBX *kBY) void k_bwd_sample(BufView<S> v, BwdParams
     }
 }
 
+// ---- tiled adjoint (8 px statistics tiles) -------------------------------------------------------
+
+constexpr int kTB = 8;                  // statistics tile edge of the tiled form
+constexpr float kLog2eB = 1.4426950408889634f;
+constexpr float kDirectExp = 60.0f;     // shift - m beyond which a pixel is evaluated directly
+
+template <int R>
+struct RegionGeom {
+    static constexpr int RW = kTB + 2 * R, NP = RW * RW, NM = 2 * R + 1;
+    static constexpr int ITEMS = (NP + kWave - 1) / kWave;
+};
+
+struct TiledWs {
+    float4 *gk;           // [H][W] (g'_0, g'_1, g'_2, k'); zero for excluded pixels
+    unsigned char *flag;  // [H][W] 1 where the pixel is evaluated directly
+    float *amin;          // [nt] the tile's age reference (smallest slot-0 age of its region)
+    int *nflag;           // [nt] flagged pixels of the tile
+    double *pp;           // [2 nt][2] parameter partials: prep (flagged pixels), then tile
+    float *part;          // [nt][K][3][NP] colour-gradient partials of each tile's region slots
+};
+
+template <int R>
+size_t tiled_ws_bytes(int32_t w, int32_t h, int32_t k) {
+    const size_t hw = (size_t)w * h;
+    const size_t nt = (size_t)((w + kTB - 1) / kTB) * ((h + kTB - 1) / kTB);
+    return align_up(hw * sizeof(float4)) + align_up(hw) + align_up(nt * 4) + align_up(nt * 4) +
+           align_up(nt * 4 * 8) + align_up(nt * (size_t)k * 3 * RegionGeom<R>::NP * 4);
+}
+
+size_t tiled_ws_bytes_r(int32_t w, int32_t h, int32_t k, int r) {
+    switch (r) {
+        case 0: return tiled_ws_bytes<0>(w, h, k);
+        case 1: return tiled_ws_bytes<1>(w, h, k);
+        case 2: return tiled_ws_bytes<2>(w, h, k);
+        case 3: return tiled_ws_bytes<3>(w, h, k);
+        default: return tiled_ws_bytes<4>(w, h, k);
+    }
+}
+
+template <int R>
+TiledWs tiled_ws_carve(void *ws, int32_t w, int32_t h, int32_t k) {
+    const size_t hw = (size_t)w * h;
+    const size_t nt = (size_t)((w + kTB - 1) / kTB) * ((h + kTB - 1) / kTB);
+    char *p = static_cast<char *>(ws);
+    TiledWs o;
+    o.gk = reinterpret_cast<float4 *>(p);
+    p += align_up(hw * sizeof(float4));
+    o.flag = reinterpret_cast<unsigned char *>(p);
+    p += align_up(hw);
+    o.amin = reinterpret_cast<float *>(p);
+    p += align_up(nt * 4);
+    o.nflag = reinterpret_cast<int *>(p);
+    p += align_up(nt * 4);
+    o.pp = reinterpret_cast<double *>(p);
+    p += align_up(nt * 4 * 8);
+    o.part = reinterpret_cast<float *>(p);
+    return o;
+}
+
+__device__ inline float wave_min_f(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Exact parameter terms of pixel (i, j) (the direct form), accumulated in float per pixel.
+template <typename S>
+__device__ inline void direct_param_terms(const BufView<S> &v, const BwdParams &p, const TileCoef &c,
+                                          int i, int j, float m, float inv, float g0, float g1,
+                                          float g2, float C0, float C1, float C2, double &d_sig,
+                                          double &d_tau) {
+    const int W = v.width, H = v.height, R = p.radius;
+    const size_t hw = (size_t)W * H;
+    float ax = 0.0f, ay = 0.0f, at = 0.0f;
+    const int qx0 = max(0, i - R), qx1 = min(W - 1, i + R);
+    const int qy0 = max(0, j - R), qy1 = min(H - 1, j + R);
+    for (int qy = qy0; qy <= qy1; ++qy)
+        for (int qx = qx0; qx <= qx1; ++qx) {
+            const size_t q = (size_t)qy * W + qx;
+            const int n = v.count[q];
+            const float bx = (float)(qx - i) - 0.5f, by = (float)(qy - j) - 0.5f;
+            for (int k = 0; k < n; ++k) {
+                const size_t s = (size_t)k * hw + q;
+                const float dx = bx + Codec<S>::dec(v.ox[s]);
+                const float dy = by + Codec<S>::dec(v.oy[s]);
+                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float e = -(dx * dx * c.cx + dy * dy * c.cy + a * a * c.ct);
+                const float pi = expf(e - m) * inv;
+                const float h = g0 * (Codec<S>::dec(v.r[s]) - C0) +
+                                g1 * (Codec<S>::dec(v.g[s]) - C1) +
+                                g2 * (Codec<S>::dec(v.b[s]) - C2);
+                const float ph = pi * h;
+                ax += ph * dx * dx;
+                ay += ph * dy * dy;
+                at += ph * a * a;
+            }
+        }
+    d_sig = (double)ax * c.fxs + (double)ay * c.fys;
+    d_tau = (double)ax * c.fxt + (double)ay * c.fyt - (double)at * c.fkt;
+}
+
+template <typename S, int R>
+__global__ __launch_bounds__(kWave) void k_bwd_prep(BufView<S> v, BwdParams p, TileGeom tg,
+                                                    const float *__restrict__ stats,
+                                                    const float *__restrict__ rgb,
+                                                    const float *__restrict__ aux,
+                                                    const float *__restrict__ grad, TiledWs ws) {
+    using G = RegionGeom<R>;
+    const int T = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = T % tg.tiles_x, ty = T / tg.tiles_x;
+    const int W = v.width, H = v.height, lane = threadIdx.x;
+    const size_t hw = (size_t)W * H;
+    const float kt2 = stats[AFR_STAT_KT2 * tg.nt + T];
+    // the gather's age reference: smallest slot-0 age over the tile's source region
+    float amin = INFINITY;
+#pragma unroll
+    for (int it = 0; it < G::ITEMS; ++it) {
+        const int pix = lane + it * kWave;
+        const int qx = tx * kTB - R + pix % G::RW, qy = ty * kTB - R + pix / G::RW;
+        if (pix < G::NP && qx >= 0 && qx < W && qy >= 0 && qy < H) {
+            const size_t q = (size_t)qy * W + qx;
+            if (v.count[q] > 0) amin = fminf(amin, Codec<S>::age(v.ta[q], p.t_now, p.dt_ref));
+        }
+    }
+    amin = wave_min_f(amin);
+    if (amin == INFINITY) amin = 0.0f;
+    const float shift = -(amin * amin) * (0.5f * kt2);
+    const int i = tx * kTB + lane % kTB, j = ty * kTB + lane / kTB;
+    double d_sig = 0.0, d_tau = 0.0;
+    int flagged = 0;
+    if (i < W && j < H) {
+        const size_t px = (size_t)j * W + i;
+        const float m = aux[px], wsum = aux[hw + px];
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        unsigned char f = 0;
+        if (wsum > 0.0f) {
+            const float g0 = grad[px], g1 = grad[hw + px], g2 = grad[2 * hw + px];
+            const float C0 = rgb[px], C1 = rgb[hw + px], C2 = rgb[2 * hw + px];
+            const float e = shift - m;
+            if (e <= kDirectExp) {
+                const float sc = expf(e) / wsum;
+                o = make_float4(g0 * sc, g1 * sc, g2 * sc, (g0 * C0 + g1 * C1 + g2 * C2) * sc);
+            } else {
+                f = 1;
+                flagged = 1;
+                const TileCoef c = tile_coef(stats, tg.nt, T, p);
+                direct_param_terms<S>(v, p, c, i, j, m, 1.0f / wsum, g0, g1, g2, C0, C1, C2, d_sig,
+                                      d_tau);
+            }
+        }
+        ws.gk[px] = o;
+        ws.flag[px] = f;
+    }
+    d_sig = wave_sum_d(d_sig);
+    d_tau = wave_sum_d(d_tau);
+    flagged = wave_sum_i(flagged);
+    if (lane == 0) {
+        ws.amin[T] = amin;
+        ws.nflag[T] = flagged;
+        ws.pp[2 * T] = d_sig;
+        ws.pp[2 * T + 1] = d_tau;
+    }
+}
+
+// One thread per source slot of the tile's region (ITEMS waves per tile). Waves run their own
+// plane loops (no barrier inside); their parameter sums are combined in wave order at the end.
+template <typename S, int R>
+__global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
+    BufView<S> v, BwdParams p, TileGeom tg, const float *__restrict__ stats, TiledWs ws) {
+    using G = RegionGeom<R>;
+    constexpr int RW = G::RW, NP = G::NP, NM = G::NM, NW = G::ITEMS;
+    __shared__ float4 s_gk[kTB * kTB];
+    __shared__ double s_red[2][NW];
+    const int T = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = T % tg.tiles_x, ty = T / tg.tiles_x;
+    const int W = v.width, H = v.height, K = v.k;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const size_t hw = (size_t)W * H;
+    if (tid < kTB * kTB) {
+        const int i = tx * kTB + tid % kTB, j = ty * kTB + tid / kTB;
+        s_gk[tid] = (i < W && j < H) ? ws.gk[(size_t)j * W + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const float sx2 = stats[AFR_STAT_SX2 * tg.nt + T], sy2 = stats[AFR_STAT_SY2 * tg.nt + T];
+    const float kt2 = stats[AFR_STAT_KT2 * tg.nt + T];
+    const float cx2 = kLog2eB * (0.5f / sx2), cy2 = kLog2eB * (0.5f / sy2);
+    const float ct2 = kLog2eB * (0.5f * kt2);
+    const float amin = ws.amin[T];
+    float gxm[NM];
+#pragma unroll
+    for (int m = 0; m < 2 * R; ++m) gxm[m] = __builtin_amdgcn_exp2f(-(float)(2 * (m - R) + 1) * cx2);
+    const int pix = tid;
+    const int rr_ = pix / RW, cc = pix % RW;
+    const int qx = tx * kTB - R + cc, qy = ty * kTB - R + rr_;
+    const bool in = pix < NP && qx >= 0 && qx < W && qy >= 0 && qy < H;
+    const unsigned q = in ? (unsigned)(qy * W + qx) : 0u;
+    const unsigned ioff = q * (unsigned)sizeof(S);
+    const int icnt = in ? v.count[q] : 0;
+    int kmax = icnt;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+    __syncthreads();  // s_gk visible
+    S rox, roy, rta, rr, rg, rb;
+    auto load_plane = [&](int k) {
+        const size_t base = (size_t)k * hw, bytes = hw * sizeof(S);
+        rox = plane_load<S>(plane_rsrc(v.ox + base, bytes), ioff);
+        roy = plane_load<S>(plane_rsrc(v.oy + base, bytes), ioff);
+        rta = plane_load<S>(plane_rsrc(v.ta + base, bytes), ioff);
+        rr = plane_load<S>(plane_rsrc(v.r + base, bytes), ioff);
+        rg = plane_load<S>(plane_rsrc(v.g + base, bytes), ioff);
+        rb = plane_load<S>(plane_rsrc(v.b + base, bytes), ioff);
+    };
+    if (kmax > 0) load_plane(0);
+    float Sx = 0.0f, Sy = 0.0f, Sa = 0.0f;
+    for (int k = 0; k < kmax; ++k) {
+        const bool on = k < icnt;
+        const float dx = on ? Codec<S>::dec(rox) - 0.5f : 0.0f;
+        const float dy = on ? Codec<S>::dec(roy) - 0.5f : 0.0f;
+        const float a = on ? Codec<S>::age(rta, p.t_now, p.dt_ref) : amin;
+        const float cr = on ? Codec<S>::dec(rr) : 0.0f;
+        const float cg = on ? Codec<S>::dec(rg) : 0.0f;
+        const float cb = on ? Codec<S>::dec(rb) : 0.0f;
+        load_plane(min(k + 1, K - 1));  // in flight during this plane's pairs
+        const float tm = on ? __builtin_amdgcn_exp2f(-((a - amin) * (a + amin)) * ct2) : 0.0f;
+        // X for the 2R+1 column offsets (times the temporal factor), kept in registers; the rows
+        // are visited one at a time with Y advanced by its recurrence.
+        float X[NM], dx2[NM];
+        const float ex = dx - (float)R, ey = dy - (float)R;
+        X[0] = __builtin_amdgcn_exp2f(-ex * ex * cx2) * tm;
+        if (R > 0) {
+            const float rhox = __builtin_amdgcn_exp2f(-2.0f * dx * cx2);
+#pragma unroll
+            for (int m = 0; m < 2 * R; ++m) X[m + 1] = X[m] * rhox * gxm[m];
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const float ux = (float)(m - R) + dx;
+            dx2[m] = ux * ux;
+        }
+        const float rhoy = __builtin_amdgcn_exp2f(-2.0f * dy * cy2);
+        float yv = __builtin_amdgcn_exp2f(-ey * ey * cy2);
+        const float a2 = a * a;
+        float gr = 0.0f, gg = 0.0f, gb = 0.0f;
+#pragma unroll 1
+        for (int n = 0; n < NM; ++n) {
+            const int jj = rr_ - n;  // tile-local row of the pixel at row offset n
+            const float uy = (float)(n - R) + dy;
+            const float dyn2 = uy * uy;
+            const bool rok = jj >= 0 && jj < kTB;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const int ii = cc - m;
+                const bool ok = rok && ii >= 0 && ii < kTB;
+                const float w = ok ? X[m] * yv : 0.0f;
+                const float4 g4 = s_gk[ok ? jj * kTB + ii : 0];
+                gr += w * g4.x;
+                gg += w * g4.y;
+                gb += w * g4.z;
+                const float hwt = w * (g4.x * cr + g4.y * cg + g4.z * cb - g4.w);
+                Sx += hwt * dx2[m];
+                Sy += hwt * dyn2;
+                Sa += hwt * a2;
+            }
+            // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2)
+            yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
+        }
+        if (on) {
+            float *pt = ws.part + ((size_t)T * K + k) * 3 * NP + pix;
+            pt[0] = gr;
+            pt[NP] = gg;
+            pt[2 * NP] = gb;
+        }
+    }
+    const TileCoef c = tile_coef(stats, tg.nt, T, p);
+    double d_sig = (double)Sx * c.fxs + (double)Sy * c.fys;
+    double d_tau = (double)Sx * c.fxt + (double)Sy * c.fyt - (double)Sa * c.fkt;
+    d_sig = wave_sum_d(d_sig);
+    d_tau = wave_sum_d(d_tau);
+    if (lane == 0) {
+        s_red[0][wid] = d_sig;
+        s_red[1][wid] = d_tau;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            a += s_red[0][w];
+            b += s_red[1][w];
+        }
+        ws.pp[2 * (tg.nt + T)] = a;
+        ws.pp[2 * (tg.nt + T) + 1] = b;
+    }
+}
+
+template <typename S, int R>
+__global__ __launch_bounds__(kBX *kBY) void k_bwd_slots(BufView<S> v, BwdParams p, TileGeom tg,
+                                                        const float *__restrict__ stats,
+                                                        const float *__restrict__ aux,
+                                                        const float *__restrict__ grad,
+                                                        TiledWs ws, float *__restrict__ gslot) {
+    using G = RegionGeom<R>;
+    constexpr int RW = G::RW, NP = G::NP;
+    const int qx = blockIdx.x * kBX + threadIdx.x;
+    const int qy = blockIdx.y * kBY + threadIdx.y;
+    const int W = v.width, H = v.height, K = v.k;
+    if (qx >= W || qy >= H) return;
+    const size_t hw = (size_t)W * H, hwk = hw * K;
+    const size_t q = (size_t)qy * W + qx;
+    const int n = v.count[q];
+    // tiles whose source region holds q, in tile order, and whether any has flagged pixels
+    int tl[4], off[4], nt_ = 0;
+    bool anyflag = false;
+    const int tqx = qx / kTB, tqy = qy / kTB;
+    for (int yy = max(0, tqy - 1); yy <= min(tg.tiles_y - 1, tqy + 1); ++yy)
+        for (int xx = max(0, tqx - 1); xx <= min(tg.tiles_x - 1, tqx + 1); ++xx) {
+            const int rx = qx - (xx * kTB - R), ry = qy - (yy * kTB - R);
+            if (rx >= 0 && rx < RW && ry >= 0 && ry < RW && nt_ < 4) {
+                tl[nt_] = yy * tg.tiles_x + xx;
+                off[nt_] = ry * RW + rx;
+                anyflag = anyflag || ws.nflag[tl[nt_]] > 0;
+                ++nt_;
+            }
+        }
+    for (int k = 0; k < K; ++k) {
+        const size_t s = (size_t)k * hw + q;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        if (k < n) {
+            for (int t = 0; t < nt_; ++t) {
+                const float *pt = ws.part + ((size_t)tl[t] * K + k) * 3 * NP + off[t];
+                s0 += pt[0];
+                s1 += pt[NP];
+                s2 += pt[2 * NP];
+            }
+            if (anyflag) {  // exact terms from pixels evaluated directly
+                const float ox = Codec<S>::dec(v.ox[s]), oy = Codec<S>::dec(v.oy[s]);
+                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                for (int py = max(0, qy - R); py <= min(H - 1, qy + R); ++py)
+                    for (int px = max(0, qx - R); px <= min(W - 1, qx + R); ++px) {
+                        const size_t pp = (size_t)py * W + px;
+                        if (!ws.flag[pp]) continue;
+                        const int T = (py / kTB) * tg.tiles_x + px / kTB;
+                        const float cx = 0.5f / stats[AFR_STAT_SX2 * tg.nt + T];
+                        const float cy = 0.5f / stats[AFR_STAT_SY2 * tg.nt + T];
+                        const float ct = 0.5f * stats[AFR_STAT_KT2 * tg.nt + T];
+                        const float dx = ((float)(qx - px) - 0.5f) + ox;
+                        const float dy = ((float)(qy - py) - 0.5f) + oy;
+                        const float e = -(dx * dx * cx + dy * dy * cy + a * a * ct);
+                        const float w = expf(e - aux[pp]) / aux[hw + pp];
+                        s0 += grad[pp] * w;
+                        s1 += grad[hw + pp] * w;
+                        s2 += grad[2 * hw + pp] * w;
+                    }
+            }
+        }
+        gslot[s] = s0;
+        gslot[hwk + s] = s1;
+        gslot[2 * hwk + s] = s2;
+    }
+}
+
+// Sums nb (sigma, tau) partials in a fixed order: thread t adds entries t, t + 256, ... in index
+// order (loads issued eight at a time), then a fixed tree over the threads.
 __global__ __launch_bounds__(256) void k_reduce_params(const double *__restrict__ partial, int nb,
                                                        float *__restrict__ out) {
     __shared__ double s[2][256];
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) {
+    constexpr int kU = 8;
+    int i = threadIdx.x;
+    for (; i + (kU - 1) * 256 < nb; i += kU * 256) {
+        double va[kU], vb[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            va[u] = partial[2 * (i + u * 256)];
+            vb[u] = partial[2 * (i + u * 256) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            a += va[u];
+            b += vb[u];
+        }
+    }
+    for (; i < nb; i += 256) {
         a += partial[2 * i];
         b += partial[2 * i + 1];
     }
@@ -224,12 +631,43 @@ hipError_t launch_bwd_typed(const afr_deep_buffer &buf, const afr_tile_stats &st
     return hipGetLastError();
 }
 
+template <typename S, int R>
+hipError_t launch_bwd_tiled(const afr_deep_buffer &buf, const afr_tile_stats &stats,
+                            const BwdParams &p, const float *rgb, const float *aux,
+                            const float *grad, float *gslot, float *gparams, void *ws,
+                            hipStream_t st) {
+    const BufView<S> v = view_of<S>(buf);
+    const TileGeom tg = geom_of(stats);
+    const TiledWs w = tiled_ws_carve<R>(ws, buf.width, buf.height, buf.k);
+    k_bwd_prep<S, R><<<tg.nt, kWave, 0, st>>>(v, p, tg, stats.data, rgb, aux, grad, w);
+    k_bwd_tile<S, R><<<tg.nt, RegionGeom<R>::ITEMS * kWave, 0, st>>>(v, p, tg, stats.data, w);
+    k_bwd_slots<S, R><<<pixel_grid(buf.width, buf.height), dim3(kBX, kBY), 0, st>>>(
+        v, p, tg, stats.data, aux, grad, w, gslot);
+    k_reduce_params<<<1, 256, 0, st>>>(w.pp, 2 * tg.nt, gparams);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_bwd_tiled_r(const afr_deep_buffer &buf, const afr_tile_stats &stats,
+                              const BwdParams &p, const float *rgb, const float *aux,
+                              const float *grad, float *gslot, float *gparams, void *ws,
+                              hipStream_t st) {
+    switch (p.radius) {
+        case 0: return launch_bwd_tiled<S, 0>(buf, stats, p, rgb, aux, grad, gslot, gparams, ws, st);
+        case 1: return launch_bwd_tiled<S, 1>(buf, stats, p, rgb, aux, grad, gslot, gparams, ws, st);
+        case 2: return launch_bwd_tiled<S, 2>(buf, stats, p, rgb, aux, grad, gslot, gparams, ws, st);
+        case 3: return launch_bwd_tiled<S, 3>(buf, stats, p, rgb, aux, grad, gslot, gparams, ws, st);
+        default: return launch_bwd_tiled<S, 4>(buf, stats, p, rgb, aux, grad, gslot, gparams, ws, st);
+    }
+}
+
 }  // namespace
 
-size_t backward_ws_bytes(int32_t w, int32_t h) {
+size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius) {
     const size_t hw = (size_t)w * h;
     const dim3 g = pixel_grid(w, h);
-    return align_up(3 * hw * 4) + align_up((size_t)g.x * g.y * 2 * 8);
+    const size_t direct = align_up(3 * hw * 4) + align_up((size_t)g.x * g.y * 2 * 8);
+    return std::max(direct, tiled_ws_bytes_r(w, h, k, radius));
 }
 
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
@@ -243,6 +681,13 @@ hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &sta
     p.sigma = prm.sigma;
     p.tau = prm.tau;
     p.e_max = prm.e_max;
+    if (stats.tile == kTB) {  // tiled form
+        if (buf.precision == AFR_FP16)
+            return launch_bwd_tiled_r<__half>(buf, stats, p, rgb, aux, grad_rgb, grad_slot,
+                                              grad_params, ws, st);
+        return launch_bwd_tiled_r<float>(buf, stats, p, rgb, aux, grad_rgb, grad_slot, grad_params,
+                                         ws, st);
+    }
     if (buf.precision == AFR_FP16)
         return launch_bwd_typed<__half>(buf, stats, p, rgb, aux, grad_rgb, grad_slot, grad_params,
                                         ws, st);

@@ -187,7 +187,7 @@ hipError_t launch_reconstruct_tiled(const afr_deep_buffer &buf, const afr_tile_s
                                     const afr_params &p, int tiles_per_wave, float *rgb, float *aux,
                                     hipStream_t st);
 
-size_t backward_ws_bytes(int32_t w, int32_t h);
+size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                            const afr_params &p, const float *rgb, const float *aux,
                            const float *grad_rgb, float *grad_slot, float *grad_params, void *ws,

@@ -53,8 +53,12 @@ def test_status_strings_and_sizes(afr):
     b = lib.afr_build_workspace_bytes(2000, 64, 64, 4)
     assert b - a >= 1000 * 32 - 256 and a >= 1000 * 32  # one 32-byte record per sample
     assert lib.afr_build_workspace_bytes(-1, 64, 64, 4) == 0
-    assert lib.afr_backward_workspace_bytes(512, 512) >= 3 * 512 * 512 * 4
-    assert lib.afr_backward_workspace_bytes(0, 5) == 0
+    assert lib.afr_backward_workspace_bytes(512, 512, 8, 2) >= 3 * 512 * 512 * 4
+    # tiled adjoint: per-pixel (g', k') and per-tile partials of every region slot and plane
+    assert lib.afr_backward_workspace_bytes(512, 512, 8, 2) >= 4096 * 8 * 3 * 144 * 4
+    assert lib.afr_backward_workspace_bytes(0, 5, 8, 2) == 0
+    assert lib.afr_backward_workspace_bytes(5, 5, 0, 2) == 0
+    assert lib.afr_backward_workspace_bytes(5, 5, 8, 5) == 0
 
 
 def _fake_buffer(afr, w=16, h=8, k=4, prec=0, t_ref=10.0, null_plane=False):
@@ -108,7 +112,7 @@ def test_stats_geometry_and_workspace_checks(afr):
     p0 = afr.Params(t_now=11.0, tau=0.0)._c()
     args = [0x2000] * 6
     assert lib.afr_reconstruct_backward(ctypes.byref(b), ctypes.byref(ok), ctypes.byref(p0), *args[:5], 0x3000, 1 << 30, None) == 2
-    small = lib.afr_backward_workspace_bytes(17, 9) - 1
+    small = lib.afr_backward_workspace_bytes(17, 9, 2, 2) - 1
     assert lib.afr_reconstruct_backward(ctypes.byref(b), ctypes.byref(ok), ctypes.byref(p), *args[:5], 0x3000, small, None) == 4
     # build: negative n, too small a workspace
     s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, -1)
