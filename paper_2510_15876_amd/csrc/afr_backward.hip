@@ -285,7 +285,7 @@ __device__ inline void direct_param_terms(const BufView<S> &v, const BwdParams &
                                           double &d_tau) {
     const int W = v.width, H = v.height, R = p.radius;
     const size_t hw = (size_t)W * H;
-    float ax = 0.0f, ay = 0.0f, at = 0.0f;
+    double ax = 0.0, ay = 0.0, at = 0.0;  // the terms cancel (sum of pi h is zero): double sums
     const int qx0 = max(0, i - R), qx1 = min(W - 1, i + R);
     const int qy0 = max(0, j - R), qy1 = min(H - 1, j + R);
     for (int qy = qy0; qy <= qy1; ++qy)
@@ -303,14 +303,14 @@ __device__ inline void direct_param_terms(const BufView<S> &v, const BwdParams &
                 const float h = g0 * (Codec<S>::dec(v.r[s]) - C0) +
                                 g1 * (Codec<S>::dec(v.g[s]) - C1) +
                                 g2 * (Codec<S>::dec(v.b[s]) - C2);
-                const float ph = pi * h;
-                ax += ph * dx * dx;
-                ay += ph * dy * dy;
-                at += ph * a * a;
+                const double ph = (double)(pi * h);
+                ax += ph * (double)(dx * dx);
+                ay += ph * (double)(dy * dy);
+                at += ph * (double)(a * a);
             }
         }
-    d_sig = (double)ax * c.fxs + (double)ay * c.fys;
-    d_tau = (double)ax * c.fxt + (double)ay * c.fyt - (double)at * c.fkt;
+    d_sig = ax * c.fxs + ay * c.fys;
+    d_tau = ax * c.fxt + ay * c.fyt - at * c.fkt;
 }
 
 template <typename S, int R>
@@ -424,7 +424,9 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         rb = plane_load<S>(plane_rsrc(v.b + base, bytes), ioff);
     };
     if (kmax > 0) load_plane(0);
-    float Sx = 0.0f, Sy = 0.0f, Sa = 0.0f;
+    // parameter terms: float within one row of pixels, double across rows (the terms cancel: the
+    // pi-weighted sum of h over a pixel's slots is zero)
+    double Sx = 0.0, Sy = 0.0, Sa = 0.0;
     for (int k = 0; k < kmax; ++k) {
         const bool on = k < icnt;
         const float dx = on ? Codec<S>::dec(rox) - 0.5f : 0.0f;
@@ -434,7 +436,8 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         const float cg = on ? Codec<S>::dec(rg) : 0.0f;
         const float cb = on ? Codec<S>::dec(rb) : 0.0f;
         load_plane(min(k + 1, K - 1));  // in flight during this plane's pairs
-        const float tm = on ? __builtin_amdgcn_exp2f(-((a - amin) * (a + amin)) * ct2) : 0.0f;
+        const float da2 = (a - amin) * (a + amin);  // a^2 - amin^2 >= 0
+        const float tm = on ? __builtin_amdgcn_exp2f(-da2 * ct2) : 0.0f;
         // X for the 2R+1 column offsets (times the temporal factor), kept in registers; the rows
         // are visited one at a time with Y advanced by its recurrence.
         float X[NM], dx2[NM];
@@ -452,7 +455,10 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         }
         const float rhoy = __builtin_amdgcn_exp2f(-2.0f * dy * cy2);
         float yv = __builtin_amdgcn_exp2f(-ey * ey * cy2);
-        const float a2 = a * a;
+        // The a^2 factor of the tau terms enters as a^2 - amin^2: for every pixel the pi-weighted sum
+        // of h over its slots is zero, so a constant offset of a^2 changes nothing but the
+        // rounding, and this one keeps the factor small wherever a weight is not negligible.
+        const float a2 = da2;
         float gr = 0.0f, gg = 0.0f, gb = 0.0f;
 #pragma unroll 1
         for (int n = 0; n < NM; ++n) {
@@ -460,6 +466,7 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             const float uy = (float)(n - R) + dy;
             const float dyn2 = uy * uy;
             const bool rok = jj >= 0 && jj < kTB;
+            float rx = 0.0f, ry = 0.0f, ra = 0.0f;
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 const int ii = cc - m;
@@ -470,10 +477,13 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
                 gg += w * g4.y;
                 gb += w * g4.z;
                 const float hwt = w * (g4.x * cr + g4.y * cg + g4.z * cb - g4.w);
-                Sx += hwt * dx2[m];
-                Sy += hwt * dyn2;
-                Sa += hwt * a2;
+                rx += hwt * dx2[m];
+                ry += hwt;
+                ra += hwt;
             }
+            Sx += (double)rx;
+            Sy += (double)ry * dyn2;
+            Sa += (double)ra * a2;
             // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2)
             yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
         }
@@ -485,8 +495,8 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         }
     }
     const TileCoef c = tile_coef(stats, tg.nt, T, p);
-    double d_sig = (double)Sx * c.fxs + (double)Sy * c.fys;
-    double d_tau = (double)Sx * c.fxt + (double)Sy * c.fyt - (double)Sa * c.fkt;
+    double d_sig = Sx * c.fxs + Sy * c.fys;
+    double d_tau = Sx * c.fxt + Sy * c.fyt - Sa * c.fkt;
     d_sig = wave_sum_d(d_sig);
     d_tau = wave_sum_d(d_tau);
     if (lane == 0) {
