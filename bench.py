@@ -111,7 +111,7 @@ STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gat
 
 def kernel_of(stage, k, radius, tpw):
     """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name)."""
-    return {"bin_count": "k_bin_count", "bin_scan": "k_scan_blocks+k_scan_sums+k_scan_add",
+    return {"bin_count": "k_bin_count", "bin_scan": "k_scan_blocks+k_scan_add",
             "bin_scatter": "k_bin_scatter",
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),

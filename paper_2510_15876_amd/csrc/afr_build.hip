@@ -7,6 +7,7 @@
 //   1. k_bin_count    per chunk of the stream: LDS histogram over bins of 64 x 4 px;
 //                     samples outside the image are dropped here
 //   2. scan           exclusive prefix sum of the (bin, chunk) counts, bin-major -> write offsets
+//                     (block scans, then each block adds the sum of the blocks before it)
 //   3. k_bin_scatter  per chunk: coalesced loads of every field, an LDS counting sort by bin, and
 //                     32-byte records (order key, x, y, t, r, g, b) staged in LDS in bin order, a
 //                     window at a time, so that consecutive lanes store consecutive records of a
@@ -69,6 +70,19 @@ __device__ inline int wave_sum_int(int v) {
     return v;
 }
 
+// Sum of one int per thread over the workgroup (blockDim.x = NT), valid in thread 0.
+template <int NT>
+__device__ inline int block_sum_int(int v) {
+    __shared__ int wsum[NT / kWave];
+    v = wave_sum_int(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / kWave; ++w) t += wsum[w];
+    return t;
+}
+
 __device__ inline int bin_of(float x, float y, const BinGeom &g) {
     return ((int)floorf(y) / g.bh) * g.nbx + (int)floorf(x) / g.bw;
 }
@@ -87,7 +101,7 @@ __device__ inline int key_index(unsigned long long key) { return (int)(unsigned)
 
 __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, ValidCtx c, BinGeom g,
                                                              int32_t *ht, int nchunks,
-                                                             unsigned long long *dropped) {
+                                                             int32_t *bad_tab) {
     __shared__ int hist[kMaxBins];
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) hist[b] = 0;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
@@ -109,8 +123,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, Vali
     __syncthreads();
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
         ht[(size_t)b * nchunks + blockIdx.x] = hist[b];
-    bad = wave_sum_int(bad);
-    if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
+    bad = block_sum_int<kChunkThreads>(bad);
+    if (threadIdx.x == 0) bad_tab[blockIdx.x] = bad;  // samples outside the image
 }
 
 // Block-wide exclusive scan of one int per thread (blockDim = NT).
@@ -173,19 +187,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t *cnt
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Exclusive scan of the block sums in place (one block, chunked), bsum[nb] = grand total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int32_t *bsum, int32_t nb) {
-    const int total = block_scan_lds<kScanThreads>(bsum, bsum, nb);
-    if (threadIdx.x == 0) bsum[nb] = total;
-}
-
+// Adds to block b's entries the sum of the block sums before it (each block sums that prefix itself,
+// so no separate scan of the block sums is needed); the last block also writes off[len] = total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *off, int64_t len,
                                                           const int32_t *bsum, int32_t nb) {
+    __shared__ int s_add;
+    int v = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) v += bsum[i];
+    v = block_sum_int<kScanThreads>(v);
+    if (threadIdx.x == 0) s_add = v;
+    __syncthreads();
+    const int add = s_add;
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
-    const int add = bsum[blockIdx.x];
     for (int e = threadIdx.x; e < kScanBlock; e += kScanThreads)
         if (base + e < len) off[base + e] += add;
-    if (blockIdx.x == 0 && threadIdx.x == 0) off[len] = bsum[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) off[len] = add + bsum[blockIdx.x];
 }
 
 struct alignas(16) Record {
@@ -215,8 +231,7 @@ struct BinRecs {
 // destination, is recomputed from its own x, y.
 __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
                                                                const int32_t *ot, int nchunks,
-                                                               Bucket bucket,
-                                                               unsigned long long *dropped) {
+                                                               Bucket bucket, int32_t *bad_tab) {
     extern __shared__ uint4 scat_lds[];  // 16-byte aligned for the staged records
     int *scat_sm = reinterpret_cast<int *>(scat_lds);
     int *tab = scat_sm;                                                  // [nb]
@@ -273,8 +288,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         }
         __syncthreads();
     }
-    bad = wave_sum_int(bad);
-    if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(dropped, (unsigned long long)bad);
+    bad = block_sum_int<kChunkThreads>(bad);
+    if (threadIdx.x == 0) bad_tab[nchunks + blockIdx.x] = bad;  // invalid time or colour
 }
 
 // Stores a record (key, x, y | t, r, g, b) or, when e < 0, an empty slot at slot-plane offset o.
@@ -424,9 +439,16 @@ __device__ inline KeyXY load_key_xy(const KeyXY *r) { return *r; }
 template <typename S, int KMAX>
 __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out, BinGeom g,
                                                             const int32_t *ot, int nchunks,
-                                                            Bucket bucket) {
+                                                            Bucket bucket, const int32_t *bad_tab,
+                                                            unsigned long long *dropped) {
     extern __shared__ uint4 sel_lds[];  // 16-byte aligned for the key list
     int *sel_sm = reinterpret_cast<int *>(sel_lds);
+    if (blockIdx.x == 0) {  // dropped samples: the per-chunk counts of the count and scatter passes
+        int v = 0;
+        for (int i = threadIdx.x; i < 2 * nchunks; i += kSelThreads) v += bad_tab[i];
+        v = block_sum_int<kSelThreads>(v);
+        if (threadIdx.x == 0) *dropped = (unsigned long long)v;
+    }
     const int npx = g.bw * g.bh;
     int *poff = sel_sm;  // [npx + 1]
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(sel_sm + ((npx + 2) & ~1));
@@ -533,19 +555,18 @@ size_t select_shmem(const BinGeom &g) {
 
 template <typename S>
 hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *ot,
-                         int nchunks, Bucket bucket, hipStream_t st) {
+                         int nchunks, Bucket bucket, const int32_t *bad_tab,
+                         unsigned long long *dropped, hipStream_t st) {
     const size_t shmem = select_shmem(g);
     const dim3 grid(g.nb), block(kSelThreads);
-    if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
-    else if (out.k <= 8) k_bin_select<S, 8><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
-    else if (out.k <= 16) k_bin_select<S, 16><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
-    else if (out.k <= 32) k_bin_select<S, 32><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
-    else if (out.k <= 64) k_bin_select<S, 64><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
-    else k_bin_select<S, 256><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket);
+    if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    else if (out.k <= 8) k_bin_select<S, 8><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    else if (out.k <= 16) k_bin_select<S, 16><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    else if (out.k <= 32) k_bin_select<S, 32><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    else if (out.k <= 64) k_bin_select<S, 64><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    else k_bin_select<S, 256><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
     return hipGetLastError();
 }
-
-__global__ void k_zero_dropped(unsigned long long *dropped) { *dropped = 0ull; }
 
 __global__ void k_fill_zero(int32_t *p, int64_t len) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -576,7 +597,7 @@ size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
     const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     return align_up((size_t)(len + 1) * 4) + align_up((size_t)(nsb + 1) * 4) +
-           2 * align_up(nn * sizeof(KeyXY)) + align_up(8);
+           align_up((size_t)2 * n_chunks(n) * 4) + 2 * align_up(nn * sizeof(KeyXY)) + align_up(8);
 }
 
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
@@ -590,6 +611,8 @@ BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     p += align_up((size_t)(len + 1) * 4);
     o.bsum = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)(nsb + 1) * 4);
+    o.bad = reinterpret_cast<int32_t *>(p);
+    p += align_up((size_t)2 * n_chunks(n) * 4);
     o.bucket = p;
     p += 2 * align_up(nn * sizeof(KeyXY));
     o.dropped_internal = reinterpret_cast<unsigned long long *>(p);
@@ -607,26 +630,27 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     const size_t half = align_up((size_t)(s.n > 0 ? s.n : 1) * sizeof(KeyXY));
     const Bucket bucket{static_cast<KeyXY *>(ws.bucket),
                         reinterpret_cast<float4 *>(static_cast<char *>(ws.bucket) + half)};
-    k_zero_dropped<<<1, 1, 0, st>>>(dropped);
-    if (s.n > 0)
-        k_bin_count<<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch, dropped);
-    else  // no samples: every (bin, chunk) count of the single empty chunk is zero
+    if (s.n > 0) {
+        k_bin_count<<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch, ws.bad);
+    } else {  // no samples: every (bin, chunk) count of the single empty chunk is zero, none dropped
         k_fill_zero<<<std::max(1, std::min((int)((len + 255) / 256), 1024)), 256, 0, st>>>(ws.offsets,
                                                                                        len);
+        k_fill_zero<<<1, 256, 0, st>>>(ws.bad, 2 * nch);
+    }
     hipError_t e = mark(0);
     if (e != hipSuccess) return e;
     k_scan_blocks<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.offsets, ws.bsum);
-    k_scan_sums<<<1, kScanThreads, 0, st>>>(ws.bsum, nsb);
     k_scan_add<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.bsum, nsb);
     if ((e = mark(1)) != hipSuccess) return e;
     const size_t scat_shmem =
         (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
     if (s.n > 0)
         k_bin_scatter<<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets, (int)nch,
-                                                                   bucket, dropped);
+                                                                   bucket, ws.bad);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(2)) != hipSuccess) return e;
-    e = out.precision == AFR_FP16 ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, st)
-                                  : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, st);
+    e = out.precision == AFR_FP16
+            ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st)
+            : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st);
     return e != hipSuccess ? e : mark(3);
 }
 

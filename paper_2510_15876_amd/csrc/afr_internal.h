@@ -134,7 +134,8 @@ void record_tiles_per_wave(const afr_deep_buffer &b, int radius, int tpw);
 struct BuildWs {
     int32_t *offsets;   // [bins * chunks + 1] (bin, chunk) counts, then their exclusive scan
     int32_t *bsum;      // scan block sums
-    void *bucket;       // [n] 32-byte records grouped by bin
+    int32_t *bad;       // [2 * chunks] dropped samples per chunk (outside the image; invalid payload)
+    void *bucket;       // [n] records grouped by bin, as two 16-byte halves in two arrays
     unsigned long long *dropped_internal;
 };
 // Buffer-resource loads of one slot plane: the descriptor (SGPRs) holds the plane's base address
