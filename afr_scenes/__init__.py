@@ -35,13 +35,16 @@ def _rng(seed: int) -> np.random.Generator:
 
 @dataclass
 class Stream:
-    """A stream of space-time samples: float32 SoA arrays of equal length."""
+    """A stream of space-time samples: float32 SoA arrays of equal length. ``vx``, ``vy`` (px/ms,
+    optional) are the image-space velocities of the surfaces the samples hit, for reprojection."""
     x: np.ndarray
     y: np.ndarray
     t: np.ndarray
     r: np.ndarray
     g: np.ndarray
     b: np.ndarray
+    vx: Optional[np.ndarray] = None
+    vy: Optional[np.ndarray] = None
 
     def __len__(self) -> int:
         return int(self.x.shape[0])
@@ -49,11 +52,19 @@ class Stream:
     def arrays(self):
         return (self.x, self.y, self.t, self.r, self.g, self.b)
 
+    def motion(self):
+        """(vx, vy), or None when the stream carries no velocities."""
+        return None if self.vx is None else (self.vx, self.vy)
+
     def select(self, mask_or_index) -> "Stream":
-        return Stream(*(a[mask_or_index] for a in self.arrays()))
+        m = self.motion()
+        extra = () if m is None else tuple(a[mask_or_index] for a in m)
+        return Stream(*(a[mask_or_index] for a in self.arrays()), *extra)
 
     def copy(self) -> "Stream":
-        return Stream(*(a.copy() for a in self.arrays()))
+        m = self.motion()
+        extra = () if m is None else tuple(a.copy() for a in m)
+        return Stream(*(a.copy() for a in self.arrays()), *extra)
 
 
 # --------------------------------------------------------------------------------------------------
@@ -80,6 +91,16 @@ class CheckerDiscScene:
         inside = (x - cx) ** 2 + (y - self.y0) ** 2 <= self.radius ** 2
         r[inside], g[inside], b[inside] = 1.0, 0.0, 0.0
         return r, g, b
+
+    def shade(self, x, y, t):
+        """Colour and image-space velocity (px/ms) of the surface at (x, y, t)."""
+        r, g, b = self.color(x, y, t)
+        x = np.asarray(x, np.float64)
+        y = np.asarray(y, np.float64)
+        cx = self.x0 + self.speed * np.asarray(t, np.float64)
+        inside = (x - cx) ** 2 + (y - self.y0) ** 2 <= self.radius ** 2
+        vx = np.where(inside, self.speed, 0.0)
+        return r, g, b, vx, np.zeros_like(vx)
 
 
 class DiscScene:
@@ -119,13 +140,19 @@ class DiscScene:
         return self.cx[d] + self.vel[d, 0] * dt, self.cy[d] + self.vel[d, 1] * dt
 
     def color(self, x, y, t):
+        return self.shade(x, y, t)[:3]
+
+    def shade(self, x, y, t):
+        """Colour and image-space velocity (px/ms) of the surface at (x, y, t): the top disc's
+        velocity, 0 on the background (its shading changes, its points do not move)."""
         x = np.asarray(x, np.float64)
         y = np.asarray(y, np.float64)
         t = np.asarray(t, np.float64)
         grey = self.background(x, y, t)
         r, g, b = grey.copy(), grey.copy(), grey.copy()
+        vx, vy = np.zeros_like(grey), np.zeros_like(grey)
         if x.size == 0:
-            return r, g, b
+            return r, g, b, vx, vy
         t_lo, t_hi = float(t.min()), float(t.max())
         for d in range(self.radius.shape[0]):
             rad = self.radius[d]
@@ -143,6 +170,7 @@ class DiscScene:
             if idx.size == 0:
                 continue
             cr, cg, cb = self.rgb[d]
+            vx[idx], vy[idx] = self.vel[d, 0], self.vel[d, 1]
             if self.highlights:
                 hx = ddx[inside] + rad / 3.0
                 hy = ddy[inside] + rad / 3.0
@@ -152,7 +180,7 @@ class DiscScene:
                 b[idx] = np.minimum(1.0, cb + hl)
             else:
                 r[idx], g[idx], b[idx] = cr, cg, cb
-        return r, g, b
+        return r, g, b, vx, vy
 
 
 # --------------------------------------------------------------------------------------------------
@@ -160,8 +188,10 @@ class DiscScene:
 # --------------------------------------------------------------------------------------------------
 
 def _shade_to_stream(scene, x32, y32, t32, sort: bool) -> Stream:
-    r, g, b = scene.color(x32.astype(np.float64), y32.astype(np.float64), t32.astype(np.float64))
-    s = Stream(x32, y32, t32, r.astype(np.float32), g.astype(np.float32), b.astype(np.float32))
+    r, g, b, vx, vy = scene.shade(x32.astype(np.float64), y32.astype(np.float64),
+                                  t32.astype(np.float64))
+    f = lambda a: a.astype(np.float32)
+    s = Stream(x32, y32, t32, f(r), f(g), f(b), f(vx), f(vy))
     if sort:
         order = np.argsort(t32, kind="stable")
         s = s.select(order)
@@ -366,7 +396,8 @@ def make_c4_sequence(n_frames: int = 32, instance: int = 0, width: int = 512, he
     for q in range(n_iv):  # shade one 8 ms interval at a time: disc sweeps stay small
         parts.append(_shade_to_stream(scene, x[:, :, q].reshape(-1), y[:, :, q].reshape(-1),
                                       t[:, :, q].reshape(-1), sort=False))
-    s = Stream(*(np.concatenate([getattr(p, f) for p in parts]) for f in "xytrgb"))
+    s = Stream(*(np.concatenate([getattr(p, f) for p in parts])
+                 for f in ("x", "y", "t", "r", "g", "b", "vx", "vy")))
     s = s.select(np.argsort(s.t, kind="stable"))
     return C4Sequence(s, scene, width, height, k, frame_times)
 

@@ -67,8 +67,8 @@ def _lib():
         lib.or_f16_round.restype = ctypes.c_double
         lib.or_f16_round.argtypes = [ctypes.c_double]
         lib.or_build.restype = ctypes.c_int
-        lib.or_build.argtypes = [ctypes.c_int64, fp, fp, fp, fp, fp, fp, ctypes.POINTER(_Buffer),
-                                 ctypes.POINTER(ctypes.c_int64)]
+        lib.or_build.argtypes = [ctypes.c_int64, fp, fp, fp, fp, fp, fp, fp, fp,
+                                 ctypes.POINTER(_Buffer), ctypes.POINTER(ctypes.c_int64)]
         lib.or_pixel_stats.restype = ctypes.c_int
         lib.or_pixel_stats.argtypes = [ctypes.POINTER(_Buffer), ctypes.POINTER(_Params)] + [_dp] * 5
         lib.or_extents.restype = None
@@ -156,17 +156,23 @@ def f16_round(v) -> np.ndarray:
     return np.array([lib.or_f16_round(float(a)) for a in v.reshape(-1)]).reshape(v.shape)
 
 
-def build_buffer(stream, width, height, k, precision="fp32", t_ref=None):
-    """Per-pixel deep buffer from a stream; returns ``(Buffer, dropped)``."""
+def build_buffer(stream, width, height, k, precision="fp32", t_ref=None, reproject=False):
+    """Per-pixel deep buffer from a stream; returns ``(Buffer, dropped)``. With ``reproject`` the
+    stream's velocities advance every sample to ``t_ref`` first (see or_build)."""
     x, y, t, r, g, b = (np.ascontiguousarray(a, np.float32) for a in stream.arrays())
+    vel = stream.motion() if reproject else None
+    if reproject and vel is None:
+        raise ValueError("reproject=True needs a stream with velocities")
+    vx, vy = (None, None) if vel is None else (np.ascontiguousarray(a, np.float32) for a in vel)
     if t_ref is None:
         t_ref = float(t.max()) if t.size else 0.0
     buf = Buffer.empty(width, height, k, precision == "fp16", float(np.float32(t_ref)))
     bc = buf._c()
     dropped = ctypes.c_int64(0)
     fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-    rc = _lib().or_build(len(x), fp(x), fp(y), fp(t), fp(r), fp(g), fp(b), ctypes.byref(bc),
-                         ctypes.byref(dropped))
+    fpn = lambda a: None if a is None else fp(a)
+    rc = _lib().or_build(len(x), fp(x), fp(y), fp(t), fp(r), fp(g), fp(b), fpn(vx), fpn(vy),
+                         ctypes.byref(bc), ctypes.byref(dropped))
     if rc:
         raise ValueError(f"or_build failed ({rc})")
     return buf, int(dropped.value)

@@ -88,6 +88,15 @@ double or_f16_round(double v)
  *
  * This replays the queue insertion literally. Pinned against a sort-and-take-top-K brute force and
  * against the counting invariants (count = min(K, arrivals); K >= occupancy keeps every sample).
+ *
+ * Reprojection (Sec. 6.2: the reconstructor redraws its samples for the current view; here with the
+ * optional per-sample velocity of Sec. 4, taken in image space). When vx, vy are given, a sample's
+ * position is advanced to the buffer's reference time before everything above:
+ *   x' = x + vx * (t_ref - t), y' = y + vy * (t_ref - t)
+ * in binary32 with three separate roundings (subtraction, product, sum; no fused multiply-add), so
+ * the home pixel is an exact function of the stored inputs. Validity and the stored offsets use
+ * x', y'. Pinned by: zero velocity equals the plain build; a sample displaced by whole pixels lands
+ * on the expected pixel with unchanged offsets; samples moved outside the image are dropped.
  * --------------------------------------------------------------------------------------------- */
 typedef struct { float t; int64_t i; } or_key;
 
@@ -99,8 +108,9 @@ static int or_key_cmp(const void *pa, const void *pb)
     return (a->i > b->i) - (a->i < b->i);
 }
 
-int or_build(int64_t n, const float *x, const float *y, const float *t, const float *r,
-             const float *g, const float *b, or_buffer *out, int64_t *dropped)
+int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, const float *r,
+             const float *g, const float *b, const float *vx, const float *vy, or_buffer *out,
+             int64_t *dropped)
 {
     const int W = out->width, H = out->height, K = out->k;
     if (W <= 0 || H <= 0 || K < 1 || K > 255 || n < 0)
@@ -116,6 +126,27 @@ int or_build(int64_t n, const float *x, const float *y, const float *t, const fl
     or_key *keys = (or_key *)malloc(sizeof(or_key) * (size_t)(n > 0 ? n : 1));
     if (!keys)
         return 4;
+    /* positions at the reference time (reprojection), or the stored positions */
+    const float *x = x_in, *y = y_in;
+    float *xa = NULL, *ya = NULL;
+    if (vx && vy && n > 0) {
+        xa = (float *)malloc(sizeof(float) * (size_t)n);
+        ya = (float *)malloc(sizeof(float) * (size_t)n);
+        if (!xa || !ya) {
+            free(keys);
+            free(xa);
+            free(ya);
+            return 4;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            volatile float d = t_ref - t[i];     /* each operation rounded on its own */
+            volatile float px = vx[i] * d, py = vy[i] * d;
+            xa[i] = x_in[i] + px;
+            ya[i] = y_in[i] + py;
+        }
+        x = xa;
+        y = ya;
+    }
     int64_t nv = 0, nd = 0;
     for (int64_t i = 0; i < n; ++i) {
         int ok = isfinite(x[i]) && isfinite(y[i]) && isfinite(t[i]) && isfinite(r[i]) &&
@@ -174,6 +205,8 @@ int or_build(int64_t n, const float *x, const float *y, const float *t, const fl
         out->count[p] = (uint8_t)(c < K ? c + 1 : K);
     }
     free(keys);
+    free(xa);
+    free(ya);
     if (dropped)
         *dropped = nd;
     return 0;

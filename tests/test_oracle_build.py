@@ -138,3 +138,64 @@ def test_fp16_build_stores_binary16_of_the_fp32_values(oracle):
     np.testing.assert_array_equal(buf16.r[sel], h(buf32.r[sel]))
     age32 = (np.float32(wl.t_ref) - buf32.ta[sel].astype(np.float32)).astype(np.float32)
     np.testing.assert_array_equal(buf16.ta[sel], h(age32))
+
+
+def _with_velocity(s, vx, vy):
+    return S.Stream(*s.arrays(), np.asarray(vx, np.float32), np.asarray(vy, np.float32))
+
+
+def test_reprojection_with_zero_velocity_is_the_plain_build(oracle):
+    rng = np.random.default_rng(31)
+    s = _stream(rng, 3000, 19, 13)
+    z = np.zeros(len(s), np.float32)
+    for precision in ("fp32", "fp16"):
+        a, da = oracle.build_buffer(s, 19, 13, 5, precision, 10.0)
+        b, db = oracle.build_buffer(_with_velocity(s, z, z), 19, 13, 5, precision, 10.0,
+                                    reproject=True)
+        assert da == db
+        for f in ("ox", "oy", "ta", "r", "g", "b", "count", "src"):
+            np.testing.assert_array_equal(getattr(a, f), getattr(b, f), err_msg=f)
+
+
+def test_reprojection_moves_samples_by_whole_pixels(oracle):
+    """Velocities that displace every sample by an exact whole number of pixels by t_ref (binary32
+    arithmetic is exact here: dyadic velocities and ages) land each sample on the shifted pixel with
+    the same sub-pixel offset; samples moved outside the image are dropped."""
+    w, h, t_ref = 16, 8, 32.0
+    x = np.array([0.25, 3.5, 15.75, 7.125], np.float32)
+    y = np.array([0.5, 2.25, 7.5, 4.0], np.float32)
+    t = np.array([24.0, 28.0, 30.0, 16.0], np.float32)          # ages 8, 4, 2, 16 ms
+    vx = np.array([0.25, -0.5, 0.5, 0.0], np.float32)          # +2, -2, +1 (out), 0 px
+    vy = np.array([0.125, 0.25, 0.0, -0.1875], np.float32)     # +1, +1, 0, -3 px
+    c = np.array([0.1, 0.2, 0.3, 0.4], np.float32)
+    s = S.Stream(x, y, t, c, c, c, vx, vy)
+    buf, dropped = oracle.build_buffer(s, w, h, 2, "fp32", t_ref, reproject=True)
+    assert dropped == 1                                          # 15.75 + 1 >= 16
+    expect = {(1, 2): 0, (3, 1): 1, (1, 7): 3}                   # (y, x) of the new home pixel
+    assert int(buf.count.sum()) == 3
+    for (py, px), i in expect.items():
+        assert buf.count[py, px] == 1
+        assert buf.src[py, px, 0] == i
+        assert buf.ox[py, px, 0] == x[i] - np.floor(x[i])
+        assert buf.oy[py, px, 0] == y[i] - np.floor(y[i])
+
+
+def test_reprojection_matches_binary32_advection_brute_force(oracle):
+    """Random velocities: the reprojected build equals the plain build of a stream whose positions
+    were advanced in binary32 (subtract, multiply, add, each rounded) outside the reference."""
+    rng = np.random.default_rng(32)
+    w, h, t_ref = 23, 17, 40.0
+    s = _stream(rng, 4000, w, h, t_max=t_ref)
+    vx = (rng.standard_normal(len(s)) * 0.2).astype(np.float32)
+    vy = (rng.standard_normal(len(s)) * 0.2).astype(np.float32)
+    d = (np.float32(t_ref) - s.t).astype(np.float32)
+    xa = (s.x + (vx * d).astype(np.float32)).astype(np.float32)
+    ya = (s.y + (vy * d).astype(np.float32)).astype(np.float32)
+    moved = S.Stream(xa, ya, s.t, s.r, s.g, s.b)
+    for precision in ("fp32", "fp16"):
+        a, da = oracle.build_buffer(_with_velocity(s, vx, vy), w, h, 6, precision, t_ref,
+                                    reproject=True)
+        b, db = oracle.build_buffer(moved, w, h, 6, precision, t_ref)
+        assert da == db > 0
+        for f in ("ox", "oy", "ta", "r", "g", "b", "count", "src"):
+            np.testing.assert_array_equal(getattr(a, f), getattr(b, f), err_msg=f)
