@@ -42,6 +42,8 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-fwdbwd", action="store_true", help="skip the forward+adjoint frames")
     ap.add_argument("--frames", type=int, default=32, help="frames in the forward+adjoint leg")
+    ap.add_argument("--reproject-frames", type=int, default=8,
+                    help="frames in the reprojection leg (0 skips it)")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
@@ -111,8 +113,8 @@ STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gat
 
 def kernel_of(stage, k, radius, tpw):
     """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name)."""
-    return {"bin_count": "k_bin_count", "bin_scan": "k_scan_blocks+k_scan_add",
-            "bin_scatter": "k_bin_scatter",
+    return {"bin_count": "k_bin_count<false>", "bin_scan": "k_scan_blocks+k_scan_add",
+            "bin_scatter": "k_bin_scatter<false>",
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),
             "estimate": "k_estimate<__half>",
@@ -344,6 +346,8 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(torch, afr, S, dev, args.frames)
+    if args.reproject_frames > 0:
+        out["reproject"] = reproject_leg(torch, afr, S, dev, args.reproject_frames)
     if args.batch > 0:
         out["batch"] = batch_leg(torch, afr, S, dev, args.batch)
     print(json.dumps(out), flush=True)
@@ -433,6 +437,44 @@ def fwd_bwd(torch, afr, S, dev, frames):
     torch.cuda.synchronize()
     return {"workload": "512x512 K=8 FP32, %d frames at 60 Hz" % frames,
             "ms_per_frame": round(e0.elapsed_time(e1) / frames, 5)}
+
+
+def reproject_leg(torch, afr, S, dev, frames, reps=5):
+    """Reconstructor reprojection on the 512x512, K=8, FP32 sequence: per frame, the RMS error against
+    the analytic ground truth of the full forward with and without advecting samples by their
+    surface velocity, and the build time of each."""
+    seq = S.make_c4_sequence(n_frames=frames)
+    W, H, K = seq.width, seq.height, seq.k
+    buf = afr.DeepBuffer(W, H, K, "fp32", 0.0, device=dev)
+    drop = torch.zeros(1, dtype=torch.int64, device=dev)
+    rms = {False: [], True: []}
+    build_ms = {False: [], True: []}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for f in range(frames):
+        wl = seq.frame_workload(f)
+        gt = torch.from_numpy(S.ground_truth(seq.scene, W, H, wl.t_now, 2)).float().to(dev)
+        s = [torch.from_numpy(a).to(dev) for a in wl.stream.arrays()]
+        vx, vy = (torch.from_numpy(a).to(dev) for a in wl.stream.motion())
+        p = afr.Params(t_now=wl.t_now)
+        for rep in (False, True):
+            vel = dict(vx=vx, vy=vy) if rep else {}
+            afr.build_deep_buffer(*s, W, H, K, "fp32", wl.t_ref, out=buf, dropped=drop, **vel)
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                afr.build_deep_buffer(*s, W, H, K, "fp32", wl.t_ref, out=buf, dropped=drop, **vel)
+            ev[1].record()
+            torch.cuda.synchronize()
+            build_ms[rep].append(ev[0].elapsed_time(ev[1]) / reps)
+            st = afr.estimate_gradients(buf, p)
+            rgb, _ = afr.reconstruct(buf, st, p)
+            rms[rep].append(float(torch.sqrt(((rgb - gt) ** 2).mean()).item()))
+    return {"workload": "512x512 K=8 FP32, %d frames at 60 Hz, 64 discs with analytic velocities"
+                        % frames,
+            "rms_plain": round(float(np.mean(rms[False])), 6),
+            "rms_reprojected": round(float(np.mean(rms[True])), 6),
+            "build_ms_plain": round(float(np.mean(build_ms[False])), 5),
+            "build_ms_reprojected": round(float(np.mean(build_ms[True])), 5)}
 
 
 if __name__ == "__main__":

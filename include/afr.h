@@ -58,10 +58,18 @@ typedef enum afr_precision {
 
 /* A stream of samples (Sec. 4.2: the sampler streams every sample to the reconstructor). Device
  * SoA float32 arrays of length n: sub-pixel position (x, y), time t in ms, and linear RGB colour. The
- * order of the stream does not matter: samples are ranked by the key (t, index). */
+ * order of the stream does not matter: samples are ranked by the key (t, index).
+ *
+ * vx, vy (optional, both or neither; NULL = no reprojection): image-space velocity in px/ms of the
+ * surface each sample hit (the optional per-sample velocity of Sec. 4). When given, the build
+ * reprojects (Sec. 6.2) every sample to the buffer's reference time before binning it:
+ *   x' = x + vx * (t_ref - t),  y' = y + vy * (t_ref - t)
+ * in binary32 with each of the subtraction, product and sum rounded on its own (no fused
+ * multiply-add), and x', y' replace x, y everywhere below (home pixel, validity, stored offsets). */
 typedef struct afr_samples {
     const float *x, *y, *t, *r, *g, *b;
     int64_t n;
+    const float *vx, *vy;
 } afr_samples;
 
 /* Per-pixel deep buffer (Sec. 4): pixel p keeps count[p] <= K slots, newest first. For every filled
@@ -131,7 +139,7 @@ const char *afr_version(void);
  * 0 <= y < height and t <= out->t_ref; in FP16 mode its age and colours must also round to finite
  * binary16 values. Invalid samples are dropped, not errors.
  *
- *   s            device sample stream; n < 2^31
+ *   s            device sample stream; n < 2^31; AFR_E_INVALID if exactly one of vx, vy is NULL
  *   out          geometry, precision, t_ref and destination planes (all overwritten)
  *   ws, ws_bytes device workspace of at least afr_build_workspace_bytes(n, width, height, k) bytes
  *   dropped_dev  optional device int64: receives the number of dropped samples

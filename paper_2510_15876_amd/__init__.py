@@ -42,7 +42,7 @@ class AfrError(RuntimeError):
 class _Samples(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("r", ctypes.c_void_p), ("g", ctypes.c_void_p), ("b", ctypes.c_void_p),
-                ("n", ctypes.c_int64)]
+                ("n", ctypes.c_int64), ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p)]
 
 
 class _DeepBuffer(ctypes.Structure):
@@ -259,18 +259,26 @@ def _workspace(nbytes: int, device, key: str) -> torch.Tensor:
 
 def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precision: str = "fp32",
                       t_ref: Optional[float] = None, out: Optional[DeepBuffer] = None,
-                      stream=None, dropped: Optional[torch.Tensor] = None, stage_events=None):
+                      stream=None, dropped: Optional[torch.Tensor] = None, stage_events=None,
+                      vx=None, vy=None):
     """Build the per-pixel deep buffer from a device sample stream (float32 SoA).
 
+    ``vx``, ``vy``: optional per-sample image-space velocities (px/ms); when given, every sample is
+    reprojected to ``t_ref`` before binning (see afr_samples in afr.h).
     ``stage_events``: optional list of ``build_stage_count()`` timing-enabled ``torch.cuda.Event``
     objects, recorded on the stream after the count, scan, scatter and select stages.
     Returns ``(buffer, dropped)`` where ``dropped`` is a device int64 tensor of one element."""
     lib = library()
+    if (vx is None) != (vy is None):
+        raise AfrError("vx and vy go together")
     xs = [x, y, t, r, g, b]
-    for a in xs:
-        if a.dtype != torch.float32 or not a.is_cuda or a.dim() != 1:
-            raise AfrError("sample arrays must be 1-D float32 device tensors")
+    vel = [] if vx is None else [vx, vy]
     n = int(x.shape[0])
+    for a in xs + vel:
+        if a.dtype != torch.float32 or not a.is_cuda or a.dim() != 1 or not a.is_contiguous():
+            raise AfrError("sample arrays must be contiguous 1-D float32 device tensors")
+        if int(a.shape[0]) != n or a.device != x.device:
+            raise AfrError("sample arrays must have one length and one device")
     if t_ref is None:
         raise AfrError("t_ref is required (every sample with t > t_ref is dropped)")
     dev = x.device
@@ -280,7 +288,8 @@ def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precisi
         out.t_ref = float(t_ref)
     if dropped is None:
         dropped = torch.zeros(1, dtype=torch.int64, device=dev)
-    s = _Samples(*(a.data_ptr() if n else None for a in xs), n)
+    s = _Samples(*(a.data_ptr() if n else None for a in xs), n,
+                 *((a.data_ptr() if n else None) for a in vel))
     wsb = lib.afr_build_workspace_bytes(n, width, height, k)
     ws = _workspace(wsb, dev, "build")
     bc = out._c()

@@ -47,6 +47,7 @@ static afr_status build_checked(const afr_samples *s, afr_deep_buffer *out, void
     if (!s || s->n < 0) return AFR_E_INVALID;
     if (s->n >= (int64_t(1) << 31)) return AFR_E_RANGE;
     if (s->n > 0 && (!s->x || !s->y || !s->t || !s->r || !s->g || !s->b)) return AFR_E_INVALID;
+    if (!s->vx != !s->vy) return AFR_E_INVALID;
     if (!ws) return AFR_E_INVALID;
     if (!build_supported(out->width, out->height)) return AFR_E_UNSUPPORTED;
     if (ws_bytes < build_ws_bytes(s->n, out->width, out->height)) return AFR_E_NOMEM;

@@ -5,7 +5,8 @@
 // per pixel; the same final state is the top-K by key (t, stream index) of the samples binned to the
 // pixel. This file computes it with a two-level partition that keeps random accesses in LDS and L2:
 //   1. k_bin_count    per chunk of the stream: LDS histogram over bins of 64 x 4 px;
-//                     samples outside the image are dropped here
+//                     samples outside the image are dropped here (after reprojection to the
+//                     reference time when the stream carries velocities; the scatter repeats it)
 //   2. scan           exclusive prefix sum of the (bin, chunk) counts, bin-major -> write offsets
 //                     (block scans, then each block adds the sum of the blocks before it)
 //   3. k_bin_scatter  per chunk: coalesced loads of every field, an LDS counting sort by bin, and
@@ -83,6 +84,15 @@ __device__ inline int block_sum_int(int v) {
     return t;
 }
 
+// Reprojection to the reference time (Sec. 6.2 with the per-sample velocity of Sec. 4): each of the
+// subtraction, product and sum is rounded on its own, so the home pixel is an exact function of the
+// stored inputs. A non-finite time or velocity makes the position non-finite, which drops the sample.
+__device__ inline void advect(float &x, float &y, float t, float vx, float vy, float t_ref) {
+    const float d = __fsub_rn(t_ref, t);
+    x = __fadd_rn(x, __fmul_rn(vx, d));
+    y = __fadd_rn(y, __fmul_rn(vy, d));
+}
+
 __device__ inline int bin_of(float x, float y, const BinGeom &g) {
     return ((int)floorf(y) / g.bh) * g.nbx + (int)floorf(x) / g.bw;
 }
@@ -99,6 +109,8 @@ __device__ inline unsigned long long order_key(float t, int i) {
 
 __device__ inline int key_index(unsigned long long key) { return (int)(unsigned)(key & 0xffffffffu); }
 
+// MOTION: the stream carries velocities and positions are reprojected first.
+template <bool MOTION>
 __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, ValidCtx c, BinGeom g,
                                                              int32_t *ht, int nchunks,
                                                              int32_t *bad_tab) {
@@ -106,11 +118,21 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, Vali
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) hist[b] = 0;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     float xs[kChunkPer], ys[kChunkPer];
+    float ts[MOTION ? kChunkPer : 1], us[MOTION ? kChunkPer : 1], vs[MOTION ? kChunkPer : 1];
 #pragma unroll
     for (int j = 0; j < kChunkPer; ++j) {  // all loads first
         const int64_t i = min(base + (int64_t)j * kChunkThreads + threadIdx.x, s.n - 1);
         xs[j] = s.x[i];
         ys[j] = s.y[i];
+        if constexpr (MOTION) {
+            ts[j] = s.t[i];
+            us[j] = s.vx[i];
+            vs[j] = s.vy[i];
+        }
+    }
+    if constexpr (MOTION) {
+#pragma unroll
+        for (int j = 0; j < kChunkPer; ++j) advect(xs[j], ys[j], ts[j], us[j], vs[j], c.t_ref);
     }
     __syncthreads();
     int bad = 0;
@@ -229,6 +251,7 @@ struct BinRecs {
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
 // position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
 // destination, is recomputed from its own x, y.
+template <bool MOTION>
 __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
                                                                const int32_t *ot, int nchunks,
                                                                Bucket bucket, int32_t *bad_tab) {
@@ -248,6 +271,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         rec[j].r = s.r[i];
         rec[j].g = s.g[i];
         rec[j].b = s.b[i];
+        if constexpr (MOTION) advect(rec[j].x, rec[j].y, rec[j].t, s.vx[i], s.vy[i], c.t_ref);
     }
     __syncthreads();
     int bin[kChunkPer], sp[kChunkPer];
@@ -631,7 +655,12 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     const Bucket bucket{static_cast<KeyXY *>(ws.bucket),
                         reinterpret_cast<float4 *>(static_cast<char *>(ws.bucket) + half)};
     if (s.n > 0) {
-        k_bin_count<<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch, ws.bad);
+        if (s.vx)
+            k_bin_count<true><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
+                                                                  ws.bad);
+        else
+            k_bin_count<false><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
+                                                                   ws.bad);
     } else {  // no samples: every (bin, chunk) count of the single empty chunk is zero, none dropped
         k_fill_zero<<<std::max(1, std::min((int)((len + 255) / 256), 1024)), 256, 0, st>>>(ws.offsets,
                                                                                        len);
@@ -644,9 +673,12 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     if ((e = mark(1)) != hipSuccess) return e;
     const size_t scat_shmem =
         (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
-    if (s.n > 0)
-        k_bin_scatter<<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets, (int)nch,
-                                                                   bucket, ws.bad);
+    if (s.n > 0 && s.vx)
+        k_bin_scatter<true><<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets,
+                                                                         (int)nch, bucket, ws.bad);
+    else if (s.n > 0)
+        k_bin_scatter<false><<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets,
+                                                                          (int)nch, bucket, ws.bad);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     e = out.precision == AFR_FP16
             ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st)

@@ -32,9 +32,14 @@ def dev_stream(stream):
     return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in stream.arrays()]
 
 
-def gpu_build(stream, w, h, k, precision, t_ref):
+def gpu_build(stream, w, h, k, precision, t_ref, reproject=False):
     afr = afr_mod()
-    buf, dropped = afr.build_deep_buffer(*dev_stream(stream), w, h, k, precision, t_ref)
+    vel = {}
+    if reproject:
+        torch = torch_mod()
+        vx, vy = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in stream.motion())
+        vel = dict(vx=vx, vy=vy)
+    buf, dropped = afr.build_deep_buffer(*dev_stream(stream), w, h, k, precision, t_ref, **vel)
     return buf, int(dropped.item())
 
 

@@ -121,6 +121,11 @@ def test_stats_geometry_and_workspace_checks(afr):
     assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 16, None, None) == 4
     s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1 << 31)
     assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 40, None, None) == 2
+    # reprojection velocities come in pairs
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000, 0x1000, None)
+    assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None) == 1
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000, None, 0x1000)
+    assert lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None) == 1
     # staged build: four stage events, none of them NULL
     assert lib.afr_build_stage_count() == 4
     s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000)

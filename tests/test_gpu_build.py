@@ -117,3 +117,44 @@ def test_staged_build_equals_build_and_times_every_stage():
     assert torch.equal(a.src, b.src) and int(da.item()) == int(db.item())
     times = [evs[i].elapsed_time(evs[i + 1]) for i in range(len(evs) - 1)]
     assert all(t >= 0.0 for t in times) and sum(times) > 0.0
+
+
+@pytest.mark.parametrize("name,precision", [("c1", "fp32"), ("c3", "fp16"), ("c4", "fp32")])
+def test_reprojected_build_matches_reference(name, precision):
+    """Samples advanced by their surface velocity to the reference time before binning: the same
+    bit-exact selection as the plain build, on the moving-disc workloads."""
+    wl = workload(name)
+    print(f"reprojected build {name} {precision} n={len(wl.stream)}", flush=True)
+    gbuf, gd = gpu_build(wl.stream, wl.width, wl.height, wl.k, precision, wl.t_ref, reproject=True)
+    obuf, od = O.build_buffer(wl.stream, wl.width, wl.height, wl.k, precision, wl.t_ref,
+                              reproject=True)
+    assert gd == od
+    assert_buffers_equal(gbuf, obuf)
+    # the moving discs do move samples to other pixels
+    plain, _ = oracle_build_cached(name, precision, wl.k)
+    assert not np.array_equal(plain.src, obuf.src)
+
+
+def test_reprojection_drops_samples_moved_out_and_non_finite_motion():
+    """Fast random velocities push many samples across bins and out of the image; non-finite
+    velocities, and an infinite velocity at age 0, drop the sample; t > t_ref stays dropped."""
+    rng = np.random.default_rng(77)
+    w, h, n, t_ref = 150, 70, 150 * 70 * 6, 30.0
+    x = (rng.random(n) * w).astype(np.float32)
+    y = (rng.random(n) * h).astype(np.float32)
+    t = rng.choice(np.arange(0, 32, 0.125, dtype=np.float32), n)   # some later than t_ref
+    t[:50] = np.float32(t_ref)                                      # age 0
+    vx = (rng.standard_normal(n) * 2.0).astype(np.float32)
+    vy = (rng.standard_normal(n) * 0.5).astype(np.float32)
+    vx[:20] = np.inf
+    vx[50:60] = np.nan
+    vy[60:70] = -np.inf
+    c = rng.random((3, n)).astype(np.float32)
+    s = S.Stream(x, y, t, c[0], c[1], c[2], vx, vy)
+    print(f"reprojection drops n={n}", flush=True)
+    for precision in ("fp32", "fp16"):
+        for k in (3, 9):
+            gbuf, gd = gpu_build(s, w, h, k, precision, t_ref, reproject=True)
+            obuf, od = O.build_buffer(s, w, h, k, precision, t_ref, reproject=True)
+            assert gd == od > n // 4
+            assert_buffers_equal(gbuf, obuf)
