@@ -23,6 +23,7 @@ import numpy as np
 __all__ = [
     "Stream", "Workload", "CheckerDiscScene", "DiscScene", "stratified_stream", "uniform_stream",
     "ground_truth", "make_workload", "make_c4_sequence", "make_c5_batch", "CONFIG_NAMES",
+    "Crosshairs", "crosshair_stream", "make_crosshair_workload",
 ]
 
 OMEGA_RAD_PER_MS = 1e-3   # background ramp rotation, 1 rad/s
@@ -111,12 +112,16 @@ class DiscScene:
     ``0.5 + 0.5 * ((x - W/2) cos wt + (y - H/2) sin wt) / (hypot(W, H) / 2)``, clipped to [0, 1].
     With ``highlights`` each disc also carries a Gaussian highlight (sigma 3 px, peak 1.0) centred at
     ``centre + (-r/3, -r/3)``, added to all three channels inside the disc and clipped at 1.
+    With ``checker > 0`` the background is instead a static checkerboard of that cell size in px,
+    grey 0.8 where ``floor(x/c) + floor(y/c)`` is even and 0.2 elsewhere.
     """
 
     def __init__(self, width: int, height: int, rng: np.random.Generator, n_discs: int,
                  t_centre: float, highlights: bool = False, speed: float = 0.5,
                  radius: tuple = (4.0, 24.0), omega: float = OMEGA_RAD_PER_MS,
-                 highlight_sigma: float = 3.0, highlight_peak: float = 1.0):
+                 highlight_sigma: float = 3.0, highlight_peak: float = 1.0,
+                 checker: float = 0.0):
+        self.checker = float(checker)
         self.width, self.height = int(width), int(height)
         self.t_centre = float(t_centre)
         self.omega = float(omega)
@@ -130,6 +135,10 @@ class DiscScene:
         self.vel = rng.uniform(-speed, speed, (n, 2))
 
     def background(self, x, y, t):
+        if self.checker > 0.0:  # static checkerboard, grey levels 0.2 and 0.8
+            c = self.checker
+            even = (np.floor(x / c) + np.floor(y / c)) % 2 == 0
+            return np.where(even, 0.8, 0.2) + 0.0 * t
         w, h = self.width, self.height
         half_diag = 0.5 * np.hypot(w, h)
         proj = (x - 0.5 * w) * np.cos(self.omega * t) + (y - 0.5 * h) * np.sin(self.omega * t)
@@ -431,3 +440,110 @@ def c5_recipe(n: int = 64, sizes=C5_SIZES, ks=C5_KS):
     size_idx = recipe.integers(0, len(sizes), n)
     k_idx = recipe.integers(0, len(ks), n)
     return [(sizes[int(a)][0], sizes[int(a)][1], ks[int(b)]) for a, b in zip(size_idx, k_idx)]
+
+
+# --------------------------------------------------------------------------------------------------
+# Crosshair sampling (Sec. 4.1, 4.2)
+# --------------------------------------------------------------------------------------------------
+
+@dataclass
+class Crosshairs:
+    """Crosshairs as int32 indices into a sample stream, one entry per crosshair: the centre
+    ``(x, y, t)``, the four samples one pixel away at the same instant (``xm``, ``xp`` at x -/+ 1,
+    ``ym``, ``yp`` at y -/+ 1) and the earlier sample ``old`` at the same sub-pixel spot. -1 marks
+    a sample that does not exist (a neighbour outside the image)."""
+    centre: np.ndarray
+    xm: np.ndarray
+    xp: np.ndarray
+    ym: np.ndarray
+    yp: np.ndarray
+    old: np.ndarray
+
+    def __len__(self) -> int:
+        return int(self.centre.shape[0])
+
+    def arrays(self):
+        return (self.centre, self.xm, self.xp, self.ym, self.yp, self.old)
+
+
+def crosshair_stream(scene, width: int, height: int, visits: int, t_now: float, t_win: float,
+                     rng: np.random.Generator):
+    """A sample stream made by crosshair sampling, and its crosshairs.
+
+    Every pixel is visited ``visits`` times at uniform times in ``(t_now - t_win, t_now]``. At each
+    visit the sampler completes the crosshair started at the previous visit to that pixel (five new
+    samples at the visit time: the centre at the spot chosen then, and its four neighbours one pixel
+    away, those outside the image omitted; the earlier sample is the one taken at that spot) and
+    starts the next one with a single sample at a new uniform sub-pixel spot (Sec. 4.2, with the
+    tile of the paper's sampler narrowed to one pixel). Every sample goes into the stream, which is
+    sorted by time; the crosshair indices refer to the sorted stream.
+
+    Draw order: spot offsets x, y as ``[H, W, visits]``, then visit-time offsets ``[H, W, visits]``.
+    """
+    shape = (height, width, visits)
+    ux = rng.random(shape)
+    uy = rng.random(shape)
+    ut = np.sort(rng.random(shape), axis=2)
+    jj, ii = np.meshgrid(np.arange(height, dtype=np.float64), np.arange(width, dtype=np.float64),
+                         indexing="ij")
+    sx = (ii[:, :, None] + ux).astype(np.float32)                # spot of the sample started
+    sy = (jj[:, :, None] + uy).astype(np.float32)
+    tv = (t_now - t_win * (1.0 - ut)).astype(np.float32)        # visit times, ascending
+    # the starting samples: one per visit
+    xs, ys, ts = [sx.reshape(-1)], [sy.reshape(-1)], [tv.reshape(-1)]
+    n_start = sx.size
+    start_id = np.arange(n_start, dtype=np.int64).reshape(shape)
+    # completed crosshairs: visit v >= 1 completes the one started at v - 1
+    cxh = sx[:, :, :-1].reshape(-1)
+    cyh = sy[:, :, :-1].reshape(-1)
+    tc = tv[:, :, 1:].reshape(-1)
+    old = start_id[:, :, :-1].reshape(-1)
+    nx = cxh.size
+    ids = {}
+    base = n_start
+    one = np.float32(1.0)
+    for name, dx, dy in (("centre", 0, 0), ("xm", -1, 0), ("xp", 1, 0), ("ym", 0, -1),
+                         ("yp", 0, 1)):
+        px = cxh if dx == 0 else (cxh - one if dx < 0 else cxh + one)
+        py = cyh if dy == 0 else (cyh - one if dy < 0 else cyh + one)
+        inside = (px >= 0) & (px < width) & (py >= 0) & (py < height)
+        k = np.nonzero(inside)[0]
+        idx = np.full(nx, -1, np.int64)
+        idx[k] = base + np.arange(k.size)
+        base += k.size
+        xs.append(px[k]); ys.append(py[k]); ts.append(tc[k])
+        ids[name] = idx
+    x = np.concatenate(xs).astype(np.float32)
+    y = np.concatenate(ys).astype(np.float32)
+    t = np.concatenate(ts).astype(np.float32)
+    s = _shade_to_stream(scene, x, y, t, sort=False)
+    order = np.argsort(t, kind="stable")
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    remap = lambda a: np.where(a >= 0, rank[np.maximum(a, 0)], -1).astype(np.int32)
+    xh = Crosshairs(remap(ids["centre"]), remap(ids["xm"]), remap(ids["xp"]), remap(ids["ym"]),
+                    remap(ids["yp"]), remap(old))
+    return s.select(order), xh
+
+
+@dataclass
+class CrosshairWorkload:
+    workload: Workload
+    crosshairs: Crosshairs
+    k_xh: int               # depth of the sampler's per-pixel crosshair queue
+
+
+def make_crosshair_workload(instance: int = 0, width: int = 256, height: int = 256,
+                            visits: int = 4, k: int = 16, k_xh: int = 4) -> CrosshairWorkload:
+    """256x256 crosshair-sampled workload: a static 8-px checkerboard (grey 0.2 / 0.8) under 16 discs
+    moving at up to 0.2 px/ms, every pixel visited ``visits`` times over a 64 ms window (about 19
+    samples per pixel), reconstructor depth ``k`` (FP32), sampler queue depth ``k_xh`` (Sec. 4 uses
+    4). Seed 6000 + instance."""
+    rng = _rng(6000 + instance)
+    t_now, t_win = 64.0, 64.0
+    scene = DiscScene(width, height, rng, 16, t_now, speed=0.2, checker=8.0)
+    s, xh = crosshair_stream(scene, width, height, visits, t_now, t_win, rng)
+    t_ref = float(np.float32(t_now))
+    wl = Workload("crosshair", s, width, height, k, "fp32", t_ref, t_ref, scene,
+                  description="256x256 crosshair sampling, checkerboard + 16 discs, FP32")
+    return CrosshairWorkload(wl, xh, k_xh)

@@ -79,6 +79,12 @@ def _lib():
         lib.or_reconstruct.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params), _dp, _dp]
         lib.or_backward.restype = ctypes.c_int
         lib.or_backward.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        lib.or_crosshair_records.restype = ctypes.c_int
+        lib.or_crosshair_records.argtypes = ([ctypes.c_int64] + [fp] * 6 + [ctypes.c_int64]
+                                             + [ip] * 6 + [ctypes.c_double] + [fp] * 3 + [_dp] * 3)
+        lib.or_crosshair_tiles.restype = ctypes.c_int
+        lib.or_crosshair_tiles.argtypes = [ctypes.POINTER(_Buffer), ctypes.POINTER(_Params), _dp]
         _lib_handle = lib
     return _lib_handle
 
@@ -254,3 +260,48 @@ def rms_grad(img, gt, scale=1.0):
     if e == 0.0:
         return np.zeros_like(d)
     return scale * d / (d.size * e)
+
+
+# ---- crosshair gradients (Sec. 4.1) --------------------------------------------------------------
+
+_XH_FIELDS = ("centre", "xm", "xp", "ym", "yp", "old")
+
+
+def crosshair_records(stream, xh, dt_floor=1e-3):
+    """Per-crosshair records: ``(cx, cy, ct)`` float32 (NaN position for a dropped crosshair) and
+    ``(gx, gy, gt)`` in FP64 (-1 where undefined); see or_crosshair_records."""
+    x, y, t, r, g, b = (np.ascontiguousarray(a, np.float32) for a in stream.arrays())
+    idx = [np.ascontiguousarray(getattr(xh, f), np.int32) for f in _XH_FIELDS]
+    n = int(idx[0].shape[0])
+    assert all(int(a.shape[0]) == n for a in idx)
+    c3 = [np.zeros(n, np.float32) for _ in range(3)]
+    g3 = [np.zeros(n, np.float64) for _ in range(3)]
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    rc = _lib().or_crosshair_records(len(x), fp(x), fp(y), fp(t), fp(r), fp(g), fp(b), n,
+                                     *(ip(a) for a in idx), float(dt_floor), *(fp(a) for a in c3),
+                                     *(a.ctypes.data_as(_dp) for a in g3))
+    if rc != 0:
+        raise ValueError(f"or_crosshair_records failed ({rc})")
+    return c3, g3
+
+
+def crosshair_buffer(stream, xh, width, height, k, t_ref, dt_floor=1e-3):
+    """The sampler's per-pixel crosshair queues (Sec. 4.1): each crosshair's record is pushed into
+    the queue of its centre pixel, which keeps the ``k`` newest (FP32; gradients in r, g, b).
+    Returns ``(Buffer, dropped)``."""
+    from afr_scenes import Stream
+    (cx, cy, ct), g3 = crosshair_records(stream, xh, dt_floor)
+    rec = Stream(cx, cy, ct, *(a.astype(np.float32) for a in g3))
+    return build_buffer(rec, width, height, k, "fp32", t_ref)
+
+
+def estimate_crosshair(buf: Buffer, xbuf: Buffer, params: Params) -> np.ndarray:
+    """Tile statistics with the gradient planes taken from the crosshair queues ``xbuf`` and the
+    extents recomputed from them (volume, variance and mean luminance from ``buf``)."""
+    stats = estimate(buf, params)
+    rc = _lib().or_crosshair_tiles(ctypes.byref(xbuf._c()), ctypes.byref(params._c()),
+                                   stats.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError(f"or_crosshair_tiles failed ({rc})")
+    return stats

@@ -438,6 +438,133 @@ int or_estimate(const or_buffer *buf, const or_params *p, double *stats)
 }
 
 /* ------------------------------------------------------------------------------------------------
+ * Crosshair gradients (Sec. 4.1). A crosshair is a centre sample at (x, y, t), four samples taken at
+ * the same instant one pixel away, (x -/+ 1, y, t) and (x, y -/+ 1, t), and an earlier sample taken
+ * at the same sub-pixel spot, (x, y, t0). Each is given here as an index into the sample stream
+ * (-1 or any index outside the stream: absent). With L the luminance of a sample:
+ *   horizontal gradient  the mean of |L_c - L_n| over the present horizontal neighbours n (the
+ *                        paper's |L - L_{x+-1}| / 2 read as the average of the two one-sided
+ *                        differences, as for the scattered estimator); likewise vertical;
+ *   temporal gradient    |L_c - L_old| / max(t - t0, dt_floor), defined when t0 < t.
+ * A neighbour or old sample whose luminance is not finite counts as absent; an undefined gradient
+ * is written as -1 (every defined one is >= 0). A crosshair whose centre is absent or has a
+ * non-finite luminance gets a NaN position, so that the queue build drops it.
+ *
+ * Each record carries the centre's position and time; the sampler pushes it into the per-pixel
+ * queue of its deep buffer (Sec. 4.1), which or_build models with the gradients in the colour
+ * fields. Pinned by: a static luminance ramp gives the ramp slopes and a zero temporal gradient;
+ * L = c t at a fixed spot gives |c|; missing neighbours and a later "old" sample are skipped.
+ * --------------------------------------------------------------------------------------------- */
+static int or_index_ok(int32_t i, int64_t n) { return i >= 0 && (int64_t)i < n; }
+
+int or_crosshair_records(int64_t ns, const float *x, const float *y, const float *t, const float *r,
+                         const float *g, const float *b, int64_t nx, const int32_t *centre,
+                         const int32_t *xm, const int32_t *xp, const int32_t *ym,
+                         const int32_t *yp, const int32_t *old, double dt_floor, float *cx,
+                         float *cy, float *ct, double *gx, double *gy, double *gt)
+{
+    for (int64_t i = 0; i < nx; ++i) {
+        const int32_t c = centre[i];
+        gx[i] = gy[i] = gt[i] = -1.0;
+        double Lc = NAN;
+        if (or_index_ok(c, ns))
+            Lc = luminance(r[c], g[c], b[c]);
+        if (!isfinite(Lc)) {
+            cx[i] = cy[i] = ct[i] = NAN;
+            continue;
+        }
+        cx[i] = x[c];
+        cy[i] = y[c];
+        ct[i] = t[c];
+        const int32_t *hn[2] = {xm, xp}, *vn[2] = {ym, yp};
+        double sum = 0.0;
+        int cnt = 0;
+        for (int q = 0; q < 2; ++q) {
+            const int32_t j = hn[q][i];
+            if (!or_index_ok(j, ns))
+                continue;
+            const double L = luminance(r[j], g[j], b[j]);
+            if (isfinite(L)) { sum += fabs(Lc - L); ++cnt; }
+        }
+        if (cnt)
+            gx[i] = sum / cnt;
+        sum = 0.0;
+        cnt = 0;
+        for (int q = 0; q < 2; ++q) {
+            const int32_t j = vn[q][i];
+            if (!or_index_ok(j, ns))
+                continue;
+            const double L = luminance(r[j], g[j], b[j]);
+            if (isfinite(L)) { sum += fabs(Lc - L); ++cnt; }
+        }
+        if (cnt)
+            gy[i] = sum / cnt;
+        const int32_t o = old[i];
+        if (or_index_ok(o, ns)) {
+            const double L0 = luminance(r[o], g[o], b[o]);
+            const double t1 = t[c], t0 = t[o];
+            if (isfinite(L0) && isfinite(t0) && isfinite(t1) && t0 < t1)
+                gt[i] = fabs(Lc - L0) / fmax(t1 - t0, dt_floor);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Tile gradients from a crosshair queue buffer (Sec. 4.1: sample gradients are averaged with the
+ * same age weights as the colour variation of Sec. 4). xbuf holds, per pixel, the newest crosshair
+ * records (FP32 mode: ta is the crosshair time, r/g/b its three gradients, -1 where undefined).
+ *   G_*(T) = sum omega g / sum omega over the tile's records with a defined g, else 0,
+ *   omega = exp(-alpha (t_now - t)).
+ * The volume, variance and mean luminance planes of `stats` (from the sample buffer) are kept; the
+ * three gradient planes are replaced and the extents recomputed from them and stats' volume.
+ * Pinned by closed forms on constructed queues (equal gradients give that gradient for any ages,
+ * two records give the exp-weighted mean, undefined records are skipped).
+ * --------------------------------------------------------------------------------------------- */
+int or_crosshair_tiles(const or_buffer *xbuf, const or_params *p, double *stats)
+{
+    const int W = xbuf->width, H = xbuf->height, K = xbuf->k, B = p->tile;
+    if (B < 1 || W < 1 || H < 1 || xbuf->fp16)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t NT = (size_t)Tx * Ty;
+    for (int ty = 0; ty < Ty; ++ty)
+        for (int tx = 0; tx < Tx; ++tx) {
+            const size_t T = (size_t)ty * Tx + tx;
+            const int i0 = tx * B, i1 = (tx + 1) * B < W ? (tx + 1) * B : W;
+            const int j0 = ty * B, j1 = (ty + 1) * B < H ? (ty + 1) * B : H;
+            double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+            for (int j = j0; j < j1; ++j)
+                for (int i = i0; i < i1; ++i) {
+                    const size_t px = (size_t)j * W + i;
+                    for (int k = 0; k < xbuf->count[px]; ++k) {
+                        const size_t s = px * K + k;
+                        const double w = exp(-p->alpha * (p->t_now - xbuf->ta[s]));
+                        const double gv[3] = {xbuf->r[s], xbuf->g[s], xbuf->b[s]};
+                        for (int c = 0; c < 3; ++c)
+                            if (gv[c] >= 0.0) {
+                                num[c] += w * gv[c];
+                                den[c] += w;
+                            }
+                    }
+                }
+            double g3[3], e5[5];
+            for (int c = 0; c < 3; ++c)
+                g3[c] = den[c] > 0.0 ? num[c] / den[c] : 0.0;
+            or_extents(g3[0], g3[1], g3[2], stats[OR_VOL * NT + T], p, e5);
+            stats[OR_GX * NT + T] = g3[0];
+            stats[OR_GY * NT + T] = g3[1];
+            stats[OR_GT * NT + T] = g3[2];
+            stats[OR_EX2 * NT + T] = e5[0];
+            stats[OR_EY2 * NT + T] = e5[1];
+            stats[OR_SX2 * NT + T] = e5[2];
+            stats[OR_SY2 * NT + T] = e5[3];
+            stats[OR_KT2 * NT + T] = e5[4];
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
  * Gather reconstruction (Sec. 5.2: per pixel, the normalised weighted average of nearby samples;
  * Sec. 5.1: Gaussian filter, axis-aligned in x, y and t, shaped per tile).
  * For pixel p = (i, j) in tile T, every filled slot s of every pixel q with |q_x - i| <= R and
