@@ -113,15 +113,17 @@ class DiscScene:
     With ``highlights`` each disc also carries a Gaussian highlight (sigma 3 px, peak 1.0) centred at
     ``centre + (-r/3, -r/3)``, added to all three channels inside the disc and clipped at 1.
     With ``checker > 0`` the background is instead a static checkerboard of that cell size in px,
-    grey 0.8 where ``floor(x/c) + floor(y/c)`` is even and 0.2 elsewhere.
+    rotated by ``checker_angle`` radians: with ``u = x cos a + y sin a``, ``v = y cos a - x sin a``,
+    grey 0.8 where ``floor(u/c) + floor(v/c)`` is even and 0.2 elsewhere.
     """
 
     def __init__(self, width: int, height: int, rng: np.random.Generator, n_discs: int,
                  t_centre: float, highlights: bool = False, speed: float = 0.5,
                  radius: tuple = (4.0, 24.0), omega: float = OMEGA_RAD_PER_MS,
                  highlight_sigma: float = 3.0, highlight_peak: float = 1.0,
-                 checker: float = 0.0):
+                 checker: float = 0.0, checker_angle: float = 0.0):
         self.checker = float(checker)
+        self.checker_angle = float(checker_angle)
         self.width, self.height = int(width), int(height)
         self.t_centre = float(t_centre)
         self.omega = float(omega)
@@ -136,8 +138,9 @@ class DiscScene:
 
     def background(self, x, y, t):
         if self.checker > 0.0:  # static checkerboard, grey levels 0.2 and 0.8
-            c = self.checker
-            even = (np.floor(x / c) + np.floor(y / c)) % 2 == 0
+            c, ca, sa = self.checker, np.cos(self.checker_angle), np.sin(self.checker_angle)
+            u, v = x * ca + y * sa, y * ca - x * sa
+            even = (np.floor(u / c) + np.floor(v / c)) % 2 == 0
             return np.where(even, 0.8, 0.2) + 0.0 * t
         w, h = self.width, self.height
         half_diag = 0.5 * np.hypot(w, h)
@@ -476,7 +479,8 @@ def crosshair_stream(scene, width: int, height: int, visits: int, t_now: float, 
     away, those outside the image omitted; the earlier sample is the one taken at that spot) and
     starts the next one with a single sample at a new uniform sub-pixel spot (Sec. 4.2, with the
     tile of the paper's sampler narrowed to one pixel). Every sample goes into the stream, which is
-    sorted by time; the crosshair indices refer to the sorted stream.
+    sorted by time; the crosshair indices refer to the sorted stream, and crosshairs are listed in
+    the order they were completed.
 
     Draw order: spot offsets x, y as ``[H, W, visits]``, then visit-time offsets ``[H, W, visits]``.
     """
@@ -523,6 +527,9 @@ def crosshair_stream(scene, width: int, height: int, visits: int, t_now: float, 
     remap = lambda a: np.where(a >= 0, rank[np.maximum(a, 0)], -1).astype(np.int32)
     xh = Crosshairs(remap(ids["centre"]), remap(ids["xm"]), remap(ids["xp"]), remap(ids["ym"]),
                     remap(ids["yp"]), remap(old))
+    # crosshairs in completion order (the order the sampler makes them)
+    by_time = np.argsort(xh.centre, kind="stable")
+    xh = Crosshairs(*(a[by_time] for a in xh.arrays()))
     return s.select(order), xh
 
 
@@ -535,13 +542,14 @@ class CrosshairWorkload:
 
 def make_crosshair_workload(instance: int = 0, width: int = 256, height: int = 256,
                             visits: int = 4, k: int = 16, k_xh: int = 4) -> CrosshairWorkload:
-    """256x256 crosshair-sampled workload: a static 8-px checkerboard (grey 0.2 / 0.8) under 16 discs
+    """256x256 crosshair-sampled workload: a static 8-px checkerboard (grey 0.2 / 0.8, rotated by
+    0.3 rad so that its edges cross pixels at every sub-pixel offset) under 16 discs
     moving at up to 0.2 px/ms, every pixel visited ``visits`` times over a 64 ms window (about 19
     samples per pixel), reconstructor depth ``k`` (FP32), sampler queue depth ``k_xh`` (Sec. 4 uses
     4). Seed 6000 + instance."""
     rng = _rng(6000 + instance)
     t_now, t_win = 64.0, 64.0
-    scene = DiscScene(width, height, rng, 16, t_now, speed=0.2, checker=8.0)
+    scene = DiscScene(width, height, rng, 16, t_now, speed=0.2, checker=8.0, checker_angle=0.3)
     s, xh = crosshair_stream(scene, width, height, visits, t_now, t_win, rng)
     t_ref = float(np.float32(t_now))
     wl = Workload("crosshair", s, width, height, k, "fp32", t_ref, t_ref, scene,

@@ -44,6 +44,7 @@ def _args():
     ap.add_argument("--frames", type=int, default=32, help="frames in the forward+adjoint leg")
     ap.add_argument("--reproject-frames", type=int, default=8,
                     help="frames in the reprojection leg (0 skips it)")
+    ap.add_argument("--no-crosshair", action="store_true", help="skip the crosshair-estimator leg")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
@@ -346,6 +347,8 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(torch, afr, S, dev, args.frames)
+    if not args.no_crosshair:
+        out["crosshair"] = crosshair_leg(torch, afr, S, dev)
     if args.reproject_frames > 0:
         out["reproject"] = reproject_leg(torch, afr, S, dev, args.reproject_frames)
     if args.batch > 0:
@@ -437,6 +440,45 @@ def fwd_bwd(torch, afr, S, dev, frames):
     torch.cuda.synchronize()
     return {"workload": "512x512 K=8 FP32, %d frames at 60 Hz" % frames,
             "ms_per_frame": round(e0.elapsed_time(e1) / frames, 5)}
+
+
+def crosshair_leg(torch, afr, S, dev, reps=20):
+    """Crosshair gradient estimator on the 256x256 crosshair-sampled workload (static checkerboard
+    under moving discs): RMS error against the analytic ground truth of the gather with the
+    scattered-sample statistics and with the crosshair statistics, the mean temporal gradient and
+    the share of tiles with none, and the time of the crosshair queue build and estimate."""
+    cw = S.make_crosshair_workload()
+    wl, xh = cw.workload, cw.crosshairs
+    W, H, K = wl.width, wl.height, wl.k
+    s = [torch.from_numpy(a).to(dev) for a in wl.stream.arrays()]
+    ids = [torch.from_numpy(a).to(dev) for a in xh.arrays()]
+    p = afr.Params(t_now=wl.t_now)
+    buf, _ = afr.build_deep_buffer(*s, W, H, K, "fp32", wl.t_ref)
+    xbuf, drop = afr.build_crosshair_buffer(s, ids, W, H, cw.k_xh, p, wl.t_ref)
+    st0 = afr.estimate_gradients(buf, p)
+    st1 = afr.estimate_gradients_crosshair(buf, xbuf, p)
+    gt = torch.from_numpy(S.ground_truth(wl.scene, W, H, wl.t_now, 4)).float().to(dev)
+    rms = lambda st: float(torch.sqrt(((afr.reconstruct(buf, st, p)[0] - gt) ** 2).mean()).item())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        afr.build_crosshair_buffer(s, ids, W, H, cw.k_xh, p, wl.t_ref, out=xbuf, dropped=drop)
+    ev[1].record()
+    for _ in range(reps):
+        afr.estimate_gradients_crosshair(buf, xbuf, p, out=st1)
+    ev[2].record()
+    torch.cuda.synchronize()
+    g0, g1 = st0[afr.STAT["gt"]], st1[afr.STAT["gt"]]
+    return {"workload": "256x256 crosshair sampling, 4 visits/px over 64 ms (%d samples, %d "
+                        "crosshairs), K=%d, crosshair queue depth %d, FP32"
+                        % (len(wl.stream), len(xh), K, cw.k_xh),
+            "rms_scattered": round(rms(st0), 6), "rms_crosshair": round(rms(st1), 6),
+            "mean_gt_scattered": float(g0.mean().item()), "mean_gt_crosshair": float(g1.mean().item()),
+            "zero_gt_tiles_scattered": round(float((g0 == 0).float().mean().item()), 4),
+            "zero_gt_tiles_crosshair": round(float((g1 == 0).float().mean().item()), 4),
+            "crosshair_build_ms": round(ev[0].elapsed_time(ev[1]) / reps, 5),
+            "crosshair_estimate_ms": round(ev[1].elapsed_time(ev[2]) / reps, 5)}
 
 
 def reproject_leg(torch, afr, S, dev, frames, reps=5):

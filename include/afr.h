@@ -178,6 +178,55 @@ afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *
                                   afr_tile_stats *out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Crosshair gradients (Sec. 4.1, 4.2). A crosshair is a centre sample at (x, y, t), the four samples
+ * taken at the same instant one pixel away, (x -/+ 1, y, t) and (x, y -/+ 1, t), and an earlier
+ * sample taken at the same sub-pixel spot, (x, y, t0). afr_crosshairs gives each as a device int32
+ * index into a sample stream; -1 (or any index outside the stream) marks an absent sample.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct afr_crosshairs {
+    const int32_t *centre;   /* [n] centre sample                                                 */
+    const int32_t *xm, *xp;  /* [n] neighbours at x - 1 and x + 1                                 */
+    const int32_t *ym, *yp;  /* [n] neighbours at y - 1 and y + 1                                 */
+    const int32_t *old;      /* [n] the earlier sample at the centre's sub-pixel spot             */
+    int64_t n;               /* number of crosshairs, < 2^31                                      */
+} afr_crosshairs;
+
+/* The sampler's crosshair queues. Per crosshair, with L the luminance of a sample (Rec. 709):
+ *   gx = mean of |L_c - L_n| over the present horizontal neighbours with finite L (else -1),
+ *   gy likewise over the vertical ones,
+ *   gt = |L_c - L_old| / max(t - t0, params->dt_floor) when the old sample is present, its L and
+ *        time are finite and t0 < t (else -1),
+ * computed in FP64 and stored as float. Each crosshair record (the centre's x, y, t and the three
+ * gradients) is pushed into the queue of the centre's pixel exactly as afr_build_deep_buffer pushes
+ * samples: `out` receives, per pixel, the newest min(K, arrivals) records, with the gradients in the
+ * r, g, b planes (gx, gy, gt) and the centre time in tage. A crosshair whose centre is absent or has a
+ * non-finite luminance, or whose record is invalid by the build's rule, is dropped.
+ *
+ *   s, xh        device sample stream (velocities ignored) and crosshairs
+ *   params       only dt_floor is used (validated like afr_estimate_gradients, without t_now)
+ *   out          AFR_FP32 only (AFR_E_UNSUPPORTED otherwise); geometry, K and t_ref as for a build
+ *   ws, ws_bytes device workspace of at least afr_crosshair_workspace_bytes(xh->n, width, height)
+ *   dropped_dev  optional device int64: receives the number of dropped crosshairs
+ */
+size_t afr_crosshair_workspace_bytes(int64_t n, int32_t width, int32_t height);
+afr_status afr_build_crosshair_buffer(const afr_samples *s, const afr_crosshairs *xh,
+                                      const afr_params *params, afr_deep_buffer *out, void *ws,
+                                      size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream);
+
+/* Tile statistics with crosshair gradients: everything afr_estimate_gradients computes from `buf`,
+ * then the three gradient planes replaced by the age-weighted means over the tile's crosshair
+ * records in `xbuf` (Sec. 4.1 with the age weights of Sec. 4),
+ *   G(T) = sum omega g / sum omega over the records with g >= 0 (0 if none),
+ *   omega = exp(-alpha (t_now - t)),
+ * and the extents recomputed from them and the tile's volume V (as stored in out, float). xbuf must
+ * be an AFR_FP32 buffer of buf's width and height made by afr_build_crosshair_buffer, with
+ * params->t_now >= xbuf->t_ref. */
+afr_status afr_estimate_gradients_crosshair(const afr_deep_buffer *buf,
+                                            const afr_deep_buffer *xbuf,
+                                            const afr_params *params, afr_tile_stats *out,
+                                            hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Adaptive space-time gather (Sec. 5.1 Gaussian filter, Sec. 5.2 normalised weighted average).
  *
  * Pixel p = (i, j) in tile T gathers every filled slot s of the pixels q with |q_x - i| <= R and

@@ -21,7 +21,7 @@ __all__ = [
     "AfrError", "Params", "DeepBuffer", "STAT_NAMES", "NSTAT", "STAT", "library", "lib_path",
     "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
-    "reconstruct_tune", "Batch",
+    "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +43,12 @@ class _Samples(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("r", ctypes.c_void_p), ("g", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p)]
+
+
+class _Crosshairs(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_void_p), ("xm", ctypes.c_void_p), ("xp", ctypes.c_void_p),
+                ("ym", ctypes.c_void_p), ("yp", ctypes.c_void_p), ("old", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
 
 
 class _DeepBuffer(ctypes.Structure):
@@ -104,6 +110,14 @@ def library():
                                                  vp, vp, P(vp)]
     lib.afr_estimate_gradients.restype = st
     lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
+    lib.afr_crosshair_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_crosshair_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    lib.afr_build_crosshair_buffer.restype = st
+    lib.afr_build_crosshair_buffer.argtypes = [P(_Samples), P(_Crosshairs), P(_Params),
+                                               P(_DeepBuffer), vp, ctypes.c_size_t, vp, vp]
+    lib.afr_estimate_gradients_crosshair.restype = st
+    lib.afr_estimate_gradients_crosshair.argtypes = [P(_DeepBuffer), P(_DeepBuffer), P(_Params),
+                                                     P(_TileStats), vp]
     for name in ("afr_reconstruct", "afr_reconstruct_plain"):
         f = getattr(lib, name)
         f.restype = st
@@ -326,6 +340,63 @@ def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tens
     bc, pc, sc = buf._c(colours), params._c(), _stats_c(out, params.tile)
     _check(lib.afr_estimate_gradients(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc),
                                       _stream(stream)), "afr_estimate_gradients")
+    return out
+
+
+def build_crosshair_buffer(samples, crosshairs, width: int, height: int, k: int, params: Params,
+                           t_ref: float, out: Optional[DeepBuffer] = None, stream=None,
+                           dropped: Optional[torch.Tensor] = None):
+    """The sampler's per-pixel crosshair queues (FP32; gradients gx, gy, gt in the r, g, b planes).
+
+    ``samples``: the six float32 device arrays (x, y, t, r, g, b) of the stream; ``crosshairs``:
+    six int32 device arrays (centre, xm, xp, ym, yp, old) of stream indices, -1 where absent.
+    Returns ``(buffer, dropped)``."""
+    lib = library()
+    xs = list(samples)
+    ids = list(crosshairs)
+    if len(xs) != 6 or len(ids) != 6:
+        raise AfrError("samples are (x, y, t, r, g, b) and crosshairs (centre, xm, xp, ym, yp, old)")
+    n = int(xs[0].shape[0])
+    nx = int(ids[0].shape[0])
+    dev = xs[0].device
+    for a in xs:
+        if (a.dtype != torch.float32 or not a.is_cuda or a.dim() != 1 or not a.is_contiguous()
+                or int(a.shape[0]) != n or a.device != dev):
+            raise AfrError("sample arrays must be contiguous 1-D float32 device tensors of one length")
+    for a in ids:
+        if (a.dtype != torch.int32 or not a.is_cuda or a.dim() != 1 or not a.is_contiguous()
+                or int(a.shape[0]) != nx or a.device != dev):
+            raise AfrError("crosshair arrays must be contiguous 1-D int32 device tensors of one length")
+    if out is None:
+        out = DeepBuffer(width, height, k, "fp32", t_ref, device=dev)
+    else:
+        out.t_ref = float(t_ref)
+    if dropped is None:
+        dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc = _Samples(*(a.data_ptr() if n else None for a in xs), n)
+    xc = _Crosshairs(*(a.data_ptr() if nx else None for a in ids), nx)
+    wsb = lib.afr_crosshair_workspace_bytes(nx, width, height)
+    ws = _workspace(wsb, dev, "crosshair")
+    bc, pc = out._c(), params._c()
+    _check(lib.afr_build_crosshair_buffer(ctypes.byref(sc), ctypes.byref(xc), ctypes.byref(pc),
+                                          ctypes.byref(bc), _ptr(ws), wsb, _ptr(dropped),
+                                          _stream(stream)), "afr_build_crosshair_buffer")
+    return out, dropped
+
+
+def estimate_gradients_crosshair(buf: DeepBuffer, xbuf: DeepBuffer, params: Params,
+                                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Tile statistics of ``buf`` with the gradient planes (and the extents) taken from the
+    crosshair queues ``xbuf``."""
+    lib = library()
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    if out is None:
+        out = torch.empty((NSTAT, ty, tx), dtype=torch.float32, device=buf.planes.device)
+    bc, xc, pc, sc = buf._c(), xbuf._c(), params._c(), _stats_c(out, params.tile)
+    _check(lib.afr_estimate_gradients_crosshair(ctypes.byref(bc), ctypes.byref(xc),
+                                                ctypes.byref(pc), ctypes.byref(sc),
+                                                _stream(stream)),
+           "afr_estimate_gradients_crosshair")
     return out
 
 

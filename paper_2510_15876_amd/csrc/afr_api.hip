@@ -73,6 +73,44 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
     return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, stage_end);
 }
 
+size_t afr_crosshair_workspace_bytes(int64_t n, int32_t width, int32_t height) {
+    if (n < 0 || width < 1 || height < 1) return 0;
+    return crosshair_ws_bytes(n, width, height);
+}
+
+afr_status afr_build_crosshair_buffer(const afr_samples *s, const afr_crosshairs *xh,
+                                      const afr_params *params, afr_deep_buffer *out, void *ws,
+                                      size_t ws_bytes, int64_t *dropped_dev, hipStream_t stream) {
+    AFR_TRY(check_buffer(out));
+    AFR_TRY(check_params(params, nullptr));
+    if (!s || s->n < 0 || !xh || xh->n < 0) return AFR_E_INVALID;
+    if (s->n >= (int64_t(1) << 31) || xh->n >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    if (s->n > 0 && (!s->x || !s->y || !s->t || !s->r || !s->g || !s->b)) return AFR_E_INVALID;
+    if (xh->n > 0 && (!xh->centre || !xh->xm || !xh->xp || !xh->ym || !xh->yp || !xh->old))
+        return AFR_E_INVALID;
+    if (!ws) return AFR_E_INVALID;
+    if (out->precision != AFR_FP32) return AFR_E_UNSUPPORTED;
+    if (!build_supported(out->width, out->height)) return AFR_E_UNSUPPORTED;
+    if (ws_bytes < crosshair_ws_bytes(xh->n, out->width, out->height)) return AFR_E_NOMEM;
+    return from_hip(launch_crosshair_build(*s, *xh, *params, *out, ws,
+                                           reinterpret_cast<unsigned long long *>(dropped_dev),
+                                           stream));
+}
+
+afr_status afr_estimate_gradients_crosshair(const afr_deep_buffer *buf,
+                                            const afr_deep_buffer *xbuf,
+                                            const afr_params *params, afr_tile_stats *out,
+                                            hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_buffer(xbuf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_params(params, xbuf));
+    AFR_TRY(check_stats(out, buf, params));
+    if (xbuf->precision != AFR_FP32) return AFR_E_UNSUPPORTED;
+    if (xbuf->width != buf->width || xbuf->height != buf->height) return AFR_E_INVALID;
+    return from_hip(launch_crosshair_estimate(*buf, *xbuf, *params, *out, stream));
+}
+
 afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *params,
                                   afr_tile_stats *out, hipStream_t stream) {
     AFR_TRY(check_buffer(buf));

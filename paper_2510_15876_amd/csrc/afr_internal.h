@@ -188,6 +188,14 @@ hipError_t launch_reconstruct_tiled(const afr_deep_buffer &buf, const afr_tile_s
                                     const afr_params &p, int tiles_per_wave, float *rgb, float *aux,
                                     hipStream_t st);
 
+size_t crosshair_ws_bytes(int64_t n, int32_t w, int32_t h);
+hipError_t launch_crosshair_build(const afr_samples &s, const afr_crosshairs &xh,
+                                  const afr_params &prm, const afr_deep_buffer &out, void *ws,
+                                  unsigned long long *dropped_or_null, hipStream_t st);
+hipError_t launch_crosshair_estimate(const afr_deep_buffer &buf, const afr_deep_buffer &xbuf,
+                                     const afr_params &prm, const afr_tile_stats &out,
+                                     hipStream_t st);
+
 size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                            const afr_params &p, const float *rgb, const float *aux,

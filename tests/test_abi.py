@@ -132,3 +132,31 @@ def test_stats_geometry_and_workspace_checks(afr):
     evs = (ctypes.c_void_p * 4)(0x10, 0x20, None, 0x40)
     assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, evs) == 1
     assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, None) == 1
+
+
+def test_crosshair_validation(afr):
+    """The crosshair calls fail validation before anything is launched: FP16 queues, missing index
+    arrays, a small workspace, and a queue whose geometry differs from the sample buffer."""
+    lib = afr.library()
+    p = afr.Params(t_now=11.0)._c()
+    s = afr._Samples(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 1000)
+    xh = afr._Crosshairs(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 500)
+    need = lib.afr_crosshair_workspace_bytes(500, 16, 8)
+    assert need >= 6 * 500 * 4 + lib.afr_build_workspace_bytes(500, 16, 8, 4)
+    b16 = _fake_buffer(afr, prec=1)
+    assert lib.afr_build_crosshair_buffer(ctypes.byref(s), ctypes.byref(xh), ctypes.byref(p), ctypes.byref(b16), 0x4000, need, None, None) == 5
+    b = _fake_buffer(afr)
+    assert lib.afr_build_crosshair_buffer(ctypes.byref(s), ctypes.byref(xh), ctypes.byref(p), ctypes.byref(b), 0x4000, need - 1, None, None) == 4
+    no_old = afr._Crosshairs(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None, 500)
+    assert lib.afr_build_crosshair_buffer(ctypes.byref(s), ctypes.byref(no_old), ctypes.byref(p), ctypes.byref(b), 0x4000, need, None, None) == 1
+    neg = afr._Crosshairs(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, -1)
+    assert lib.afr_build_crosshair_buffer(ctypes.byref(s), ctypes.byref(neg), ctypes.byref(p), ctypes.byref(b), 0x4000, need, None, None) == 1
+    bad_p = afr.Params(t_now=11.0, dt_floor=0.0)._c()
+    assert lib.afr_build_crosshair_buffer(ctypes.byref(s), ctypes.byref(xh), ctypes.byref(bad_p), ctypes.byref(b), 0x4000, need, None, None) == 2
+    # estimate: the queue must be FP32 and of the sample buffer's size
+    st = afr._TileStats(8, 2, 1, 0x1000)
+    other = _fake_buffer(afr, w=24)
+    assert lib.afr_estimate_gradients_crosshair(ctypes.byref(b), ctypes.byref(other), ctypes.byref(p), ctypes.byref(st), None) == 1
+    assert lib.afr_estimate_gradients_crosshair(ctypes.byref(b), ctypes.byref(b16), ctypes.byref(p), ctypes.byref(st), None) == 5
+    late = afr.Params(t_now=9.0)._c()   # before the buffers' t_ref
+    assert lib.afr_estimate_gradients_crosshair(ctypes.byref(b), ctypes.byref(b), ctypes.byref(late), ctypes.byref(st), None) == 2
