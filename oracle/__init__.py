@@ -54,6 +54,12 @@ class _Buffer(ctypes.Structure):
                 ("count", ctypes.POINTER(ctypes.c_uint8)), ("src", ctypes.POINTER(ctypes.c_int32))]
 
 
+class _Splat(ctypes.Structure):
+    _fields_ = [("size_default", ctypes.c_float), ("size_min", ctypes.c_float),
+                ("size_max", ctypes.c_float), ("grow", ctypes.c_float), ("shrink", ctypes.c_float),
+                ("n_low", ctypes.c_int), ("n_high", ctypes.c_int)]
+
+
 _lib_handle = None
 
 
@@ -85,6 +91,12 @@ def _lib():
                                              + [ip] * 6 + [ctypes.c_double] + [fp] * 3 + [_dp] * 3)
         lib.or_crosshair_tiles.restype = ctypes.c_int
         lib.or_crosshair_tiles.argtypes = [ctypes.POINTER(_Buffer), ctypes.POINTER(_Params), _dp]
+        lib.or_scatter.restype = ctypes.c_int
+        lib.or_scatter.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params), fp,
+                                   ctypes.c_float, _dp, _dp, fp, fp]
+        lib.or_splat_sizes.restype = None
+        lib.or_splat_sizes.argtypes = [ctypes.c_int, ctypes.c_int, fp, fp,
+                                       ctypes.POINTER(_Splat), fp]
         _lib_handle = lib
     return _lib_handle
 
@@ -305,3 +317,53 @@ def estimate_crosshair(buf: Buffer, xbuf: Buffer, params: Params) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"or_crosshair_tiles failed ({rc})")
     return stats
+
+
+# ---- scatter form and adaptive splat size (Sec. 5.2, 6.2) ----------------------------------------
+
+@dataclass
+class SplatParams:
+    """Adaptive splat size (Sec. 6.2): grow 4x below 4 splats per pixel, shrink 0.7x above 32.
+    Sizes are splat edge lengths in px; the defaults start at the gather's 5 x 5 block."""
+    size_default: float = 5.0
+    size_min: float = 1.0
+    size_max: float = 16.0
+    grow: float = 4.0
+    shrink: float = 0.7
+    n_low: int = 4
+    n_high: int = 32
+
+    def _c(self) -> _Splat:
+        return _Splat(self.size_default, self.size_min, self.size_max, self.grow, self.shrink,
+                      int(self.n_low), int(self.n_high))
+
+
+def splat_sizes(width, height, coverage, sp: SplatParams) -> np.ndarray:
+    """Per-pixel splat size [H, W] float32 for the next image from this image's coverage map
+    ``(n, mean size)`` (each [H, W] float32), or from nothing (``coverage=None``: the first image)."""
+    fp = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    n = sz = None
+    if coverage is not None:
+        n, sz = (np.ascontiguousarray(a, np.float32) for a in coverage)
+    out = np.zeros((height, width), np.float32)
+    _lib().or_splat_sizes(int(width), int(height), fp(n), fp(sz), ctypes.byref(sp._c()), fp(out))
+    return out
+
+
+def scatter(buf: Buffer, stats: np.ndarray, params: Params, size, max_size: float):
+    """Scatter-form image: ``(rgb [3,H,W], aux [2,H,W], (n, mean size))`` with per-source-pixel splat
+    sizes ``size`` [H, W] (see or_scatter)."""
+    stats = np.ascontiguousarray(stats, np.float64)
+    size = np.ascontiguousarray(size, np.float32)
+    H, W = buf.height, buf.width
+    rgb = np.zeros((3, H, W), np.float64)
+    aux = np.zeros((2, H, W), np.float64)
+    n = np.zeros((H, W), np.float32)
+    ms = np.zeros((H, W), np.float32)
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    rc = _lib().or_scatter(ctypes.byref(buf._c()), stats.ctypes.data_as(_dp),
+                           ctypes.byref(params._c()), fp(size), float(max_size),
+                           rgb.ctypes.data_as(_dp), aux.ctypes.data_as(_dp), fp(n), fp(ms))
+    if rc:
+        raise ValueError(f"or_scatter failed ({rc})")
+    return rgb, aux, (n, ms)

@@ -767,3 +767,149 @@ int or_backward(const or_buffer *buf, const double *stats, const or_params *p,
     grad_params[1] = g_tau;
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------------
+ * Scatter reconstruction (Sec. 5.2: every buffered sample is splatted onto the image and adds its
+ * filter-weighted colour and its weight to each pixel its splat covers; the image is the ratio of
+ * the two sums). A sample of home pixel q = (q_x, q_y) with offsets (ox, oy) and splat size
+ * size[q] (Sec. 6.2: all samples of a region share the region's splat size) covers pixel p when
+ *   |d_x| <= h and |d_y| <= h,  d_x = ((q_x - p_x) - 1/2) + ox,  d_y likewise,  h = min(size, max)/2
+ * with d and h evaluated in binary32 (an integer decision, so it is taken in the precision of the
+ * GPU form). Its exponent at p uses p's tile parameters, as the fragment program of Sec. 5.2 reads
+ * the tile texture at the fragment:
+ *   E = -1/2 (d_x^2 / sx2 + d_y^2 / sy2 + a^2 kt2).
+ * Per pixel, C_p = sum exp(E - E_max) c / W', W' = sum exp(E - E_max), aux = (E_max, W'), as for the
+ * gather; a pixel no splat covers is 0 with aux (0, 0). The coverage map records, per pixel, the
+ * number n of splats that covered it and their mean size (0 if n = 0): sizes are counted in
+ * units of 1/256 px (round(256 size), exact for the sizes or_splat_sizes makes), the integer sum
+ * of units is exact, and the mean is (float(units) / n) / 256 in binary32.
+ * The two passes (maxima, then sums) follow the splat loop over samples.
+ * Pinned by: with size 2R + 1 and offsets inside (0, 1) the covered set is the gather's block and
+ * the image equals or_reconstruct; a lone sample paints exactly its footprint with its colour;
+ * coverage counts on regular sample grids have closed forms.
+ * --------------------------------------------------------------------------------------------- */
+static int or_covers(int q, int p, double o, float h, double *d)
+{
+    volatile float dq = (float)(q - p) - 0.5f;
+    volatile float df = dq + (float)o;
+    *d = df;
+    return fabsf(df) <= h;
+}
+
+int or_scatter(const or_buffer *buf, const double *stats, const or_params *p, const float *size,
+               float max_size, double *rgb, double *aux, float *cov_n, float *cov_size)
+{
+    const int W = buf->width, H = buf->height, K = buf->k, B = p->tile;
+    if (B < 1 || !(max_size > 0.0f))
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty;
+    double *emax = (double *)malloc(sizeof(double) * HW * 5);
+    int64_t *units = (int64_t *)malloc(sizeof(int64_t) * HW);
+    if (!emax || !units) {
+        free(emax);
+        free(units);
+        return 4;
+    }
+    double *ws = emax + HW, *cr = emax + 2 * HW, *cg = emax + 3 * HW, *cb = emax + 4 * HW;
+    for (size_t i = 0; i < HW; ++i) {
+        emax[i] = -INFINITY;
+        ws[i] = cr[i] = cg[i] = cb[i] = 0.0;
+        units[i] = 0;
+        cov_n[i] = 0.0f;
+    }
+    const int reach = (int)ceil(0.5 * max_size + 0.5) + 1;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int qy = 0; qy < H; ++qy)
+            for (int qx = 0; qx < W; ++qx) {
+                const size_t q = (size_t)qy * W + qx;
+                const float sz = fminf(size[q], max_size);
+                volatile float h = 0.5f * sz;
+                for (int k = 0; k < buf->count[q]; ++k) {
+                    const size_t s = q * K + k;
+                    const double a = slot_age(buf, p, s);
+                    for (int py = qy - reach; py <= qy + reach; ++py) {
+                        double dy;
+                        if (py < 0 || py >= H || !or_covers(qy, py, buf->oy[s], h, &dy))
+                            continue;
+                        for (int px = qx - reach; px <= qx + reach; ++px) {
+                            double dx;
+                            if (px < 0 || px >= W || !or_covers(qx, px, buf->ox[s], h, &dx))
+                                continue;
+                            const size_t o = (size_t)py * W + px;
+                            const size_t T = (size_t)(py / B) * Tx + (px / B);
+                            const double sx2 = stats[OR_SX2 * NT + T];
+                            const double sy2 = stats[OR_SY2 * NT + T];
+                            const double kt2 = stats[OR_KT2 * NT + T];
+                            /* the exponent from the exact offsets, not the binary32 test values */
+                            const double ex = (qx - px - 0.5) + buf->ox[s];
+                            const double ey = (qy - py - 0.5) + buf->oy[s];
+                            const double E = -0.5 * (ex * ex / sx2 + ey * ey / sy2 + a * a * kt2);
+                            if (pass == 0) {
+                                if (E > emax[o]) emax[o] = E;
+                                cov_n[o] += 1.0f;
+                                units[o] += (int64_t)rintf(256.0f * sz);
+                            } else {
+                                const double w = exp(E - emax[o]);
+                                ws[o] += w;
+                                cr[o] += w * buf->r[s];
+                                cg[o] += w * buf->g[s];
+                                cb[o] += w * buf->b[s];
+                            }
+                        }
+                    }
+                }
+            }
+    for (size_t i = 0; i < HW; ++i) {
+        if (cov_n[i] > 0.0f) {
+            rgb[i] = cr[i] / ws[i];
+            rgb[HW + i] = cg[i] / ws[i];
+            rgb[2 * HW + i] = cb[i] / ws[i];
+            aux[i] = emax[i];
+            aux[HW + i] = ws[i];
+            volatile float m = (float)units[i] / cov_n[i];
+            cov_size[i] = m * 0.00390625f;
+        } else {
+            rgb[i] = rgb[HW + i] = rgb[2 * HW + i] = 0.0;
+            aux[i] = aux[HW + i] = 0.0;
+            cov_size[i] = 0.0f;
+        }
+    }
+    free(emax);
+    free(units);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Adaptive splat size (Sec. 6.2). The splat size of pixel q for the next image is the mean size of
+ * the splats that reached q in the previous image, multiplied by `grow` where fewer than n_low
+ * splats reached it (undersampled: grow fast) and by `shrink` where more than n_high did
+ * (oversampled: shrink gradually); with no splat at all, or no previous image, the base is
+ * `size_default`. The result is clamped to [size_min, size_max] and rounded to a multiple of
+ * 1/256 px (ties to even), all in binary32, so that sizes are exact and coverage sums of them too.
+ * Pinned by the rule's cases (n = 0, n < n_low, n_low <= n <= n_high, n > n_high, the clamps).
+ * --------------------------------------------------------------------------------------------- */
+typedef struct {
+    float size_default, size_min, size_max, grow, shrink;
+    int n_low, n_high;
+} or_splat;
+
+void or_splat_sizes(int W, int H, const float *cov_n, const float *cov_size, const or_splat *sp,
+                    float *size)
+{
+    for (size_t i = 0; i < (size_t)W * H; ++i) {
+        volatile float v = sp->size_default;
+        if (cov_n && cov_size) {
+            const float n = cov_n[i];
+            if (n > 0.0f)
+                v = cov_size[i];
+            if (n < (float)sp->n_low)
+                v = v * sp->grow;
+            else if (n > (float)sp->n_high)
+                v = v * sp->shrink;
+        }
+        v = fminf(fmaxf(v, sp->size_min), sp->size_max);
+        volatile float u = v * 256.0f;
+        size[i] = rintf(u) * 0.00390625f;
+    }
+}
