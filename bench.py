@@ -291,6 +291,28 @@ def main():
     pe[1].record()
     torch.cuda.synchronize()
     plain_ms = pe[0].elapsed_time(pe[1]) / n_plain
+
+    # scatter form on the same buffers: splats of the gather's block size, then the sizes the
+    # adaptive rule settles on after a few images of the same buffer
+    sp = afr.SplatParams()
+    size = afr.splat_sizes(W, H, None, sp, device=dev)
+    cov = torch.empty((2, H, W), device=dev)
+    scatter_ms = {}
+    for label in ("block", "adaptive"):
+        if label == "adaptive":
+            for _ in range(4):
+                afr.reconstruct_scatter(bufs[0], stats[0], p, size, sp.size_max, rgb=rgb_plain,
+                                        want_aux=False, coverage=cov)
+                afr.splat_sizes(W, H, cov, sp, out=size)
+        torch.cuda.synchronize()
+        pe[0].record()
+        for i in range(n_plain):
+            afr.reconstruct_scatter(bufs[i % ROTATE], stats[i % ROTATE], p, size, sp.size_max,
+                                    rgb=rgb_plain, want_aux=False, coverage=cov)
+        pe[1].record()
+        torch.cuda.synchronize()
+        scatter_ms[label] = round(pe[0].elapsed_time(pe[1]) / n_plain, 5)
+    scatter_ms["adaptive_mean_size"] = round(float(size.mean().item()), 4)
     fwd_ms = stage_ms["estimate"] + stage_ms["gather"]
 
     out = {
@@ -316,6 +338,7 @@ def main():
         "samples_filtered_per_s": round(occupied / (fwd_ms * 1e-3), 1),
         "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
         "plain_reconstruct_ms": round(plain_ms, 5),
+        "scatter_reconstruct_ms": scatter_ms,
         "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": round(dom_gbs, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": dom_bytes,
@@ -484,13 +507,18 @@ def crosshair_leg(torch, afr, S, dev, reps=20):
 def reproject_leg(torch, afr, S, dev, frames, reps=5):
     """Reconstructor reprojection on the 512x512, K=8, FP32 sequence: per frame, the RMS error against
     the analytic ground truth of the full forward with and without advecting samples by their
-    surface velocity, and the build time of each."""
+    surface velocity, and the build time of each; on the reprojected buffers also the scatter form
+    with the adaptive splat size carried from frame to frame, and the holes (pixels no sample
+    reaches) of each form."""
     seq = S.make_c4_sequence(n_frames=frames)
     W, H, K = seq.width, seq.height, seq.k
     buf = afr.DeepBuffer(W, H, K, "fp32", 0.0, device=dev)
     drop = torch.zeros(1, dtype=torch.int64, device=dev)
     rms = {False: [], True: []}
     build_ms = {False: [], True: []}
+    rms_scatter, holes_gather, holes_scatter = [], [], []
+    sp = afr.SplatParams()
+    cov = None
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for f in range(frames):
         wl = seq.frame_workload(f)
@@ -509,14 +537,24 @@ def reproject_leg(torch, afr, S, dev, frames, reps=5):
             torch.cuda.synchronize()
             build_ms[rep].append(ev[0].elapsed_time(ev[1]) / reps)
             st = afr.estimate_gradients(buf, p)
-            rgb, _ = afr.reconstruct(buf, st, p)
+            rgb, aux = afr.reconstruct(buf, st, p)
             rms[rep].append(float(torch.sqrt(((rgb - gt) ** 2).mean()).item()))
+            if rep:  # the scatter form with adaptive splat size on the reprojected buffer
+                size = afr.splat_sizes(W, H, cov, sp, device=dev)
+                srgb, _, cov = afr.reconstruct_scatter(buf, st, p, size, sp.size_max,
+                                                       want_aux=False)
+                rms_scatter.append(float(torch.sqrt(((srgb - gt) ** 2).mean()).item()))
+                holes_gather.append(int((aux[1] == 0).sum().item()))
+                holes_scatter.append(int((cov[0] == 0).sum().item()))
     return {"workload": "512x512 K=8 FP32, %d frames at 60 Hz, 64 discs with analytic velocities"
                         % frames,
             "rms_plain": round(float(np.mean(rms[False])), 6),
             "rms_reprojected": round(float(np.mean(rms[True])), 6),
             "build_ms_plain": round(float(np.mean(build_ms[False])), 5),
-            "build_ms_reprojected": round(float(np.mean(build_ms[True])), 5)}
+            "build_ms_reprojected": round(float(np.mean(build_ms[True])), 5),
+            "rms_reprojected_scatter_adaptive": round(float(np.mean(rms_scatter)), 6),
+            "holes_per_frame_gather": float(np.mean(holes_gather)),
+            "holes_per_frame_scatter_adaptive": float(np.mean(holes_scatter))}
 
 
 if __name__ == "__main__":

@@ -178,6 +178,46 @@ afr_status afr_estimate_gradients(const afr_deep_buffer *buf, const afr_params *
                                   afr_tile_stats *out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Scatter form (Sec. 5.2) with adaptive splat size (Sec. 6.2).
+ *
+ * Every filled slot s of pixel q is a splat: a square of edge size[q] (px) centred on the sample,
+ * covering output pixel p when |d_x| <= h and |d_y| <= h, with
+ *   d_x = ((q_x - p_x) - 1/2) + ox_s,  d_y = ((q_y - p_y) - 1/2) + oy_s,  h = min(size[q], max_size)/2
+ * evaluated in binary32 (all samples of a pixel share its splat size, as the samples of a region do
+ * in the paper). At p the splat has exponent E = -1/2 (d_x^2 / sx2 + d_y^2 / sy2 + a^2 kt2) with p's
+ * tile parameters, and C_p = sum exp(E - E_max) c / W', W' = sum exp(E - E_max) over the covering
+ * splats; aux = (E_max, W'); a pixel no splat covers is 0 with aux (0, 0). With size 2R + 1 every
+ * sample whose offsets lie strictly inside (0, 1) covers exactly the pixels whose gather block
+ * holds it, so the image equals afr_reconstruct's. The coverage map holds, per pixel, the number n
+ * of covering splats and their mean size (0 if none), taken as (float(sum of round(256 size)) / n)
+ * / 256 in binary32. Colour sums are accumulated with atomics: their last bits may differ from run
+ * to run; footprints, counts and mean sizes are exact.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct afr_splat_params {
+    float size_default;  /* size without a previous image, or where no splat arrived, px [5]      */
+    float size_min, size_max;  /* clamp of the sizes, px [1, 16]; 0 < min <= default <= max <= 64 */
+    float grow;          /* factor where fewer than n_low splats arrived [4]; >= 1                  */
+    float shrink;        /* factor where more than n_high splats arrived [0.7]; in (0, 1]          */
+    int32_t n_low, n_high; /* [4, 32]; 0 <= n_low <= n_high                                        */
+} afr_splat_params;
+
+/* Splat sizes for the next image from this image's coverage map (Sec. 6.2): the mean size of the
+ * splats that reached the pixel (size_default where none did), times grow where n < n_low or
+ * shrink where n > n_high, clamped to [size_min, size_max] and rounded to a multiple of 1/256 px
+ * (binary32, ties to even).
+ *   coverage  device [2][H][W] (n, mean size) from afr_reconstruct_scatter, or NULL: the first image
+ *   size      device [H][W] output */
+afr_status afr_splat_sizes(int32_t width, int32_t height, const float *coverage,
+                           const afr_splat_params *params, float *size, hipStream_t stream);
+
+/*   size      device [H][W] splat edge per source pixel, px (values above max_size count as max_size)
+ *   max_size  largest splat edge, px, in (0, 64]; it bounds how far a splat reaches
+ *   rgb       device [3][H][W];  aux  device [2][H][W] or NULL;  coverage  device [2][H][W] or NULL */
+afr_status afr_reconstruct_scatter(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                   const afr_params *params, const float *size, float max_size,
+                                   float *rgb, float *aux, float *coverage, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Crosshair gradients (Sec. 4.1, 4.2). A crosshair is a centre sample at (x, y, t), the four samples
  * taken at the same instant one pixel away, (x -/+ 1, y, t) and (x, y -/+ 1, t), and an earlier
  * sample taken at the same sub-pixel spot, (x, y, t0). afr_crosshairs gives each as a device int32

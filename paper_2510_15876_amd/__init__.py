@@ -22,6 +22,7 @@ __all__ = [
     "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
     "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
+    "SplatParams", "splat_sizes", "reconstruct_scatter",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -110,6 +111,11 @@ def library():
                                                  vp, vp, P(vp)]
     lib.afr_estimate_gradients.restype = st
     lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
+    lib.afr_splat_sizes.restype = st
+    lib.afr_splat_sizes.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, P(_SplatParams), vp, vp]
+    lib.afr_reconstruct_scatter.restype = st
+    lib.afr_reconstruct_scatter.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), vp,
+                                            ctypes.c_float, vp, vp, vp, vp]
     lib.afr_crosshair_workspace_bytes.restype = ctypes.c_size_t
     lib.afr_crosshair_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
     lib.afr_build_crosshair_buffer.restype = st
@@ -195,6 +201,28 @@ class Params:
         return _Params(self.sigma, self.tau, self.alpha, self.e_min, self.e_max, self.g_floor,
                        self.dt_floor, self.age_floor, int(self.radius), int(self.tile),
                        self.t_now)
+
+
+class _SplatParams(ctypes.Structure):
+    _fields_ = [("size_default", ctypes.c_float), ("size_min", ctypes.c_float),
+                ("size_max", ctypes.c_float), ("grow", ctypes.c_float), ("shrink", ctypes.c_float),
+                ("n_low", ctypes.c_int32), ("n_high", ctypes.c_int32)]
+
+
+@dataclass
+class SplatParams:
+    """Adaptive splat size (see ``afr_splat_params`` in include/afr.h)."""
+    size_default: float = 5.0
+    size_min: float = 1.0
+    size_max: float = 16.0
+    grow: float = 4.0
+    shrink: float = 0.7
+    n_low: int = 4
+    n_high: int = 32
+
+    def _c(self) -> _SplatParams:
+        return _SplatParams(self.size_default, self.size_min, self.size_max, self.grow,
+                            self.shrink, int(self.n_low), int(self.n_high))
 
 
 def tiles_shape(width: int, height: int, tile: int):
@@ -341,6 +369,47 @@ def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tens
     _check(lib.afr_estimate_gradients(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc),
                                       _stream(stream)), "afr_estimate_gradients")
     return out
+
+
+def splat_sizes(width: int, height: int, coverage: Optional[torch.Tensor], sp: SplatParams,
+                out: Optional[torch.Tensor] = None, device=None, stream=None) -> torch.Tensor:
+    """Per-pixel splat size [H, W] for the next image from this image's coverage map [2, H, W]
+    (``None``: the first image)."""
+    lib = library()
+    dev = coverage.device if coverage is not None else (out.device if out is not None else device)
+    if dev is None:
+        raise AfrError("splat_sizes needs a device when there is no coverage map or output")
+    if coverage is not None and (coverage.dtype != torch.float32 or not coverage.is_contiguous()
+                                 or tuple(coverage.shape) != (2, height, width)):
+        raise AfrError("coverage must be a contiguous float32 [2, H, W] tensor")
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.float32, device=dev)
+    _check(lib.afr_splat_sizes(width, height, _ptr(coverage), ctypes.byref(sp._c()), _ptr(out),
+                               _stream(stream)), "afr_splat_sizes")
+    return out
+
+
+def reconstruct_scatter(buf: DeepBuffer, stats: torch.Tensor, params: Params, size: torch.Tensor,
+                        max_size: float, rgb: Optional[torch.Tensor] = None, want_aux: bool = True,
+                        coverage: Optional[torch.Tensor] = None, want_coverage: bool = True,
+                        stream=None):
+    """Scatter-form image ``(rgb [3,H,W], aux [2,H,W] or None, coverage [2,H,W] or None)`` with the
+    per-source-pixel splat sizes ``size`` [H, W]."""
+    lib = library()
+    dev = buf.planes.device
+    H, W = buf.height, buf.width
+    if size.dtype != torch.float32 or not size.is_contiguous() or tuple(size.shape) != (H, W):
+        raise AfrError("size must be a contiguous float32 [H, W] tensor")
+    if rgb is None:
+        rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    aux = torch.empty((2, H, W), dtype=torch.float32, device=dev) if want_aux else None
+    if coverage is None and want_coverage:
+        coverage = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+    bc, pc, sc = buf._c(), params._c(), _stats_c(stats, params.tile)
+    _check(lib.afr_reconstruct_scatter(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
+                                       _ptr(size), float(max_size), _ptr(rgb), _ptr(aux),
+                                       _ptr(coverage), _stream(stream)), "afr_reconstruct_scatter")
+    return rgb, aux, coverage
 
 
 def build_crosshair_buffer(samples, crosshairs, width: int, height: int, k: int, params: Params,

@@ -73,6 +73,33 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
     return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, stage_end);
 }
 
+afr_status afr_splat_sizes(int32_t width, int32_t height, const float *coverage,
+                           const afr_splat_params *sp, float *size, hipStream_t stream) {
+    if (!sp || !size) return AFR_E_INVALID;
+    if (width < 1 || height < 1 || (int64_t)width * height >= (int64_t(1) << 29)) return AFR_E_RANGE;
+    const float vals[] = {sp->size_default, sp->size_min, sp->size_max, sp->grow, sp->shrink};
+    for (float v : vals)
+        if (!finite(v)) return AFR_E_RANGE;
+    if (!(sp->size_min > 0.0f) || sp->size_default < sp->size_min ||
+        sp->size_max < sp->size_default || sp->size_max > kMaxSplat)
+        return AFR_E_RANGE;
+    if (sp->grow < 1.0f || !(sp->shrink > 0.0f) || sp->shrink > 1.0f) return AFR_E_RANGE;
+    if (sp->n_low < 0 || sp->n_high < sp->n_low) return AFR_E_RANGE;
+    return from_hip(launch_splat_sizes(width, height, coverage, *sp, size, stream));
+}
+
+afr_status afr_reconstruct_scatter(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                                   const afr_params *params, const float *size, float max_size,
+                                   float *rgb, float *aux, float *coverage, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!size || !rgb) return AFR_E_INVALID;
+    if (!finite(max_size) || !(max_size > 0.0f) || max_size > kMaxSplat) return AFR_E_RANGE;
+    return from_hip(launch_scatter(*buf, *stats, *params, size, max_size, rgb, aux, coverage,
+                                   stream));
+}
+
 size_t afr_crosshair_workspace_bytes(int64_t n, int32_t width, int32_t height) {
     if (n < 0 || width < 1 || height < 1) return 0;
     return crosshair_ws_bytes(n, width, height);

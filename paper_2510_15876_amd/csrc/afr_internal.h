@@ -196,6 +196,14 @@ hipError_t launch_crosshair_estimate(const afr_deep_buffer &buf, const afr_deep_
                                      const afr_params &prm, const afr_tile_stats &out,
                                      hipStream_t st);
 
+constexpr float kMaxSplat = 64.0f;  // largest splat edge the scatter form accepts, px
+int splat_reach(float max_size);
+hipError_t launch_splat_sizes(int32_t w, int32_t h, const float *coverage,
+                              const afr_splat_params &sp, float *size, hipStream_t st);
+hipError_t launch_scatter(const afr_deep_buffer &buf, const afr_tile_stats &stats,
+                          const afr_params &prm, const float *size, float max_size, float *rgb,
+                          float *aux, float *coverage, hipStream_t st);
+
 size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                            const afr_params &p, const float *rgb, const float *aux,

@@ -160,3 +160,22 @@ def test_crosshair_validation(afr):
     assert lib.afr_estimate_gradients_crosshair(ctypes.byref(b), ctypes.byref(b16), ctypes.byref(p), ctypes.byref(st), None) == 5
     late = afr.Params(t_now=9.0)._c()   # before the buffers' t_ref
     assert lib.afr_estimate_gradients_crosshair(ctypes.byref(b), ctypes.byref(b), ctypes.byref(late), ctypes.byref(st), None) == 2
+
+
+def test_scatter_validation(afr):
+    lib = afr.library()
+    sp = afr.SplatParams()
+    assert lib.afr_splat_sizes(16, 8, None, ctypes.byref(sp._c()), None, None) == 1
+    for bad in (dict(size_min=0.0), dict(size_default=0.5), dict(size_max=65.0),
+                dict(grow=0.5), dict(shrink=0.0), dict(shrink=1.5), dict(n_low=40),
+                dict(size_max=float("nan"))):
+        b = afr.SplatParams(**{**sp.__dict__, **bad})
+        assert lib.afr_splat_sizes(16, 8, None, ctypes.byref(b._c()), 0x1000, None) == 2, bad
+    assert lib.afr_splat_sizes(0, 8, None, ctypes.byref(sp._c()), 0x1000, None) == 2
+    b = _fake_buffer(afr)
+    p = afr.Params(t_now=11.0)._c()
+    st = afr._TileStats(8, 2, 1, 0x1000)
+    for m in (0.0, 65.0, float("inf"), float("nan")):
+        assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), 0x2000, m, 0x3000, None, None, None) == 2
+    assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), None, 5.0, 0x3000, None, None, None) == 1
+    assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), 0x2000, 5.0, None, None, None, None) == 1
