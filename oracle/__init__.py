@@ -60,6 +60,11 @@ class _Splat(ctypes.Structure):
                 ("n_low", ctypes.c_int), ("n_high", ctypes.c_int)]
 
 
+class _Sampler(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("lambda_", ctypes.c_double), ("m", ctypes.c_double),
+                ("gain", ctypes.c_double)]
+
+
 _lib_handle = None
 
 
@@ -97,6 +102,14 @@ def _lib():
         lib.or_splat_sizes.restype = None
         lib.or_splat_sizes.argtypes = [ctypes.c_int, ctypes.c_int, fp, fp,
                                        ctypes.POINTER(_Splat), fp]
+        lib.or_sampler_stats.restype = ctypes.c_int
+        lib.or_sampler_stats.argtypes = [ctypes.POINTER(_Buffer), _dp, ctypes.POINTER(_Params),
+                                         ctypes.POINTER(_Sampler), _dp, _dp, _dp]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.or_sampler_select.restype = ctypes.c_int
+        lib.or_sampler_select.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp,
+                                          ctypes.c_int64, u32p, fp, fp,
+                                          ctypes.POINTER(ctypes.c_int32)]
         _lib_handle = lib
     return _lib_handle
 
@@ -367,3 +380,55 @@ def scatter(buf: Buffer, stats: np.ndarray, params: Params, size, max_size: floa
     if rc:
         raise ValueError(f"or_scatter failed ({rc})")
     return rgb, aux, (n, ms)
+
+
+# ---- sampler feedback statistics and tile selection (Sec. 4, 4.1, 6.1) ---------------------------
+
+SAMPLER_GLOBALS = ("sum_v", "sum_u", "mean_empty", "dcds", "dcdt", "mean_age", "S", "target_tiles")
+
+
+@dataclass
+class SamplerParams:
+    """Tile error weights (Sec. 6.1: kappa for variation, lambda for undersampling; the occlusion
+    share 1 - kappa - lambda has no term here), the undersampling factor m and the gain constant i
+    of Sec. 4.1."""
+    kappa: float = 0.7
+    lam: float = 0.3
+    m: float = 2.0
+    gain: float = 1.0
+
+    def _c(self) -> _Sampler:
+        return _Sampler(float(self.kappa), float(self.lam), float(self.m), float(self.gain))
+
+
+def sampler_stats(buf: Buffer, stats: np.ndarray, params: Params, sp: SamplerParams):
+    """``(E [Ty, Tx], u [Ty, Tx], globals dict)`` from the sampler's buffer and its statistics."""
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    stats = np.ascontiguousarray(stats, np.float64)
+    E = np.zeros((ty, tx))
+    u = np.zeros((ty, tx))
+    g = np.zeros(len(SAMPLER_GLOBALS))
+    rc = _lib().or_sampler_stats(ctypes.byref(buf._c()), stats.ctypes.data_as(_dp),
+                                 ctypes.byref(params._c()), ctypes.byref(sp._c()),
+                                 E.ctypes.data_as(_dp), u.ctypes.data_as(_dp), g.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError(f"or_sampler_stats failed ({rc})")
+    return E, u, dict(zip(SAMPLER_GLOBALS, g))
+
+
+def sampler_select(width, height, tile, E, rnd):
+    """Sample spots for the next samples: ``(x, y, tile index)`` for ``n = len(rnd) // 3`` draws;
+    ``E`` is the float32 tile error [Ty, Tx], ``rnd`` uint32 [3 n] (see or_sampler_select)."""
+    E = np.ascontiguousarray(E, np.float32)
+    rnd = np.ascontiguousarray(rnd, np.uint32)
+    n = rnd.size // 3
+    x = np.zeros(n, np.float32)
+    y = np.zeros(n, np.float32)
+    t = np.zeros(n, np.int32)
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    rc = _lib().or_sampler_select(int(width), int(height), int(tile), fp(E), n,
+                                  rnd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), fp(x), fp(y),
+                                  t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc:
+        raise ValueError(f"or_sampler_select failed ({rc})")
+    return x, y, t

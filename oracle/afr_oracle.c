@@ -913,3 +913,162 @@ void or_splat_sizes(int W, int H, const float *cov_n, const float *cov_size, con
         size[i] = rintf(u) * 0.00390625f;
     }
 }
+
+/* ------------------------------------------------------------------------------------------------
+ * Sampler feedback statistics (Sec. 4, 4.1, 6.1). Inputs: the sampler's deep buffer (per-pixel
+ * queues of depth b, Sec. 4) and its tile statistics from or_estimate (which hold the age-weighted
+ * luminance variance v_T of Sec. 4 and the tile gradients of Sec. 4.1). Per tile T of s_T pixels:
+ *   |T| = samples in T's block, empty_T = s_T b - |T|;
+ *   mean empty per tile e = (w h b - |buffer|) / |tiles|;
+ *   u_T = 1 - min(1, m e / empty_T)            (undersampling, Sec. 6.1; read with the mean empty
+ *                                               count per tile in the numerator; 0 when empty_T = 0)
+ *   E_T = s_T (kappa v_T / sum v + lambda u_T / sum u)   (tile error, Sec. 6.1, without the
+ *                                               occlusion term, which needs occlusion rays; a term
+ *                                               whose sum is 0 contributes 0)
+ * Gain control (Sec. 4.1): with dC/ds the mean over tiles of (G_x + G_y) / 2, dC/dt the mean of G_t
+ * and T the mean over non-empty tiles of their mean sample age, the tile width that balances
+ * dC/ds S = i dC/dt T is S = i (dC/dt) T / (dC/ds), and the target tile count is w h / S^2
+ * (0 when dC/dt = 0, +inf when dC/ds = 0 < dC/dt).
+ * glob receives: sum v, sum u, e, dC/ds, dC/dt, T, S, target tile count.
+ * Pinned by hand-computed u and E on two-tile buffers, the normalisations (sum E_T / s_T over tiles
+ * is kappa + lambda when both sums are positive) and a constructed gain-control case.
+ * --------------------------------------------------------------------------------------------- */
+typedef struct {
+    double kappa, lambda, m, gain;
+} or_sampler;
+
+int or_sampler_stats(const or_buffer *buf, const double *stats, const or_params *p,
+                     const or_sampler *sp, double *E, double *u, double *glob)
+{
+    const int W = buf->width, H = buf->height, K = buf->k, B = p->tile;
+    if (B < 1)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t NT = (size_t)Tx * Ty;
+    double *empty = (double *)malloc(sizeof(double) * NT);
+    if (!empty)
+        return 4;
+    double n_all = 0.0, sum_v = 0.0, sum_gs = 0.0, sum_gt = 0.0, sum_age = 0.0, n_aged = 0.0;
+    for (int ty = 0; ty < Ty; ++ty)
+        for (int tx = 0; tx < Tx; ++tx) {
+            const size_t T = (size_t)ty * Tx + tx;
+            const int i0 = tx * B, i1 = (tx + 1) * B < W ? (tx + 1) * B : W;
+            const int j0 = ty * B, j1 = (ty + 1) * B < H ? (ty + 1) * B : H;
+            double n_t = 0.0, a_t = 0.0;
+            for (int j = j0; j < j1; ++j)
+                for (int i = i0; i < i1; ++i) {
+                    const size_t px = (size_t)j * W + i;
+                    for (int k = 0; k < buf->count[px]; ++k) {
+                        n_t += 1.0;
+                        a_t += slot_age(buf, p, px * K + k);
+                    }
+                }
+            empty[T] = (double)(i1 - i0) * (j1 - j0) * K - n_t;
+            n_all += n_t;
+            if (n_t > 0.0) {
+                sum_age += a_t / n_t;
+                n_aged += 1.0;
+            }
+            sum_v += stats[OR_VAR * NT + T];
+            sum_gs += 0.5 * (stats[OR_GX * NT + T] + stats[OR_GY * NT + T]);
+            sum_gt += stats[OR_GT * NT + T];
+        }
+    const double e = ((double)W * H * K - n_all) / (double)NT;
+    double sum_u = 0.0;
+    for (size_t T = 0; T < NT; ++T) {
+        u[T] = empty[T] > 0.0 ? 1.0 - fmin(1.0, sp->m * e / empty[T]) : 0.0;
+        sum_u += u[T];
+    }
+    for (int ty = 0; ty < Ty; ++ty)
+        for (int tx = 0; tx < Tx; ++tx) {
+            const size_t T = (size_t)ty * Tx + tx;
+            const int bw = (tx + 1) * B < W ? B : W - tx * B;
+            const int bh = (ty + 1) * B < H ? B : H - ty * B;
+            double v = 0.0;
+            if (sum_v > 0.0)
+                v += sp->kappa * stats[OR_VAR * NT + T] / sum_v;
+            if (sum_u > 0.0)
+                v += sp->lambda * u[T] / sum_u;
+            E[T] = (double)bw * bh * v;
+        }
+    const double dcds = sum_gs / (double)NT, dcdt = sum_gt / (double)NT;
+    const double tbar = n_aged > 0.0 ? sum_age / n_aged : 0.0;
+    double S, target;
+    if (dcdt == 0.0) {
+        S = INFINITY;
+        target = 0.0;
+    } else if (dcds == 0.0) {
+        S = 0.0;
+        target = INFINITY;
+    } else {
+        S = sp->gain * dcdt * tbar / dcds;
+        target = S > 0.0 ? (double)W * H / (S * S) : INFINITY;
+    }
+    const double g[8] = {sum_v, sum_u, e, dcds, dcdt, tbar, S, target};
+    memcpy(glob, g, sizeof(g));
+    free(empty);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Tile selection for the next samples (Sec. 4: the sampler picks a tile at random and a uniform
+ * spot inside it; with fixed tiles, a tile is picked with probability proportional to its error
+ * E_T, which biases sampling as the paper's equal-error adaptive tiles do under uniform choice).
+ * Integer weights make the choice exact: q_T = floor(E_T / E_max * 2^24) computed in FP64 from the
+ * binary32 E_T (E_T that is negative or not finite counts as 0; when no tile is positive every q_T
+ * is 1); with Q = sum q_T, draw k takes r = rnd[k] >> 8 and picks the tile T with
+ * cum_T <= (r Q) >> 24 < cum_T + q_T. Its spot is x = x0 + u1 bw, y = y0 + u2 bh in binary32 with
+ * u1 = (rnd[n + k] >> 8) 2^-24 and u2 = (rnd[2n + k] >> 8) 2^-24, (x0, y0) the tile corner and
+ * (bw, bh) its clipped size; a spot that rounds onto the far edge is moved to the float below it.
+ * At most 65536 tiles, so that r Q stays below 2^64.
+ * Pinned by hand-computed draws on two tiles, frequencies on many draws and uniform E.
+ * --------------------------------------------------------------------------------------------- */
+int or_sampler_select(int W, int H, int B, const float *E, int64_t n, const uint32_t *rnd,
+                      float *x, float *y, int32_t *tile)
+{
+    if (B < 1 || W < 1 || H < 1)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const size_t NT = (size_t)Tx * Ty;
+    if (NT > 65536) /* keeps r Q below 2^64 */
+        return 1;
+    uint64_t *cum = (uint64_t *)malloc(sizeof(uint64_t) * (NT + 1));
+    if (!cum)
+        return 4;
+    double emax = 0.0;
+    for (size_t T = 0; T < NT; ++T)
+        if (isfinite(E[T]) && E[T] > emax)
+            emax = E[T];
+    cum[0] = 0;
+    for (size_t T = 0; T < NT; ++T) {
+        uint64_t q = 1;
+        if (emax > 0.0)
+            q = (isfinite(E[T]) && E[T] > 0.0f) ? (uint64_t)floor((double)E[T] / emax * 16777216.0)
+                                                : 0;
+        cum[T + 1] = cum[T] + q;
+    }
+    const uint64_t Q = cum[NT];
+    for (int64_t k = 0; k < n; ++k) {
+        const uint64_t target = ((uint64_t)(rnd[k] >> 8) * Q) >> 24;
+        size_t lo = 0, hi = NT; /* the T with cum[T] <= target < cum[T + 1] */
+        while (hi - lo > 1) {
+            const size_t mid = (lo + hi) / 2;
+            if (cum[mid] <= target) lo = mid;
+            else hi = mid;
+        }
+        const int tx = (int)(lo % Tx), ty = (int)(lo / Tx);
+        const int x0 = tx * B, y0 = ty * B;
+        const int bw = x0 + B < W ? B : W - x0, bh = y0 + B < H ? B : H - y0;
+        volatile float u1 = (float)(rnd[n + k] >> 8) * 5.9604644775390625e-8f;
+        volatile float u2 = (float)(rnd[2 * n + k] >> 8) * 5.9604644775390625e-8f;
+        volatile float ox = u1 * (float)bw, oy = u2 * (float)bh;
+        volatile float xs = (float)x0 + ox, ys = (float)y0 + oy;
+        const float xe = (float)(x0 + bw), ye = (float)(y0 + bh);
+        x[k] = xs < xe ? xs : nextafterf(xe, 0.0f);
+        y[k] = ys < ye ? ys : nextafterf(ye, 0.0f);
+        if (tile)
+            tile[k] = (int32_t)lo;
+    }
+    free(cum);
+    return 0;
+}
