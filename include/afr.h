@@ -218,6 +218,54 @@ afr_status afr_reconstruct_scatter(const afr_deep_buffer *buf, const afr_tile_st
                                    float *rgb, float *aux, float *coverage, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Sampler feedback (Sec. 4, 4.1, 6.1): per-tile statistics the sampler steers by, computed from its
+ * own deep buffer (per-pixel queues of depth b; Sec. 4 uses b = 4) and that buffer's tile statistics
+ * from afr_estimate_gradients. Per tile T of s_T pixels:
+ *   |T| = samples in T, empty_T = s_T b - |T|, e = (w h b - |buffer|) / tiles (mean empty per tile),
+ *   u_T = 1 - min(1, m e / empty_T)  (0 when empty_T = 0)              undersampling (Sec. 6.1)
+ *   E_T = s_T (kappa v_T / sum v + lambda u_T / sum u)                  tile error (Sec. 6.1)
+ * with v_T the tile's age-weighted luminance variance (Sec. 4); a share whose sum is 0 adds 0; the
+ * occlusion share of the paper needs occlusion rays and is left out. Gain control (Sec. 4.1): with
+ * dC/ds the mean over tiles of (G_x + G_y) / 2, dC/dt the mean of G_t and T the mean over non-empty
+ * tiles of their mean sample age, S = gain dC/dt T / dC/ds balances dC/ds S = gain dC/dt T, and the
+ * target tile count is w h / S^2 (S = 0 and inf tiles when dC/dt = 0: static content is tiled as
+ * finely as possible; S = inf and 0 tiles when dC/ds = 0 < dC/dt). All sums are FP64 in a fixed
+ * order.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct afr_sampler_params {
+    float kappa;   /* weight of the variation share [0.7]; kappa, lambda >= 0, kappa + lambda <= 1 */
+    float lambda;  /* weight of the undersampling share [0.3]                                      */
+    float m;       /* undersampling factor m >= 0 [2]                                              */
+    float gain;    /* gain constant i > 0 [1]                                                      */
+} afr_sampler_params;
+
+/* Workspace for afr_sampler_stats and afr_sampler_select on `tiles` tiles. */
+size_t afr_sampler_workspace_bytes(int32_t tiles);
+
+/*   buf, stats  the sampler's buffer and its statistics (stats->tile == params->tile)
+ *   E, u        device [tiles_y][tiles_x] float outputs
+ *   globals     device double[8]: sum v, sum u, e, dC/ds, dC/dt, T, S, target tile count */
+afr_status afr_sampler_stats(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                             const afr_params *params, const afr_sampler_params *sp, float *E,
+                             float *u, double *globals, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Spots for the next n samples (Sec. 4: a tile at random, then a uniform spot in it). With fixed
+ * tiles a tile is drawn with probability proportional to E_T, which biases sampling as the paper's
+ * equal-error adaptive tiles do under a uniform choice. The choice is exact integer arithmetic:
+ * q_T = floor(E_T / E_max 2^24) in FP64 (E_T negative or not finite: 0; all q_T = 1 when no E_T is
+ * positive), Q = sum q_T, and draw k takes r = rnd[k] >> 8 and the tile T with
+ * cum_T <= (r Q) >> 24 < cum_T + q_T. Its spot is x = x0 + u1 bw, y = y0 + u2 bh in binary32, with
+ * u1 = (rnd[n + k] >> 8) 2^-24, u2 = (rnd[2n + k] >> 8) 2^-24, (x0, y0) the tile's corner and
+ * (bw, bh) its size clipped to the image; a spot that rounds onto the far edge takes the float below.
+ *   E        device [tiles_y][tiles_x] float (tiles of edge `tile` over width x height), at most 65536
+ *   rnd      device uint32 [3 n], random bits supplied by the caller
+ *   x, y     device float [n] outputs; tile_out optional device int32 [n] (the chosen tile) */
+afr_status afr_sampler_select(int32_t width, int32_t height, int32_t tile, const float *E,
+                              int64_t n, const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Crosshair gradients (Sec. 4.1, 4.2). A crosshair is a centre sample at (x, y, t), the four samples
  * taken at the same instant one pixel away, (x -/+ 1, y, t) and (x, y -/+ 1, t), and an earlier
  * sample taken at the same sub-pixel spot, (x, y, t0). afr_crosshairs gives each as a device int32

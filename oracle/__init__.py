@@ -110,6 +110,9 @@ def _lib():
         lib.or_sampler_select.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp,
                                           ctypes.c_int64, u32p, fp, fp,
                                           ctypes.POINTER(ctypes.c_int32)]
+        lib.or_sampler_tile_weights.restype = ctypes.c_int
+        lib.or_sampler_tile_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp,
+                                                ctypes.c_double, ctypes.c_int, fp]
         _lib_handle = lib
     return _lib_handle
 
@@ -432,3 +435,16 @@ def sampler_select(width, height, tile, E, rnd):
     if rc:
         raise ValueError(f"or_sampler_select failed ({rc})")
     return x, y, t
+
+
+def sampler_tile_weights(width, height, tile, E, target=1.0, n_parts=0):
+    """Equal-error tile weights [Ty, Tx] float32 (see or_sampler_tile_weights): ``n_parts`` parts,
+    or the gain-control ``target`` tile count rounded and clamped when ``n_parts`` is 0."""
+    E = np.ascontiguousarray(E, np.float32)
+    out = np.zeros(E.shape, np.float32)
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    rc = _lib().or_sampler_tile_weights(int(width), int(height), int(tile), fp(E), float(target),
+                                        int(n_parts), fp(out))
+    if rc:
+        raise ValueError(f"or_sampler_tile_weights failed ({rc})")
+    return out

@@ -928,7 +928,8 @@ void or_splat_sizes(int W, int H, const float *cov_n, const float *cov_size, con
  * Gain control (Sec. 4.1): with dC/ds the mean over tiles of (G_x + G_y) / 2, dC/dt the mean of G_t
  * and T the mean over non-empty tiles of their mean sample age, the tile width that balances
  * dC/ds S = i dC/dt T is S = i (dC/dt) T / (dC/ds), and the target tile count is w h / S^2
- * (0 when dC/dt = 0, +inf when dC/ds = 0 < dC/dt).
+ * (S = 0 and +inf tiles when dC/dt = 0: static content is tiled as finely as possible; S = +inf and
+ * 0 tiles when dC/ds = 0 < dC/dt).
  * glob receives: sum v, sum u, e, dC/ds, dC/dt, T, S, target tile count.
  * Pinned by hand-computed u and E on two-tile buffers, the normalisations (sum E_T / s_T over tiles
  * is kappa + lambda when both sums are positive) and a constructed gain-control case.
@@ -994,12 +995,12 @@ int or_sampler_stats(const or_buffer *buf, const double *stats, const or_params 
     const double dcds = sum_gs / (double)NT, dcdt = sum_gt / (double)NT;
     const double tbar = n_aged > 0.0 ? sum_age / n_aged : 0.0;
     double S, target;
-    if (dcdt == 0.0) {
-        S = INFINITY;
-        target = 0.0;
-    } else if (dcds == 0.0) {
+    if (dcdt == 0.0) { /* static content: the finest tiling */
         S = 0.0;
         target = INFINITY;
+    } else if (dcds == 0.0) {
+        S = INFINITY;
+        target = 0.0;
     } else {
         S = sp->gain * dcdt * tbar / dcds;
         target = S > 0.0 ? (double)W * H / (S * S) : INFINITY;
@@ -1070,5 +1071,109 @@ int or_sampler_select(int W, int H, int B, const float *E, int64_t n, const uint
             tile[k] = (int32_t)lo;
     }
     free(cum);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Equal-error tiles (Sec. 4: the sampler's tiles each hold about the same colour variation and are
+ * picked uniformly, so small tiles form over edges and motion; Sec. 4.1: gain control sets how many
+ * tiles there are). The adaptive K-D tree itself is not built; its effect is reproduced over the
+ * fixed statistics tiles: the tiles are put in Morton (Z-curve) order, the curve is cut into N
+ * parts of equal error, and each part is picked with probability 1/N, a uniform spot inside it.
+ * Exactly:
+ *   q_T = integer error weights as in or_sampler_select, C_m = sum of q over the first m tiles on
+ *   the curve, Q = C_nt; tile m starts in part p_m = min(N - 1, floor(C_m N / Q));
+ *   a part that tiles start in is the run of those tiles, and spreads its 1/N over them by area;
+ *   a part no tile starts in lies inside the error of the tile before it on the curve, which takes
+ *   its whole 1/N.
+ * The output weight of tile T (proportional to its probability; the factor 1/N is dropped) is
+ *   P_T = s_T / A(run of p_T) + (number of parts strictly between p_T and the next tile's part,
+ *         or up to N for the last tile),
+ * in FP64 from integers, stored as float. With Q = 0 every P_T is s_T (uniform by area). N is the
+ * gain-control target tile count rounded and clamped to [1, tiles], or an explicit count.
+ * Pinned by: N = 1 is uniform by area; equal errors with N = tiles give every tile weight 1; a
+ * single tile holding all the error takes N - 2 whole parts; the weights sum to N.
+ * --------------------------------------------------------------------------------------------- */
+static uint32_t or_spread_bits(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 16; ++b)
+        r |= ((v >> b) & 1u) << (2 * b);
+    return r;
+}
+
+typedef struct { uint32_t code; int32_t tile; } or_morton;
+
+static int or_morton_cmp(const void *a, const void *b)
+{
+    const uint32_t x = ((const or_morton *)a)->code, y = ((const or_morton *)b)->code;
+    return (x > y) - (x < y);
+}
+
+int or_sampler_tile_weights(int W, int H, int B, const float *E, double target, int n_override,
+                            float *P)
+{
+    if (B < 1 || W < 1 || H < 1)
+        return 1;
+    const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
+    const int NT = Tx * Ty;
+    if (NT > 65536)
+        return 1;
+    int N = n_override;
+    if (N <= 0) {
+        double r = isnan(target) ? 1.0 : nearbyint(target);
+        N = r < 1.0 ? 1 : (r > NT ? NT : (int)r);
+    }
+    if (N > NT)
+        N = NT;
+    or_morton *ord = (or_morton *)malloc(sizeof(or_morton) * NT);
+    uint64_t *C = (uint64_t *)malloc(sizeof(uint64_t) * (NT + 1));
+    int64_t *A = (int64_t *)malloc(sizeof(int64_t) * (NT + 1));
+    int64_t *part = (int64_t *)malloc(sizeof(int64_t) * NT);
+    if (!ord || !C || !A || !part) {
+        free(ord); free(C); free(A); free(part);
+        return 4;
+    }
+    for (int ty = 0; ty < Ty; ++ty)
+        for (int tx = 0; tx < Tx; ++tx) {
+            ord[ty * Tx + tx].code = or_spread_bits((uint32_t)tx) | (or_spread_bits((uint32_t)ty) << 1);
+            ord[ty * Tx + tx].tile = ty * Tx + tx;
+        }
+    qsort(ord, NT, sizeof(or_morton), or_morton_cmp);
+    double emax = 0.0;
+    for (int T = 0; T < NT; ++T)
+        if (isfinite(E[T]) && E[T] > emax)
+            emax = E[T];
+    C[0] = 0;
+    A[0] = 0;
+    for (int m = 0; m < NT; ++m) {
+        const int T = ord[m].tile, tx = T % Tx, ty = T / Tx;
+        const int bw = (tx + 1) * B < W ? B : W - tx * B, bh = (ty + 1) * B < H ? B : H - ty * B;
+        uint64_t q = 0;
+        if (emax > 0.0 && isfinite(E[T]) && E[T] > 0.0f)
+            q = (uint64_t)floor((double)E[T] / emax * 16777216.0);
+        C[m + 1] = C[m] + q;
+        A[m + 1] = A[m] + (int64_t)bw * bh;
+    }
+    const uint64_t Q = C[NT];
+    for (int m = 0; m < NT; ++m) {
+        const uint64_t p = Q ? C[m] * (uint64_t)N / Q : 0;
+        part[m] = p < (uint64_t)N - 1 ? (int64_t)p : N - 1;
+    }
+    for (int m = 0; m < NT; ++m) {
+        const int T = ord[m].tile;
+        const double s = (double)(A[m + 1] - A[m]);
+        if (Q == 0) {
+            P[T] = (float)s;
+            continue;
+        }
+        int lo = m, hi = m + 1; /* the run of tiles starting in the same part */
+        while (lo > 0 && part[lo - 1] == part[m]) --lo;
+        while (hi < NT && part[hi] == part[m]) ++hi;
+        const int64_t next = m + 1 < NT ? part[m + 1] : N;
+        const int64_t extra = next - part[m] - 1 > 0 ? next - part[m] - 1 : 0;
+        P[T] = (float)(s / (double)(A[hi] - A[lo]) + (double)extra);
+    }
+    free(ord); free(C); free(A); free(part);
     return 0;
 }

@@ -1,0 +1,259 @@
+// Sampler feedback statistics (Sec. 4, 4.1, 6.1) and error-proportional tile selection.
+//
+//   k_smp_tiles    one wave per tile of the sampler's buffer: the tile's sample count and mean
+//                  sample age (FP64), plus its variation and mean gradients from the statistics
+//   k_smp_global   one workgroup: fixed-order FP64 reductions over tiles (sample total, variation,
+//                  gradients, ages), then each tile's undersampling u_T, their sum, each tile's error
+//                  E_T and the gain-control figures
+//   k_smp_weights  one workgroup: integer tile weights q_T = floor(E_T / E_max 2^24) and their
+//                  exclusive prefix sum (exact, so independent of the scan's order)
+//   k_smp_draw     one thread per new sample: the tile whose weight interval holds the draw (binary
+//                  search over the prefix sums) and a uniform spot inside it, in binary32
+#include "afr_internal.h"
+
+namespace afr {
+namespace {
+
+constexpr int kGThreads = 1024;
+
+struct TilePart {
+    double empty, age, v, gs, gt;  // empty slots; mean age (or -1 if the tile holds no sample)
+};
+
+template <typename S>
+__global__ __launch_bounds__(kWave) void k_smp_tiles(BufView<S> v, double t_now, double dt_ref,
+                                                     TileGeom tg, const float *__restrict__ stats,
+                                                     TilePart *part) {
+    const int T = blockIdx.x;
+    const int tx = T % tg.tiles_x, ty = T / tg.tiles_x, B = tg.tile;
+    const int i0 = tx * B, j0 = ty * B;
+    const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
+    const size_t plane = (size_t)v.width * v.height;
+    double n = 0.0, a = 0.0;
+    for (int e = threadIdx.x; e < bw * bh; e += kWave) {
+        const size_t px = (size_t)(j0 + e / bw) * v.width + i0 + e % bw;
+        const int c = v.count[px];
+        for (int k = 0; k < c; ++k) {
+            n += 1.0;
+            a += Codec<S>::age64(v.ta[(size_t)k * plane + px], t_now, dt_ref);
+        }
+    }
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+        n += __shfl_xor(n, m, kWave);
+        a += __shfl_xor(a, m, kWave);
+    }
+    if (threadIdx.x != 0) return;
+    const int nt = tg.nt;
+    TilePart p;
+    p.empty = (double)bw * bh * v.k - n;
+    p.age = n > 0.0 ? a / n : -1.0;
+    p.v = stats[AFR_STAT_VAR * nt + T];
+    p.gs = 0.5 * ((double)stats[AFR_STAT_GX * nt + T] + (double)stats[AFR_STAT_GY * nt + T]);
+    p.gt = stats[AFR_STAT_GT * nt + T];
+    part[T] = p;
+}
+
+// Sum of one double per thread over the workgroup in a fixed order; the result is valid in every
+// thread.
+__device__ inline double block_sum(double x, double *sh) {
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m, kWave);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) sh[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kGThreads / kWave; ++i) t += sh[i];
+    return t;
+}
+
+struct SmpParams {
+    double kappa, lambda, m, gain;
+};
+
+__global__ __launch_bounds__(kGThreads) void k_smp_global(const TilePart *__restrict__ part,
+                                                           TileGeom tg, int W, int H, int K,
+                                                           SmpParams sp, float *E, float *u,
+                                                           double *glob) {
+    __shared__ double sh[kGThreads / kWave];
+    const int nt = tg.nt;
+    double empty = 0.0, sv = 0.0, sgs = 0.0, sgt = 0.0, sage = 0.0, naged = 0.0;
+    for (int T = threadIdx.x; T < nt; T += kGThreads) {
+        const TilePart p = part[T];
+        empty += p.empty;
+        sv += p.v;
+        sgs += p.gs;
+        sgt += p.gt;
+        if (p.age >= 0.0) {
+            sage += p.age;
+            naged += 1.0;
+        }
+    }
+    empty = block_sum(empty, sh);
+    sv = block_sum(sv, sh);
+    sgs = block_sum(sgs, sh);
+    sgt = block_sum(sgt, sh);
+    sage = block_sum(sage, sh);
+    naged = block_sum(naged, sh);
+    const double e = empty / (double)nt;  // empty slots are exact integers in FP64
+    double su = 0.0;
+    for (int T = threadIdx.x; T < nt; T += kGThreads) {
+        const double et = part[T].empty;
+        const double ut = et > 0.0 ? 1.0 - fmin(1.0, sp.m * e / et) : 0.0;
+        u[T] = (float)ut;
+        su += ut;
+    }
+    su = block_sum(su, sh);
+    for (int T = threadIdx.x; T < nt; T += kGThreads) {
+        const int tx = T % tg.tiles_x, ty = T / tg.tiles_x;
+        const int bw = min(tg.tile, W - tx * tg.tile), bh = min(tg.tile, H - ty * tg.tile);
+        const double et = part[T].empty;
+        const double ut = et > 0.0 ? 1.0 - fmin(1.0, sp.m * e / et) : 0.0;
+        double x = 0.0;
+        if (sv > 0.0) x += sp.kappa * part[T].v / sv;
+        if (su > 0.0) x += sp.lambda * ut / su;
+        E[T] = (float)((double)bw * bh * x);
+    }
+    if (threadIdx.x == 0) {
+        const double dcds = sgs / (double)nt, dcdt = sgt / (double)nt;
+        const double tbar = naged > 0.0 ? sage / naged : 0.0;
+        double S, target;
+        if (dcdt == 0.0) {  // static content: the finest tiling
+            S = 0.0;
+            target = INFINITY;
+        } else if (dcds == 0.0) {
+            S = INFINITY;
+            target = 0.0;
+        } else {
+            S = sp.gain * dcdt * tbar / dcds;
+            target = S > 0.0 ? (double)W * H / (S * S) : INFINITY;
+        }
+        glob[0] = sv;
+        glob[1] = su;
+        glob[2] = e;
+        glob[3] = dcds;
+        glob[4] = dcdt;
+        glob[5] = tbar;
+        glob[6] = S;
+        glob[7] = target;
+    }
+    (void)K;
+}
+
+__global__ __launch_bounds__(kGThreads) void k_smp_weights(const float *__restrict__ E, int nt,
+                                                            unsigned long long *cum) {
+    __shared__ float smax[kGThreads / kWave];
+    __shared__ unsigned long long ssum[kGThreads / kWave];
+    // largest positive finite error (exact: a maximum)
+    float m = 0.0f;
+    for (int T = threadIdx.x; T < nt; T += kGThreads) {
+        const float x = E[T];
+        if (isfinite(x) && x > m) m = x;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == 0) smax[w] = m;
+    __syncthreads();
+    m = 0.0f;
+    for (int i = 0; i < kGThreads / kWave; ++i) m = fmaxf(m, smax[i]);
+    const double emax = m;
+    // each thread owns a contiguous run of tiles; runs are scanned in thread order
+    const int per = (nt + kGThreads - 1) / kGThreads;
+    const int t0 = min(nt, threadIdx.x * per), t1 = min(nt, t0 + per);
+    auto weight = [&](int T) -> unsigned long long {
+        if (!(emax > 0.0)) return 1ull;
+        const float x = E[T];
+        return (isfinite(x) && x > 0.0f) ? (unsigned long long)floor((double)x / emax * 16777216.0)
+                                         : 0ull;
+    };
+    unsigned long long run = 0;
+    for (int T = t0; T < t1; ++T) run += weight(T);
+    // exclusive scan of the run totals across the workgroup
+    unsigned long long incl = run;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned long long n = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += n;
+    }
+    if (lane == kWave - 1) ssum[w] = incl;
+    __syncthreads();
+    unsigned long long base = incl - run;
+    for (int i = 0; i < w; ++i) base += ssum[i];
+    for (int T = t0; T < t1; ++T) {
+        cum[T] = base;
+        base += weight(T);
+    }
+    if (threadIdx.x == kGThreads - 1) cum[nt] = base;
+}
+
+struct DrawGeom {
+    int W, H, B, tiles_x, nt;
+};
+
+__global__ __launch_bounds__(256) void k_smp_draw(const unsigned long long *__restrict__ cum,
+                                                   DrawGeom g, const uint32_t *__restrict__ rnd,
+                                                   int64_t n, float *x, float *y, int32_t *tile) {
+#pragma clang fp contract(off)
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const unsigned long long Q = cum[g.nt];
+    const unsigned long long target = ((unsigned long long)(rnd[k] >> 8) * Q) >> 24;
+    int lo = 0, hi = g.nt;  // the T with cum[T] <= target < cum[T + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cum[mid] <= target) lo = mid;
+        else hi = mid;
+    }
+    const int tx = lo % g.tiles_x, ty = lo / g.tiles_x;
+    const int x0 = tx * g.B, y0 = ty * g.B;
+    const int bw = min(g.B, g.W - x0), bh = min(g.B, g.H - y0);
+    const float u1 = (float)(rnd[n + k] >> 8) * 5.9604644775390625e-8f;
+    const float u2 = (float)(rnd[2 * n + k] >> 8) * 5.9604644775390625e-8f;
+    const float xs = (float)x0 + u1 * (float)bw, ys = (float)y0 + u2 * (float)bh;
+    const float xe = (float)(x0 + bw), ye = (float)(y0 + bh);
+    x[k] = xs < xe ? xs : __uint_as_float(__float_as_uint(xe) - 1u);
+    y[k] = ys < ye ? ys : __uint_as_float(__float_as_uint(ye) - 1u);
+    if (tile) tile[k] = lo;
+}
+
+}  // namespace
+
+size_t sampler_ws_bytes(int32_t tiles) {
+    return align_up((size_t)tiles * sizeof(TilePart)) + align_up((size_t)(tiles + 1) * 8);
+}
+
+hipError_t launch_sampler_stats(const afr_deep_buffer &buf, const afr_tile_stats &stats,
+                                const afr_params &prm, const afr_sampler_params &sp, float *E,
+                                float *u, double *glob, void *ws, hipStream_t st) {
+    const TileGeom tg = geom_of(stats);
+    TilePart *part = static_cast<TilePart *>(ws);
+    const double t_now = prm.t_now, dt_ref = (double)prm.t_now - (double)buf.t_ref;
+    if (buf.precision == AFR_FP16)
+        k_smp_tiles<__half><<<tg.nt, kWave, 0, st>>>(view_of<__half>(buf), t_now, dt_ref, tg,
+                                                     stats.data, part);
+    else
+        k_smp_tiles<float><<<tg.nt, kWave, 0, st>>>(view_of<float>(buf), t_now, dt_ref, tg,
+                                                    stats.data, part);
+    const SmpParams p{sp.kappa, sp.lambda, sp.m, sp.gain};
+    k_smp_global<<<1, kGThreads, 0, st>>>(part, tg, buf.width, buf.height, buf.k, p, E, u, glob);
+    return hipGetLastError();
+}
+
+hipError_t launch_sampler_select(int32_t w, int32_t h, int32_t tile, const float *E, int64_t n,
+                                 const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
+                                 void *ws, hipStream_t st) {
+    const int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;
+    const int nt = tiles_x * tiles_y;
+    unsigned long long *cum = reinterpret_cast<unsigned long long *>(
+        static_cast<char *>(ws) + align_up((size_t)nt * sizeof(TilePart)));
+    k_smp_weights<<<1, kGThreads, 0, st>>>(E, nt, cum);
+    if (n > 0) {
+        const DrawGeom g{w, h, tile, tiles_x, nt};
+        k_smp_draw<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(cum, g, rnd, n, x, y, tile_out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace afr

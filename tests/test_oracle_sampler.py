@@ -64,7 +64,7 @@ def test_error_shares_sum_to_the_weights(oracle):
 def test_gain_control(oracle):
     """Gradients (G_x, G_y, G_t) = (0.02, 0.04, 0.001) everywhere and sample ages 10 and 30 ms: dC/ds
     = 0.03, dC/dt = 0.001, T = 20 ms, S = i dC/dt T / dC/ds = 2i/3 and the target tile count is
-    w h / S^2; static content (G_t = 0) asks for no tiles."""
+    w h / S^2; static content (G_t = 0) asks for the finest tiling (S = 0, unbounded tile count)."""
     w, h = 16, 8
     buf = _buffer(oracle, w, h, 4, [[2] * w for _ in range(h)], [10.0, 30.0])
     p = oracle.Params(t_now=100.0, tile=8)
@@ -77,7 +77,7 @@ def test_gain_control(oracle):
         np.testing.assert_allclose(g["target_tiles"], w * h / (2.0 * gain / 3.0) ** 2, rtol=1e-13)
     st = _stats(oracle, w, h, 8, gx=0.02, gy=0.04, gt=0.0)
     _, _, g = oracle.sampler_stats(buf, st, p, oracle.SamplerParams())
-    assert g["target_tiles"] == 0.0 and np.isinf(g["S"])
+    assert g["S"] == 0.0 and np.isinf(g["target_tiles"])
 
 
 def _rnd(rng, n):
@@ -130,3 +130,55 @@ def test_spot_never_reaches_the_far_edge(oracle):
     rnd = np.array([0, (2 ** 24 - 1) << 8, 0], np.uint64).astype(np.uint32)
     x, y, t = oracle.sampler_select(w, h, B, E, rnd)
     assert t[0] == 79 and x[0] == np.nextafter(np.float32(635), np.float32(0)) and y[0] == 0
+
+
+def test_equal_error_tiles_one_part_is_uniform_by_area(oracle):
+    rng = np.random.default_rng(21)
+    w, h, B = 37, 29, 8
+    E = rng.random(oracle.tiles_shape(w, h, B)).astype(np.float32)
+    P = oracle.sampler_tile_weights(w, h, B, E, n_parts=1)
+    ty, tx = E.shape
+    area = np.outer([8] * (ty - 1) + [h - 8 * (ty - 1)], [8] * (tx - 1) + [w - 8 * (tx - 1)])
+    np.testing.assert_allclose(P, area / (w * h), rtol=1e-7)
+    # no error anywhere: uniform by area whatever the part count
+    P0 = oracle.sampler_tile_weights(w, h, B, np.zeros_like(E), n_parts=7)
+    np.testing.assert_array_equal(P0, area.astype(np.float32))
+
+
+def test_equal_error_tiles_follow_the_z_curve(oracle):
+    """4 x 4 tiles, error 1 on the top-left 2 x 2 quadrant (the first four tiles on the Z-curve),
+    four parts: the first three quadrant tiles are parts of their own (weight 1), the fourth shares
+    the last part with the 12 error-free tiles (weight 1/13 each). A row-major order would give the
+    tile below the top-left corner 1/3 instead."""
+    E = np.zeros((4, 4), np.float32)
+    E[:2, :2] = 1.0
+    P = oracle.sampler_tile_weights(32, 32, 8, E, n_parts=4)
+    assert P[0, 0] == 1.0 and P[0, 1] == 1.0 and P[1, 0] == 1.0
+    rest = np.ones((4, 4), bool)
+    rest[0, 0] = rest[0, 1] = rest[1, 0] = False
+    np.testing.assert_allclose(P[rest], 1.0 / 13.0, rtol=1e-7)
+    np.testing.assert_allclose(P.sum(), 4.0, rtol=1e-6)
+
+
+def test_equal_error_tiles_equal_errors_and_a_dominant_tile(oracle):
+    """Equal errors with as many parts as tiles: one part per tile, weight 1 each. All error in one
+    tile (in the middle of the curve): that tile takes N - 2 whole parts plus its share of the
+    first run; the error-free tiles before and after it share the first and the last part. The
+    weights always sum to N, and the gain target rounds and clamps into [1, tiles]."""
+    E = np.ones((6, 8), np.float32)
+    np.testing.assert_array_equal(oracle.sampler_tile_weights(64, 48, 8, E, n_parts=48), 1.0)
+    E = np.zeros((6, 8), np.float32)
+    # tile (x 2, y 3): Z-code spread(2) | spread(3) << 1 = 4 | 10 = 14, and the 14 smaller codes
+    # all lie in the top-left 4 x 4 block of the grid: curve position 14 of 48
+    E[3, 2] = 5.0
+    N = 10
+    P = oracle.sampler_tile_weights(64, 48, 8, E, n_parts=N)
+    assert P[3, 2] == np.float32(1.0 / 15.0 + (N - 2))
+    np.testing.assert_allclose(P.sum(), N, rtol=1e-6)
+    np.testing.assert_allclose(P[0, 0], 1.0 / 15.0, rtol=1e-7)   # in the first run (14 + 1 tiles)
+    np.testing.assert_allclose(P[5, 7], 1.0 / 33.0, rtol=1e-7)   # in the last run (33 tiles)
+    rng = np.random.default_rng(2)
+    E = (rng.random((6, 8)) ** 4).astype(np.float32)
+    for target, n in ((0.2, 1), (7.4, 7), (7.6, 8), (1e9, 48), (np.inf, 48), (np.nan, 1)):
+        P = oracle.sampler_tile_weights(64, 48, 8, E, target=target)
+        np.testing.assert_allclose(P.sum(), n, rtol=1e-6)
