@@ -23,7 +23,7 @@ import numpy as np
 __all__ = [
     "Stream", "Workload", "CheckerDiscScene", "DiscScene", "stratified_stream", "uniform_stream",
     "ground_truth", "make_workload", "make_c4_sequence", "make_c5_batch", "CONFIG_NAMES",
-    "Crosshairs", "crosshair_stream", "make_crosshair_workload",
+    "Crosshairs", "crosshair_stream", "make_crosshair_workload", "shade_samples",
 ]
 
 OMEGA_RAD_PER_MS = 1e-3   # background ramp rotation, 1 rad/s
@@ -208,6 +208,12 @@ def _shade_to_stream(scene, x32, y32, t32, sort: bool) -> Stream:
         order = np.argsort(t32, kind="stable")
         s = s.select(order)
     return s
+
+
+def shade_samples(scene, x, y, t, sort: bool = True) -> Stream:
+    """A stream of samples of ``scene`` taken at the given float32 spots and times."""
+    return _shade_to_stream(scene, np.asarray(x, np.float32), np.asarray(y, np.float32),
+                            np.asarray(t, np.float32), sort)
 
 
 def stratified_stream(scene, width: int, height: int, m, t_now: float, t_win: float,

@@ -45,6 +45,8 @@ def _args():
     ap.add_argument("--reproject-frames", type=int, default=8,
                     help="frames in the reprojection leg (0 skips it)")
     ap.add_argument("--no-crosshair", action="store_true", help="skip the crosshair-estimator leg")
+    ap.add_argument("--sampler-frames", type=int, default=10,
+                    help="frames of the closed-loop sampling leg (0 skips it)")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
@@ -370,6 +372,8 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(torch, afr, S, dev, args.frames)
+    if args.sampler_frames > 0:
+        out["sampler"] = sampler_leg(torch, afr, S, dev, args.sampler_frames)
     if not args.no_crosshair:
         out["crosshair"] = crosshair_leg(torch, afr, S, dev)
     if args.reproject_frames > 0:
@@ -463,6 +467,69 @@ def fwd_bwd(torch, afr, S, dev, frames):
     torch.cuda.synchronize()
     return {"workload": "512x512 K=8 FP32, %d frames at 60 Hz" % frames,
             "ms_per_frame": round(e0.elapsed_time(e1) / frames, 5)}
+
+
+def sampler_leg(torch, afr, S, dev, frames, budget=2):
+    """Closed-loop sampling on the 256x256 moving-disc scene: the first 64 ms are sampled uniformly,
+    then each 60 Hz frame the sampler draws ``budget`` samples per pixel, either uniformly or from
+    its feedback (its own depth-4 buffer -> statistics -> tile error -> equal-error tiles -> spots),
+    the scene is shaded at those spots on the host, and the reconstructor's K-deep queues (kept
+    from frame to frame: a queue only loses samples to newer ones) are rebuilt, estimated and
+    gathered at the frame time. Reports the mean RMS error against the analytic ground truth of each
+    sampler and the GPU time of the feedback step per frame."""
+    wl = S.make_workload("c2")
+    scene, W, H, K, B = wl.scene, wl.width, wl.height, wl.k, 8
+    ty, tx = afr.tiles_shape(W, H, B)
+    sp = afr.SamplerParams()
+    gts = {}
+    res = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for mode in ("uniform", "feedback"):
+        rng = np.random.default_rng(1)
+        s = S.stratified_stream(scene, W, H, 8, 64.0, 64.0, rng)
+        cur = [torch.from_numpy(a).to(dev) for a in s.arrays()]
+        rms, fb_ms, parts = [], [], []
+        for f in range(1, frames + 1):
+            t_prev = float(np.float32(64.0 + (f - 1) * S.FRAME_MS))
+            t_now = float(np.float32(64.0 + f * S.FRAME_MS))
+            n = W * H * budget
+            r = rng.integers(0, 2 ** 32, 3 * n, dtype=np.uint64).astype(np.uint32)
+            rd = torch.from_numpy(r.view(np.int32)).to(dev)
+            torch.cuda.synchronize()
+            ev[0].record()
+            if mode == "feedback":
+                p = afr.Params(t_now=t_prev, tile=B)
+                sbuf, _ = afr.build_deep_buffer(*cur, W, H, 4, "fp32", t_prev)
+                st = afr.estimate_gradients(sbuf, p)
+                E, _, g = afr.sampler_stats(sbuf, st, p, sp)
+                P = afr.sampler_tile_weights(W, H, B, E, globals_=g)
+            else:
+                P = afr.sampler_tile_weights(W, H, B, torch.zeros((ty, tx), device=dev), n_parts=1)
+            x, y, _ = afr.sampler_select(W, H, B, P, rd, want_tile=False)
+            ev[1].record()
+            torch.cuda.synchronize()
+            if mode == "feedback":
+                fb_ms.append(ev[0].elapsed_time(ev[1]))
+                parts.append(float(g[7].item()))
+            t = (t_prev + (t_now - t_prev) * rng.random(n)).astype(np.float32)
+            new = S.shade_samples(scene, x.cpu().numpy(), y.cpu().numpy(), t)
+            cur = [torch.cat([a, torch.from_numpy(b).to(dev)]) for a, b in zip(cur, new.arrays())]
+            buf, _ = afr.build_deep_buffer(*cur, W, H, K, "fp32", t_now)
+            keep = buf.src[buf.src >= 0].long().sort().values
+            cur = [a[keep].contiguous() for a in cur]   # what the queues still hold
+            buf, _ = afr.build_deep_buffer(*cur, W, H, K, "fp32", t_now)
+            pr = afr.Params(t_now=t_now)
+            rgb, _ = afr.reconstruct(buf, afr.estimate_gradients(buf, pr), pr)
+            if f not in gts:
+                gts[f] = torch.from_numpy(S.ground_truth(scene, W, H, t_now, 2)).float().to(dev)
+            rms.append(float(torch.sqrt(((rgb - gts[f]) ** 2).mean()).item()))
+        res[mode] = (rms, fb_ms, parts)
+    return {"workload": "256x256 16 discs over a rotating ramp, %d frames at 60 Hz, %d samples/px "
+                        "per frame, K=%d, sampler depth 4, 8 px tiles" % (frames, budget, K),
+            "rms_uniform": round(float(np.mean(res["uniform"][0])), 6),
+            "rms_feedback": round(float(np.mean(res["feedback"][0])), 6),
+            "feedback_ms_per_frame": round(float(np.mean(res["feedback"][1])), 5),
+            "mean_target_tiles": round(float(np.mean(res["feedback"][2])), 1)}
 
 
 def crosshair_leg(torch, afr, S, dev, reps=20):

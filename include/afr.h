@@ -236,7 +236,7 @@ typedef struct afr_sampler_params {
     float kappa;   /* weight of the variation share [0.7]; kappa, lambda >= 0, kappa + lambda <= 1 */
     float lambda;  /* weight of the undersampling share [0.3]                                      */
     float m;       /* undersampling factor m >= 0 [2]                                              */
-    float gain;    /* gain constant i > 0 [1]                                                      */
+    float gain;    /* gain constant i > 0 [4]                                                      */
 } afr_sampler_params;
 
 /* Workspace for afr_sampler_stats and afr_sampler_select on `tiles` tiles. */
@@ -249,6 +249,26 @@ afr_status afr_sampler_stats(const afr_deep_buffer *buf, const afr_tile_stats *s
                              const afr_params *params, const afr_sampler_params *sp, float *E,
                              float *u, double *globals, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/* Equal-error tiles (Sec. 4: the sampler's tiles hold about equal colour variation and are picked
+ * uniformly; Sec. 4.1: gain control sets their number). The adaptive K-D tiling is not built; its
+ * effect is reproduced over the fixed tiles: on the Z-curve (Morton order) over the tile grid, the
+ * integer error weights q_T of afr_sampler_select are summed (C_m over the first m tiles, total Q),
+ * tile m starts in part p_m = min(N - 1, floor(C_m N / Q)), and each of the N parts is worth 1/N:
+ * a part that tiles start in spreads it over them by area, a part no tile starts in gives it to the
+ * tile before it on the curve. Output, per tile, proportional to its probability:
+ *   P_T = s_T / (area of the tiles starting in p_T) + (parts strictly between p_T and the next
+ *         tile's part, or up to N after the last tile)
+ * in FP64 from integers, stored as float; P_T = s_T when Q = 0. Feeding P to afr_sampler_select
+ * draws from these tiles.
+ *   E         device [tiles_y][tiles_x] float tile errors (at most 65536 tiles)
+ *   globals   device double[8] from afr_sampler_stats: N = the target tile count rounded to
+ *             nearest and clamped to [1, tiles] (1 if NaN); may be NULL when n_parts > 0
+ *   n_parts   N itself when > 0 (clamped to the tile count)
+ *   weights   device [tiles_y][tiles_x] float output */
+afr_status afr_sampler_tile_weights(int32_t width, int32_t height, int32_t tile, const float *E,
+                                    const double *globals, int32_t n_parts, float *weights,
+                                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Spots for the next n samples (Sec. 4: a tile at random, then a uniform spot in it). With fixed
  * tiles a tile is drawn with probability proportional to E_T, which biases sampling as the paper's

@@ -398,7 +398,7 @@ class SamplerParams:
     kappa: float = 0.7
     lam: float = 0.3
     m: float = 2.0
-    gain: float = 1.0
+    gain: float = 4.0
 
     def _c(self) -> _Sampler:
         return _Sampler(float(self.kappa), float(self.lam), float(self.m), float(self.gain))

@@ -22,7 +22,8 @@ __all__ = [
     "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
     "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
-    "SplatParams", "splat_sizes", "reconstruct_scatter",
+    "SplatParams", "splat_sizes", "reconstruct_scatter", "SamplerParams", "sampler_stats",
+    "sampler_select", "sampler_tile_weights", "SAMPLER_GLOBALS",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -111,6 +112,17 @@ def library():
                                                  vp, vp, P(vp)]
     lib.afr_estimate_gradients.restype = st
     lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
+    lib.afr_sampler_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_sampler_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.afr_sampler_stats.restype = st
+    lib.afr_sampler_stats.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), P(_SamplerParams),
+                                      vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.afr_sampler_tile_weights.restype = st
+    lib.afr_sampler_tile_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                             ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
+    lib.afr_sampler_select.restype = st
+    lib.afr_sampler_select.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                       ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.afr_splat_sizes.restype = st
     lib.afr_splat_sizes.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, P(_SplatParams), vp, vp]
     lib.afr_reconstruct_scatter.restype = st
@@ -223,6 +235,26 @@ class SplatParams:
     def _c(self) -> _SplatParams:
         return _SplatParams(self.size_default, self.size_min, self.size_max, self.grow,
                             self.shrink, int(self.n_low), int(self.n_high))
+
+
+class _SamplerParams(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_float), ("lambda_", ctypes.c_float), ("m", ctypes.c_float),
+                ("gain", ctypes.c_float)]
+
+
+@dataclass
+class SamplerParams:
+    """Sampler feedback weights (see ``afr_sampler_params`` in include/afr.h)."""
+    kappa: float = 0.7
+    lam: float = 0.3
+    m: float = 2.0
+    gain: float = 4.0
+
+    def _c(self) -> _SamplerParams:
+        return _SamplerParams(self.kappa, self.lam, self.m, self.gain)
+
+
+SAMPLER_GLOBALS = ("sum_v", "sum_u", "mean_empty", "dcds", "dcdt", "mean_age", "S", "target_tiles")
 
 
 def tiles_shape(width: int, height: int, tile: int):
@@ -369,6 +401,70 @@ def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tens
     _check(lib.afr_estimate_gradients(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc),
                                       _stream(stream)), "afr_estimate_gradients")
     return out
+
+
+def sampler_stats(buf: DeepBuffer, stats: torch.Tensor, params: Params, sp: SamplerParams,
+                  stream=None):
+    """Sampler feedback from the sampler's buffer and its statistics: ``(E [Ty,Tx], u [Ty,Tx],
+    globals float64 [8])`` (globals in ``SAMPLER_GLOBALS`` order)."""
+    lib = library()
+    dev = buf.planes.device
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    E = torch.empty((ty, tx), dtype=torch.float32, device=dev)
+    u = torch.empty((ty, tx), dtype=torch.float32, device=dev)
+    g = torch.empty(8, dtype=torch.float64, device=dev)
+    wsb = lib.afr_sampler_workspace_bytes(ty * tx)
+    ws = _workspace(wsb, dev, "sampler")
+    bc, sc, pc = buf._c(), _stats_c(stats, params.tile), params._c()
+    _check(lib.afr_sampler_stats(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
+                                 ctypes.byref(sp._c()), _ptr(E), _ptr(u), _ptr(g), _ptr(ws), wsb,
+                                 _stream(stream)), "afr_sampler_stats")
+    return E, u, g
+
+
+def sampler_tile_weights(width: int, height: int, tile: int, E: torch.Tensor,
+                         globals_: Optional[torch.Tensor] = None, n_parts: int = 0,
+                         out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Equal-error tile weights [Ty, Tx] (see afr_sampler_tile_weights): ``n_parts`` parts, or the
+    gain-control target count in ``globals_`` (from ``sampler_stats``) when ``n_parts`` is 0."""
+    lib = library()
+    ty, tx = tiles_shape(width, height, tile)
+    if E.dtype != torch.float32 or not E.is_contiguous() or tuple(E.shape) != (ty, tx):
+        raise AfrError("E must be a contiguous float32 [tiles_y, tiles_x] tensor")
+    if globals_ is not None and (globals_.dtype != torch.float64 or globals_.numel() != 8):
+        raise AfrError("globals_ must be the float64 [8] tensor of sampler_stats")
+    if out is None:
+        out = torch.empty_like(E)
+    wsb = lib.afr_sampler_workspace_bytes(ty * tx)
+    ws = _workspace(wsb, E.device, "sampler")
+    _check(lib.afr_sampler_tile_weights(width, height, tile, _ptr(E), _ptr(globals_), int(n_parts),
+                                        _ptr(out), _ptr(ws), wsb, _stream(stream)),
+           "afr_sampler_tile_weights")
+    return out
+
+
+def sampler_select(width: int, height: int, tile: int, E: torch.Tensor, rnd: torch.Tensor,
+                   want_tile: bool = True, stream=None):
+    """Spots ``(x, y, tile or None)`` for ``n = rnd.numel() // 3`` new samples, tiles drawn in
+    proportion to ``E`` [Ty, Tx] (see afr_sampler_select)."""
+    lib = library()
+    dev = E.device
+    ty, tx = tiles_shape(width, height, tile)
+    if E.dtype != torch.float32 or not E.is_contiguous() or tuple(E.shape) != (ty, tx):
+        raise AfrError("E must be a contiguous float32 [tiles_y, tiles_x] tensor")
+    if rnd.dtype != torch.int32 or not rnd.is_contiguous() or rnd.dim() != 1 or rnd.numel() % 3:
+        raise AfrError("rnd must be a contiguous 1-D int32 tensor (uint32 bits) of length 3 n")
+    n = rnd.numel() // 3
+    x = torch.empty(n, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    t = torch.empty(n, dtype=torch.int32, device=dev) if want_tile else None
+    wsb = lib.afr_sampler_workspace_bytes(ty * tx)
+    ws = _workspace(wsb, dev, "sampler")
+    _check(lib.afr_sampler_select(width, height, tile, _ptr(E), n, _ptr(rnd) if n else None,
+                                  _ptr(x) if n else None, _ptr(y) if n else None,
+                                  _ptr(t) if (t is not None and n) else None, _ptr(ws), wsb,
+                                  _stream(stream)), "afr_sampler_select")
+    return x, y, t
 
 
 def splat_sizes(width: int, height: int, coverage: Optional[torch.Tensor], sp: SplatParams,

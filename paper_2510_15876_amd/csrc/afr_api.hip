@@ -73,6 +73,56 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
     return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, stage_end);
 }
 
+size_t afr_sampler_workspace_bytes(int32_t tiles) {
+    if (tiles < 1) return 0;
+    return sampler_ws_bytes(tiles);
+}
+
+afr_status afr_sampler_stats(const afr_deep_buffer *buf, const afr_tile_stats *stats,
+                             const afr_params *params, const afr_sampler_params *sp, float *E,
+                             float *u, double *globals, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!sp || !E || !u || !globals || !ws) return AFR_E_INVALID;
+    const float vals[] = {sp->kappa, sp->lambda, sp->m, sp->gain};
+    for (float v : vals)
+        if (!finite(v)) return AFR_E_RANGE;
+    if (sp->kappa < 0.0f || sp->lambda < 0.0f || sp->kappa + sp->lambda > 1.0f) return AFR_E_RANGE;
+    if (sp->m < 0.0f || !(sp->gain > 0.0f)) return AFR_E_RANGE;
+    const int64_t nt = (int64_t)stats->tiles_x * stats->tiles_y;
+    if (nt > (int64_t(1) << 30)) return AFR_E_RANGE;
+    if (ws_bytes < sampler_ws_bytes((int32_t)nt)) return AFR_E_NOMEM;
+    return from_hip(launch_sampler_stats(*buf, *stats, *params, *sp, E, u, globals, ws, stream));
+}
+
+afr_status afr_sampler_tile_weights(int32_t width, int32_t height, int32_t tile, const float *E,
+                                    const double *globals, int32_t n_parts, float *weights,
+                                    void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!E || !weights || !ws) return AFR_E_INVALID;
+    if (n_parts <= 0 && !globals) return AFR_E_INVALID;
+    if (width < 1 || height < 1 || tile < 1) return AFR_E_RANGE;
+    const int64_t nt = (int64_t)((width + tile - 1) / tile) * ((height + tile - 1) / tile);
+    if (nt > kMaxSamplerTiles) return AFR_E_RANGE;
+    if (ws_bytes < sampler_ws_bytes((int32_t)nt)) return AFR_E_NOMEM;
+    return from_hip(launch_sampler_tile_weights(width, height, tile, E, globals, n_parts, weights,
+                                                ws, stream));
+}
+
+afr_status afr_sampler_select(int32_t width, int32_t height, int32_t tile, const float *E,
+                              int64_t n, const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
+                              void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!E || !ws || n < 0) return AFR_E_INVALID;
+    if (n > 0 && (!rnd || !x || !y)) return AFR_E_INVALID;
+    if (width < 1 || height < 1 || tile < 1) return AFR_E_RANGE;
+    const int64_t nt = (int64_t)((width + tile - 1) / tile) * ((height + tile - 1) / tile);
+    if (nt > kMaxSamplerTiles || n >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    if (ws_bytes < sampler_ws_bytes((int32_t)nt)) return AFR_E_NOMEM;
+    return from_hip(launch_sampler_select(width, height, tile, E, n, rnd, x, y, tile_out, ws,
+                                          stream));
+}
+
 afr_status afr_splat_sizes(int32_t width, int32_t height, const float *coverage,
                            const afr_splat_params *sp, float *size, hipStream_t stream) {
     if (!sp || !size) return AFR_E_INVALID;

@@ -204,6 +204,18 @@ hipError_t launch_scatter(const afr_deep_buffer &buf, const afr_tile_stats &stat
                           const afr_params &prm, const float *size, float max_size, float *rgb,
                           float *aux, float *coverage, hipStream_t st);
 
+constexpr int kMaxSamplerTiles = 65536;  // keeps the selection's draw times total below 2^64
+size_t sampler_ws_bytes(int32_t tiles);
+hipError_t launch_sampler_stats(const afr_deep_buffer &buf, const afr_tile_stats &stats,
+                                const afr_params &prm, const afr_sampler_params &sp, float *E,
+                                float *u, double *glob, void *ws, hipStream_t st);
+hipError_t launch_sampler_tile_weights(int32_t w, int32_t h, int32_t tile, const float *E,
+                                       const double *glob, int32_t n_parts, float *P, void *ws,
+                                       hipStream_t st);
+hipError_t launch_sampler_select(int32_t w, int32_t h, int32_t tile, const float *E, int64_t n,
+                                 const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
+                                 void *ws, hipStream_t st);
+
 size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                            const afr_params &p, const float *rgb, const float *aux,

@@ -218,10 +218,212 @@ __global__ __launch_bounds__(256) void k_smp_draw(const unsigned long long *__re
     if (tile) tile[k] = lo;
 }
 
+// ---- equal-error tiles along the Z-curve ---------------------------------------------------------
+
+__device__ inline uint32_t spread_bits(uint32_t v) {
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Position of tile (tx, ty) on the Z-curve over a tiles_x x tiles_y grid: the number of tiles
+// whose code is smaller. For each set bit of the code, the codes that agree above it and have a 0
+// there fix the high bits of x and of y and leave the low ones free; their count inside the grid
+// is a product of two clamped ranges.
+__device__ inline int z_rank(int tx, int ty, int tiles_x, int tiles_y) {
+    const uint32_t c = spread_bits(tx) | (spread_bits(ty) << 1);
+    long long rank = 0;
+    for (int i = 31; i >= 0; --i) {
+        if (!((c >> i) & 1u)) continue;
+        const int fx = (i + 1) / 2, fy = i / 2;  // free low bits of x and y below position i
+        // fixed high bits: those of c above i, with bit i cleared
+        const uint32_t hi = (c >> i) & ~1u;
+        uint32_t px = 0, py = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int pos = i + b;
+            if (pos > 31) break;
+            const uint32_t bit = (hi >> b) & 1u;
+            if (pos % 2 == 0) px |= bit << (pos / 2 - fx);
+            else py |= bit << ((pos - 1) / 2 - fy);
+        }
+        const long long nx = min(max((long long)tiles_x - ((long long)px << fx), 0ll), 1ll << fx);
+        const long long ny = min(max((long long)tiles_y - ((long long)py << fy), 0ll), 1ll << fy);
+        rank += nx * ny;
+    }
+    return (int)rank;
+}
+
+struct WeightsGeom {
+    int W, H, B, tiles_x, tiles_y, nt;
+};
+
+__global__ __launch_bounds__(256) void k_smp_zorder(WeightsGeom g, int32_t *perm) {
+    const int T = blockIdx.x * 256 + threadIdx.x;
+    if (T >= g.nt) return;
+    perm[z_rank(T % g.tiles_x, T / g.tiles_x, g.tiles_x, g.tiles_y)] = T;
+}
+
+__device__ inline int tile_area(int T, const WeightsGeom &g) {
+    const int tx = T % g.tiles_x, ty = T / g.tiles_x;
+    return min(g.B, g.W - tx * g.B) * min(g.B, g.H - ty * g.B);
+}
+
+// Exclusive prefix sums along the curve of the integer error weights (C) and of the tile areas (A).
+__global__ __launch_bounds__(kGThreads) void k_smp_zscan(const float *__restrict__ E,
+                                                          const int32_t *__restrict__ perm,
+                                                          WeightsGeom g, unsigned long long *C,
+                                                          long long *A) {
+    __shared__ float smax[kGThreads / kWave];
+    __shared__ unsigned long long sq[kGThreads / kWave];
+    __shared__ long long sa[kGThreads / kWave];
+    const int nt = g.nt;
+    float m = 0.0f;
+    for (int T = threadIdx.x; T < nt; T += kGThreads) {
+        const float x = E[T];
+        if (isfinite(x) && x > m) m = x;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == 0) smax[w] = m;
+    __syncthreads();
+    m = 0.0f;
+    for (int i = 0; i < kGThreads / kWave; ++i) m = fmaxf(m, smax[i]);
+    const double emax = m;
+    auto weight = [&](int T) -> unsigned long long {
+        const float x = E[T];
+        return (emax > 0.0 && isfinite(x) && x > 0.0f)
+                   ? (unsigned long long)floor((double)x / emax * 16777216.0)
+                   : 0ull;
+    };
+    const int per = (nt + kGThreads - 1) / kGThreads;
+    const int m0 = min(nt, threadIdx.x * per), m1 = min(nt, m0 + per);
+    unsigned long long rq = 0;
+    long long ra = 0;
+    for (int i = m0; i < m1; ++i) {
+        rq += weight(perm[i]);
+        ra += tile_area(perm[i], g);
+    }
+    unsigned long long iq = rq;
+    long long ia = ra;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned long long nq = __shfl_up(iq, o, kWave);
+        const long long na = __shfl_up(ia, o, kWave);
+        if (lane >= o) {
+            iq += nq;
+            ia += na;
+        }
+    }
+    if (lane == kWave - 1) {
+        sq[w] = iq;
+        sa[w] = ia;
+    }
+    __syncthreads();
+    unsigned long long bq = iq - rq;
+    long long ba = ia - ra;
+    for (int i = 0; i < w; ++i) {
+        bq += sq[i];
+        ba += sa[i];
+    }
+    for (int i = m0; i < m1; ++i) {
+        C[i] = bq;
+        A[i] = ba;
+        bq += weight(perm[i]);
+        ba += tile_area(perm[i], g);
+    }
+    if (threadIdx.x == kGThreads - 1) {
+        C[nt] = bq;
+        A[nt] = ba;
+    }
+}
+
+__device__ inline int parts_of(const double *glob, int n_parts, int nt) {
+    int N = n_parts;
+    if (N <= 0) {
+        const double t = glob[7];
+        const double r = isnan(t) ? 1.0 : rint(t);
+        N = r < 1.0 ? 1 : (r > (double)nt ? nt : (int)r);
+    }
+    return min(N, nt);
+}
+
+__global__ __launch_bounds__(256) void k_smp_zparts(const unsigned long long *__restrict__ C,
+                                                    WeightsGeom g, const double *glob, int n_parts,
+                                                    int32_t *part) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= g.nt) return;
+    const int N = parts_of(glob, n_parts, g.nt);
+    const unsigned long long Q = C[g.nt];
+    const unsigned long long p = Q ? C[m] * (unsigned long long)N / Q : 0ull;
+    part[m] = p < (unsigned long long)(N - 1) ? (int)p : N - 1;
+}
+
+__global__ __launch_bounds__(256) void k_smp_zweights(const int32_t *__restrict__ perm,
+                                                      const unsigned long long *__restrict__ C,
+                                                      const long long *__restrict__ A,
+                                                      const int32_t *__restrict__ part,
+                                                      WeightsGeom g, const double *glob,
+                                                      int n_parts, float *P) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= g.nt) return;
+    const int T = perm[m];
+    const double s = (double)(A[m + 1] - A[m]);
+    if (C[g.nt] == 0ull) {
+        P[T] = (float)s;
+        return;
+    }
+    const int pm = part[m];
+    int lo = 0, hi = m;  // first position of this part: part[lo] == pm, lo <= m
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (part[mid] < pm) lo = mid + 1;
+        else hi = mid;
+    }
+    int lo2 = m + 1, hi2 = g.nt;  // first position after this part
+    while (lo2 < hi2) {
+        const int mid = (lo2 + hi2) >> 1;
+        if (part[mid] <= pm) lo2 = mid + 1;
+        else hi2 = mid;
+    }
+    const int N = parts_of(glob, n_parts, g.nt);
+    const int next = m + 1 < g.nt ? part[m + 1] : N;
+    const int extra = max(0, next - pm - 1);
+    P[T] = (float)(s / (double)(A[lo2] - A[lo]) + (double)extra);
+}
+
 }  // namespace
 
 size_t sampler_ws_bytes(int32_t tiles) {
-    return align_up((size_t)tiles * sizeof(TilePart)) + align_up((size_t)(tiles + 1) * 8);
+    const size_t nt = (size_t)tiles;
+    return align_up(nt * sizeof(TilePart)) + align_up((nt + 1) * 8) +  // stats parts, select prefix
+           align_up(nt * 4) + 2 * align_up((nt + 1) * 8) + align_up(nt * 4);  // Z-curve order, C, A, parts
+}
+
+hipError_t launch_sampler_tile_weights(int32_t w, int32_t h, int32_t tile, const float *E,
+                                       const double *glob, int32_t n_parts, float *P, void *ws,
+                                       hipStream_t st) {
+    const int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;
+    const int nt = tiles_x * tiles_y;
+    char *p = static_cast<char *>(ws) + align_up((size_t)nt * sizeof(TilePart)) +
+              align_up((size_t)(nt + 1) * 8);
+    int32_t *perm = reinterpret_cast<int32_t *>(p);
+    p += align_up((size_t)nt * 4);
+    unsigned long long *C = reinterpret_cast<unsigned long long *>(p);
+    p += align_up((size_t)(nt + 1) * 8);
+    long long *A = reinterpret_cast<long long *>(p);
+    p += align_up((size_t)(nt + 1) * 8);
+    int32_t *part = reinterpret_cast<int32_t *>(p);
+    const WeightsGeom g{w, h, tile, tiles_x, tiles_y, nt};
+    const int nb = (nt + 255) / 256;
+    k_smp_zorder<<<nb, 256, 0, st>>>(g, perm);
+    k_smp_zscan<<<1, kGThreads, 0, st>>>(E, perm, g, C, A);
+    k_smp_zparts<<<nb, 256, 0, st>>>(C, g, glob, n_parts, part);
+    k_smp_zweights<<<nb, 256, 0, st>>>(perm, C, A, part, g, glob, n_parts, P);
+    return hipGetLastError();
 }
 
 hipError_t launch_sampler_stats(const afr_deep_buffer &buf, const afr_tile_stats &stats,

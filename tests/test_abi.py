@@ -179,3 +179,35 @@ def test_scatter_validation(afr):
         assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), 0x2000, m, 0x3000, None, None, None) == 2
     assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), None, 5.0, 0x3000, None, None, None) == 1
     assert lib.afr_reconstruct_scatter(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), 0x2000, 5.0, None, None, None, None) == 1
+
+
+def test_sampler_validation(afr):
+    lib = afr.library()
+    b = _fake_buffer(afr)
+    p = afr.Params(t_now=11.0)._c()
+    st = afr._TileStats(8, 2, 1, 0x1000)
+    need = lib.afr_sampler_workspace_bytes(2)
+    assert need > 0 and lib.afr_sampler_workspace_bytes(0) == 0
+    ok = afr.SamplerParams()
+    args = (0x2000, 0x3000, 0x4000, 0x5000)
+    for bad in (dict(kappa=-0.1), dict(kappa=0.8, lam=0.3), dict(m=-1.0), dict(gain=0.0),
+                dict(gain=float("inf"))):
+        sp = afr.SamplerParams(**{**ok.__dict__, **bad})
+        assert lib.afr_sampler_stats(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), ctypes.byref(sp._c()), *args, need, None) == 2, bad
+    assert lib.afr_sampler_stats(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), ctypes.byref(ok._c()), *args, need - 1, None) == 4
+    assert lib.afr_sampler_stats(ctypes.byref(b), ctypes.byref(st), ctypes.byref(p), ctypes.byref(ok._c()), None, 0x3000, 0x4000, 0x5000, need, None) == 1
+    # selection: at most 65536 tiles, a large enough workspace, arrays for n > 0
+    big = lib.afr_sampler_workspace_bytes(1 << 20)
+    assert lib.afr_sampler_select(4096, 4096, 8, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, 0x5000, big, None) == 2
+    assert lib.afr_sampler_select(64, 64, 8, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, 0x5000, 16, None) == 4
+    assert lib.afr_sampler_select(64, 64, 8, 0x1000, 10, None, 0x3000, 0x4000, None, 0x5000, big, None) == 1
+    assert lib.afr_sampler_select(64, 64, 0, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, 0x5000, big, None) == 2
+
+
+def test_sampler_tile_weights_validation(afr):
+    lib = afr.library()
+    need = lib.afr_sampler_workspace_bytes(64)
+    assert lib.afr_sampler_tile_weights(64, 64, 8, 0x1000, None, 0, 0x2000, 0x3000, need, None) == 1
+    assert lib.afr_sampler_tile_weights(64, 64, 8, 0x1000, 0x4000, 0, 0x2000, 0x3000, need - 1, None) == 4
+    assert lib.afr_sampler_tile_weights(4096, 4096, 4, 0x1000, None, 3, 0x2000, 0x3000, 1 << 30, None) == 2
+    assert lib.afr_sampler_tile_weights(64, 64, 8, None, None, 3, 0x2000, 0x3000, need, None) == 1
