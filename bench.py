@@ -181,10 +181,10 @@ def algorithmic_bytes(stage, n, n_binned, occupied, W, H, K, nt):
     """Bytes a kernel must move by its own inputs and outputs (FP16 storage: 2 B per field). The
     build's (bin, chunk) offset table (< 1% of the scatter's bytes) is left out."""
     e = 2
-    if stage == "bin_scatter":   # every field of every sample; one 32 B record per binned sample
-        return 24 * n + 32 * n_binned
+    if stage == "bin_scatter":   # every field of every sample; one 24 B record per binned sample
+        return 24 * n + 24 * n_binned   # (key, x, y) 16 B + binary16 payload 8 B
     if stage == "bin_select":    # every record once; all K slot planes, src and count written
-        return 32 * n_binned + K * W * H * (6 * e + 4) + W * H
+        return 24 * n_binned + K * W * H * (6 * e + 4) + W * H
     if stage == "estimate":      # count, colour and age of every occupied slot; 11 stats planes
         return W * H + occupied * 4 * e + 11 * 4 * nt
     if stage == "gather":        # every occupied slot once, count, 3-channel float image

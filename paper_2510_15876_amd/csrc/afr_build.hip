@@ -12,7 +12,8 @@
 //   3. k_bin_scatter  per chunk: coalesced loads of every field, an LDS counting sort by bin, and
 //                     32-byte records (order key, x, y, t, r, g, b) staged in LDS in bin order, a
 //                     window at a time, so that consecutive lanes store consecutive records of a
-//                     bin's run; invalid time or colour writes key 0
+//                     bin's run (for a binary16 buffer the payload is stored already encoded, 8
+//                     bytes); invalid time or colour writes key 0
 //   4. k_bin_select   per bin: its records' keys are counting-sorted by pixel into an LDS list
 //                     (in one sweep that holds the keys in registers when the bin fits the list,
 //                     else in passes over groups of rows), each pixel takes a register top-K over
@@ -20,6 +21,8 @@
 // Every decision is integer or an exact comparison of stored float32 inputs, so the result is
 // bit-exact and independent of launch shape and atomic order (atomics only order records inside a
 // group that is sorted by key afterwards).
+#include <type_traits>
+
 #include "afr_internal.h"
 
 namespace afr {
@@ -232,8 +235,9 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 32, "staged record is 32 bytes");
 
-// The bucket holds each record as two 16-byte halves in separate arrays: (key, x, y), read by the
-// selection's sweep, and (t, r, g, b), read only for the records a pixel keeps.
+// The bucket holds each record in two arrays: (key, x, y), 16 bytes, read by the selection's sweep,
+// and the payload, read only for the records a pixel keeps: (t, r, g, b) as float4 for a binary32
+// buffer, or already encoded as four binary16 values (age, r | g, b) in 8 bytes for a binary16 one.
 struct alignas(16) KeyXY {
     unsigned long long key;
     float x, y;
@@ -241,12 +245,18 @@ struct alignas(16) KeyXY {
 static_assert(sizeof(KeyXY) == 16, "record half is 16 bytes");
 struct Bucket {
     KeyXY *a;
-    float4 *b;
+    float4 *b;  // binary32 payload
+    uint2 *h;   // binary16 payload (same memory as b)
 };
 struct BinRecs {
     const KeyXY *a;
     const float4 *b;
+    const uint2 *h;
 };
+
+__device__ inline unsigned pack_half2(__half lo, __half hi) {
+    return (unsigned)__half_as_ushort(lo) | ((unsigned)__half_as_ushort(hi) << 16);
+}
 
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
 // position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
@@ -308,7 +318,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
             const Record e = stage[q];
             const int d = tab[bin_of(e.x, e.y, g)] + w0 + q;
             bucket.a[d] = KeyXY{e.key, e.x, e.y};
-            bucket.b[d] = make_float4(e.t, e.r, e.g, e.b);
+            if (c.fp16)
+                bucket.h[d] = make_uint2(
+                    pack_half2(Codec<__half>::enc_time(e.t, c.t_ref), Codec<__half>::enc(e.r)),
+                    pack_half2(Codec<__half>::enc(e.g), Codec<__half>::enc(e.b)));
+            else
+                bucket.b[d] = make_float4(e.t, e.r, e.g, e.b);
         }
         __syncthreads();
     }
@@ -337,12 +352,42 @@ __device__ inline void store_record(const afr_deep_buffer &out, size_t o, int e,
     }
 }
 
+// Binary16 mode: the select keeps each listed record's encoded offsets (ox | oy << 16) in LDS, so
+// that a kept record's fetch reads only its (t, r, g, b) half.
+template <typename S>
+constexpr bool kOxyInList = std::is_same<S, __half>::value;
+
+__device__ inline unsigned encode_oxy(float x, float y) {
+    return (unsigned)__half_as_ushort(Codec<__half>::enc(x - floorf(x))) |
+           ((unsigned)__half_as_ushort(Codec<__half>::enc(y - floorf(y))) << 16);
+}
+
+// Stores a kept binary16 record from its encoded offsets, stream index and encoded payload.
+__device__ inline void store_record_oxy(const afr_deep_buffer &out, size_t o, unsigned oxy, int src,
+                                        const uint2 &h) {
+    auto lo = [](unsigned v) { return __ushort_as_half((unsigned short)(v & 0xffffu)); };
+    auto hi = [](unsigned v) { return __ushort_as_half((unsigned short)(v >> 16)); };
+    static_cast<__half *>(out.ox)[o] = lo(oxy);
+    static_cast<__half *>(out.oy)[o] = hi(oxy);
+    static_cast<__half *>(out.tage)[o] = lo(h.x);
+    static_cast<__half *>(out.r)[o] = hi(h.x);
+    static_cast<__half *>(out.g)[o] = lo(h.y);
+    static_cast<__half *>(out.b)[o] = hi(h.y);
+    if (out.src) out.src[o] = src;
+}
+
 // Stores record e of the bin (or an empty slot when e < 0) at slot-plane offset o.
 template <typename S>
 __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const BinRecs &rs, int e) {
     KeyXY a{0ull, 0.0f, 0.0f};
     float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (e >= 0) {
+    if constexpr (kOxyInList<S>) {
+        if (e >= 0) {
+            a = rs.a[e];
+            store_record_oxy(out, o, encode_oxy(a.x, a.y), key_index(a.key), rs.h[e]);
+            return;
+        }
+    } else if (e >= 0) {
         a = rs.a[e];
         c = rs.b[e];
     }
@@ -355,7 +400,7 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Bi
 template <typename S, int KMAX>
 __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t hw,
                                     const BinRecs &recs, const unsigned long long *keys,
-                                    const unsigned short *pos, int l0, int l1) {
+                                    const unsigned short *pos, const unsigned *oxy, int l0, int l1) {
     const int K = out.k;
     int nvalid = 0;
     if constexpr (KMAX <= 64) {
@@ -368,7 +413,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
         }
         for (int l = l0; l < l1; ++l) {
             unsigned long long c = keys[l];
-            int ce = pos[l];
+            int ce = l;  // list index of the candidate
             nvalid += c != 0ull;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
@@ -389,19 +434,33 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
         for (int k0 = 0; k0 < KMAX; k0 += kG) {
             KeyXY a[kG];
             float4 c[kG];
+            uint2 h[kOxyInList<S> ? kG : 1];
 #pragma unroll
             for (int j = 0; j < kG; ++j) {
                 a[j] = KeyXY{0ull, 0.0f, 0.0f};
                 c[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (kOxyInList<S>) h[j] = make_uint2(0u, 0u);
                 if (k0 + j < n) {
-                    a[j] = recs.a[tp[k0 + j]];
-                    c[j] = recs.b[tp[k0 + j]];
+                    const int e = pos[tp[k0 + j]];
+                    if constexpr (kOxyInList<S>) {
+                        h[j] = recs.h[e];
+                    } else {
+                        a[j] = recs.a[e];
+                        c[j] = recs.b[e];
+                    }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kG; ++j)
-                if (k0 + j < K)
-                    store_record<S>(out, (size_t)(k0 + j) * hw + p, k0 + j < n ? 0 : -1, a[j], c[j]);
+            for (int j = 0; j < kG; ++j) {
+                if (k0 + j >= K) continue;
+                const size_t o = (size_t)(k0 + j) * hw + p;
+                if constexpr (kOxyInList<S>) {
+                    if (k0 + j < n) store_record_oxy(out, o, oxy[tp[k0 + j]], key_index(top[k0 + j]), h[j]);
+                    else store_record<S>(out, o, -1, a[j], c[j]);
+                } else {
+                    store_record<S>(out, o, k0 + j < n ? 0 : -1, a[j], c[j]);
+                }
+            }
         }
         out.count[p] = (uint8_t)n;
     } else {
@@ -477,10 +536,11 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     int *poff = sel_sm;  // [npx + 1]
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(sel_sm + ((npx + 2) & ~1));
     unsigned short *pos = reinterpret_cast<unsigned short *>(keys + kListCap);
+    unsigned *oxy = reinterpret_cast<unsigned *>(pos + kListCap);  // binary16 only
     const int b = blockIdx.x;
     const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
     const int nrec = s1 - s0;
-    const BinRecs recs{bucket.a + s0, bucket.b + s0};
+    const BinRecs recs{bucket.a + s0, bucket.b + s0, bucket.h + s0};
     const int bx0 = (b % g.nbx) * g.bw, by0 = (b / g.nbx) * g.bh;
     const int W = out.width, H = out.height;
     const size_t hw = (size_t)W * H;
@@ -494,6 +554,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
         // One sweep: each thread keeps its records' keys, pixels and ranks in registers.
         unsigned long long kk[kSelPer];
         int id[kSelPer], rk[kSelPer];
+        unsigned ox[kOxyInList<S> ? kSelPer : 1];
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j) {
             const int e = j * kSelThreads + threadIdx.x;
@@ -502,6 +563,7 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
                 kk[j] = r.key;
                 id[j] = local_id(r.x, r.y);
                 rk[j] = atomicAdd(&poff[id[j]], 1);
+                if constexpr (kOxyInList<S>) ox[j] = encode_oxy(r.x, r.y);
             }
         }
         __syncthreads();
@@ -515,13 +577,14 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
                 const int l = poff[id[j]] + rk[j];
                 keys[l] = kk[j];
                 pos[l] = (unsigned short)e;
+                if constexpr (kOxyInList<S>) oxy[l] = ox[j];
             }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < rows * g.bw; q += kSelThreads) {
             const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
             if (px < W)
-                select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, poff[q],
+                select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, oxy, poff[q],
                                       poff[q + 1]);
         }
         return;
@@ -552,13 +615,14 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
                     const int l = atomicAdd(&poff[q], 1) - lo;
                     keys[l] = r.key;
                     pos[l] = (unsigned short)e;
+                    if constexpr (kOxyInList<S>) oxy[l] = encode_oxy(r.x, r.y);
                 }
             }
             __syncthreads();
             for (int q = q0 + threadIdx.x; q < q1; q += kSelThreads) {
                 const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
                 if (px < W)
-                    select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos,
+                    select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, oxy,
                                           q == q0 ? 0 : poff[q - 1] - lo, poff[q] - lo);
             }
         } else {
@@ -572,16 +636,18 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     }
 }
 
+template <typename S>
 size_t select_shmem(const BinGeom &g) {
     return (size_t)((g.bw * g.bh + 2) & ~1) * sizeof(int) +
-           kListCap * (sizeof(unsigned long long) + sizeof(unsigned short));
+           kListCap * (sizeof(unsigned long long) + sizeof(unsigned short) +
+                       (kOxyInList<S> ? sizeof(unsigned) : 0));
 }
 
 template <typename S>
 hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *ot,
                          int nchunks, Bucket bucket, const int32_t *bad_tab,
                          unsigned long long *dropped, hipStream_t st) {
-    const size_t shmem = select_shmem(g);
+    const size_t shmem = select_shmem<S>(g);
     const dim3 grid(g.nb), block(kSelThreads);
     if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
     else if (out.k <= 8) k_bin_select<S, 8><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
@@ -652,8 +718,9 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     const int64_t len = (int64_t)g.nb * nch;
     const int nsb = (int)((len + kScanBlock - 1) / kScanBlock);
     const size_t half = align_up((size_t)(s.n > 0 ? s.n : 1) * sizeof(KeyXY));
-    const Bucket bucket{static_cast<KeyXY *>(ws.bucket),
-                        reinterpret_cast<float4 *>(static_cast<char *>(ws.bucket) + half)};
+    char *pay = static_cast<char *>(ws.bucket) + half;
+    const Bucket bucket{static_cast<KeyXY *>(ws.bucket), reinterpret_cast<float4 *>(pay),
+                        reinterpret_cast<uint2 *>(pay)};
     if (s.n > 0) {
         if (s.vx)
             k_bin_count<true><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
