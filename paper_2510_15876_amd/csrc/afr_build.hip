@@ -18,6 +18,8 @@
 //                     (in one sweep that holds the keys in registers when the bin fits the list,
 //                     else in passes over groups of rows), each pixel takes a register top-K over
 //                     its keys, and the selected records are stored to the slot planes
+// Chunks are dealt to XCDs in contiguous runs, so that the table entries of neighbouring chunks
+// (adjacent in the bin-major table) and the ends of their runs in each bin meet in one L2.
 // Every decision is integer or an exact comparison of stored float32 inputs, so the result is
 // bit-exact and independent of launch shape and atomic order (atomics only order records inside a
 // group that is sorted by key afterwards).
@@ -119,7 +121,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, Vali
                                                              int32_t *bad_tab) {
     __shared__ int hist[kMaxBins];
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) hist[b] = 0;
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)chunk * kChunk;
     float xs[kChunkPer], ys[kChunkPer];
     float ts[MOTION ? kChunkPer : 1], us[MOTION ? kChunkPer : 1], vs[MOTION ? kChunkPer : 1];
 #pragma unroll
@@ -147,9 +150,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, Vali
     }
     __syncthreads();
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
-        ht[(size_t)b * nchunks + blockIdx.x] = hist[b];
+        ht[(size_t)b * nchunks + chunk] = hist[b];
     bad = block_sum_int<kChunkThreads>(bad);
-    if (threadIdx.x == 0) bad_tab[blockIdx.x] = bad;  // samples outside the image
+    if (threadIdx.x == 0) bad_tab[chunk] = bad;  // samples outside the image
 }
 
 // Block-wide exclusive scan of one int per thread (blockDim = NT).
@@ -270,7 +273,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
     int *tab = scat_sm;                                                  // [nb]
     Record *stage = reinterpret_cast<Record *>(scat_sm + ((g.nb + 3) & ~3));  // [kWin]
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) tab[b] = 0;
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)chunk * kChunk;
     Record rec[kChunkPer];
 #pragma unroll
     for (int j = 0; j < kChunkPer; ++j) {  // coalesced loads of every field
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         if (bin[j] >= 0) sp[j] += tab[bin[j]];  // position in the chunk's bin-sorted order
     __syncthreads();
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
-        tab[b] = ot[(size_t)b * nchunks + blockIdx.x] - tab[b];
+        tab[b] = ot[(size_t)b * nchunks + chunk] - tab[b];
     __syncthreads();
     for (int w0 = 0; w0 < nvalid; w0 += kWin) {
 #pragma unroll
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         __syncthreads();
     }
     bad = block_sum_int<kChunkThreads>(bad);
-    if (threadIdx.x == 0) bad_tab[nchunks + blockIdx.x] = bad;  // invalid time or colour
+    if (threadIdx.x == 0) bad_tab[nchunks + chunk] = bad;  // invalid time or colour
 }
 
 // Stores a record (key, x, y | t, r, g, b) or, when e < 0, an empty slot at slot-plane offset o.
