@@ -1,5 +1,5 @@
 // afr_estimate_gradients (see afr_tile_estimate.h): for tiles of edge <= 8 one 256-thread workgroup
-// per 64-pixel-wide strip of tiles, else one workgroup per tile. Workgroups are dealt to XCDs in
+// per 32-pixel-wide strip of tiles, else one workgroup per tile. Workgroups are dealt to XCDs in
 // contiguous bands so that the one-pixel halos neighbouring workgroups share hit one L2.
 #include "afr_tile_estimate.h"
 

@@ -11,7 +11,7 @@
 // variance merges per-pixel (weight, mean, M2) triples with the pairwise form of Welford's update.
 //
 // Two drivers share these routines: a strip kernel (afr_estimate_gradients, tiles of edge <= 8)
-// where a workgroup covers a 64-pixel-wide strip of tiles, so that each wave reads whole image rows
+// where a workgroup covers a 32-pixel-wide strip of tiles, so that each wave reads whole image rows
 // per slot plane, and a per-tile routine (tiles up to 16 px, and the batched kernel). Floating-point
 // contraction is off in every routine here, so a pixel's moments and a tile's reduction round the
 // same way in either driver and the statistics are identical bit for bit.
@@ -339,7 +339,7 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
 // ---- strip driver (tiles of edge <= 8) ----------------------------------------------------------
 
 constexpr int kStripThreads = 256;
-constexpr int kStripW = 64;                                  // pixels
+constexpr int kStripW = 32;                                  // pixels
 constexpr int kStripRegion = (kStripW + 2) * (8 + 2);        // region pixels, at most 660
 constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
 
