@@ -10,7 +10,7 @@ import pytest
 
 import afr_scenes as S
 import oracle as O
-from helpers import DEV, afr_mod, gpu_build, torch_mod
+from helpers import afr_mod, gpu_build, torch_mod
 
 pytestmark = pytest.mark.gpu
 

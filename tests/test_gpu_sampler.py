@@ -7,7 +7,6 @@ order: tile errors within 1e-6 relative, undersampling within 1e-7, the global f
 import numpy as np
 import pytest
 
-import afr_scenes as S
 import oracle as O
 from helpers import (DEV, afr_mod, gpu_build, params, stats_f32_as_f64, stats_to_gpu, torch_mod,
                      workload)

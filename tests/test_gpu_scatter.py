@@ -7,7 +7,6 @@ with LDS atomics in arrival order: max |C - C_ref| <= 1e-5 on [0, 1] colours, as
 import numpy as np
 import pytest
 
-import afr_scenes as S
 import oracle as O
 from helpers import (DEV, afr_mod, gpu_build, oracle_build_cached, params, stats_f32_as_f64,
                      stats_to_gpu, torch_mod, workload)
