@@ -33,10 +33,10 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = kScanThreads * kScanItems;
-constexpr int kChunkThreads = 1024;
-constexpr int kChunkPer = 8;
+constexpr int kChunkThreads = 512;  // two 512-thread scatter workgroups share a CU, so one loads
+constexpr int kChunkPer = 8;        // while the other sorts and stores
 constexpr int kChunk = kChunkThreads * kChunkPer;  // samples per chunk
-constexpr int kWin = 4096;  // records staged in LDS per scatter window (128 KiB of gfx950's 160 KiB)
+constexpr int kWin = 2048;  // records staged in LDS per scatter window (64 KiB: two workgroups per CU)
 constexpr int kBinW = 64;                          // bin width, px
 constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
 constexpr int kMaxBinPx = 2048;                    // pixels per bin (rows grow from 4 to 32)
