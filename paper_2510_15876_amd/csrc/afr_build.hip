@@ -398,6 +398,12 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Bi
     store_record<S>(out, o, e, a, c);
 }
 
+// LDS slot of list entry l: one pad entry after every 16, so that the lanes of a wave, which read
+// their pixels' lists at a stride of about 16 entries when pixels hold about 16 records, spread over
+// the LDS banks instead of meeting in two.
+constexpr int kListSlots = kListCap + kListCap / 16;
+__device__ inline int swz(int l) { return l + (l >> 4); }
+
 // Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: insertion into a
 // descending register list (one unsigned compare and selects per entry, the same instruction stream
 // in every lane). Larger K: repeated maximum scans. The selected records are then loaded together.
@@ -416,7 +422,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
             tp[k] = 0;
         }
         for (int l = l0; l < l1; ++l) {
-            unsigned long long c = keys[l];
+            unsigned long long c = keys[swz(l)];
             int ce = l;  // list index of the candidate
             nvalid += c != 0ull;
 #pragma unroll
@@ -445,7 +451,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
                 c[j] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if constexpr (kOxyInList<S>) h[j] = make_uint2(0u, 0u);
                 if (k0 + j < n) {
-                    const int e = pos[tp[k0 + j]];
+                    const int e = pos[swz(tp[k0 + j])];
                     if constexpr (kOxyInList<S>) {
                         h[j] = recs.h[e];
                     } else {
@@ -459,7 +465,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
                 if (k0 + j >= K) continue;
                 const size_t o = (size_t)(k0 + j) * hw + p;
                 if constexpr (kOxyInList<S>) {
-                    if (k0 + j < n) store_record_oxy(out, o, oxy[tp[k0 + j]], key_index(top[k0 + j]), h[j]);
+                    if (k0 + j < n) store_record_oxy(out, o, oxy[swz(tp[k0 + j])], key_index(top[k0 + j]), h[j]);
                     else store_record<S>(out, o, -1, a[j], c[j]);
                 } else {
                     store_record<S>(out, o, k0 + j < n ? 0 : -1, a[j], c[j]);
@@ -468,7 +474,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
         }
         out.count[p] = (uint8_t)n;
     } else {
-        for (int l = l0; l < l1; ++l) nvalid += keys[l] != 0ull;
+        for (int l = l0; l < l1; ++l) nvalid += keys[swz(l)] != 0ull;
         const int n = min(nvalid, K);
         unsigned long long prev = ~0ull;
         for (int k = 0; k < K; ++k) {
@@ -476,10 +482,10 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
             int be = 0;
             if (k < n) {
                 for (int l = l0; l < l1; ++l) {
-                    const unsigned long long c = keys[l];
+                    const unsigned long long c = keys[swz(l)];
                     const bool take = c < prev && c > best;
                     best = take ? c : best;
-                    be = take ? (int)pos[l] : be;
+                    be = take ? (int)pos[swz(l)] : be;
                 }
                 prev = best;
             }
@@ -521,8 +527,9 @@ __device__ inline void select_pixel_scan(const afr_deep_buffer &out, size_t p, s
 // Key, x and y of a record in one 16-byte load.
 __device__ inline KeyXY load_key_xy(const KeyXY *r) { return *r; }
 
-// One workgroup per bin. LDS: per-pixel offsets [npx + 1], then the key list [kListCap] (u64)
-// and the records' positions in the bin [kListCap] (u16).
+// One workgroup per bin. LDS: per-pixel offsets [npx + 1], then the key list (u64), the records'
+// positions in the bin (u16) and, for binary16 buffers, their encoded offsets (u32), each with
+// kListSlots entries (kListCap records plus the pads of swz).
 template <typename S, int KMAX>
 __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out, BinGeom g,
                                                             const int32_t *ot, int nchunks,
@@ -539,8 +546,8 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     const int npx = g.bw * g.bh;
     int *poff = sel_sm;  // [npx + 1]
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(sel_sm + ((npx + 2) & ~1));
-    unsigned short *pos = reinterpret_cast<unsigned short *>(keys + kListCap);
-    unsigned *oxy = reinterpret_cast<unsigned *>(pos + kListCap);  // binary16 only
+    unsigned short *pos = reinterpret_cast<unsigned short *>(keys + kListSlots);
+    unsigned *oxy = reinterpret_cast<unsigned *>(pos + kListSlots);  // binary16 only
     const int b = blockIdx.x;
     const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
     const int nrec = s1 - s0;
@@ -579,9 +586,9 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
             const int e = j * kSelThreads + threadIdx.x;
             if (e < nrec) {
                 const int l = poff[id[j]] + rk[j];
-                keys[l] = kk[j];
-                pos[l] = (unsigned short)e;
-                if constexpr (kOxyInList<S>) oxy[l] = ox[j];
+                keys[swz(l)] = kk[j];
+                pos[swz(l)] = (unsigned short)e;
+                if constexpr (kOxyInList<S>) oxy[swz(l)] = ox[j];
             }
         }
         __syncthreads();
@@ -617,9 +624,9 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
                 const int q = local_id(r.x, r.y);
                 if (q >= q0 && q < q1) {
                     const int l = atomicAdd(&poff[q], 1) - lo;
-                    keys[l] = r.key;
-                    pos[l] = (unsigned short)e;
-                    if constexpr (kOxyInList<S>) oxy[l] = encode_oxy(r.x, r.y);
+                    keys[swz(l)] = r.key;
+                    pos[swz(l)] = (unsigned short)e;
+                    if constexpr (kOxyInList<S>) oxy[swz(l)] = encode_oxy(r.x, r.y);
                 }
             }
             __syncthreads();
@@ -643,8 +650,8 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
 template <typename S>
 size_t select_shmem(const BinGeom &g) {
     return (size_t)((g.bw * g.bh + 2) & ~1) * sizeof(int) +
-           kListCap * (sizeof(unsigned long long) + sizeof(unsigned short) +
-                       (kOxyInList<S> ? sizeof(unsigned) : 0));
+           kListSlots * (sizeof(unsigned long long) + sizeof(unsigned short) +
+                         (kOxyInList<S> ? sizeof(unsigned) : 0));
 }
 
 template <typename S>
