@@ -213,7 +213,10 @@ def roofline_entry(stage, kernel, nbytes, ms, traffic, pairs):
         return {"bound": "alu", "kernel": kernel, "achieved": round(tf, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
-                "algorithmic_flops": flops, "ms_per_launch": round(ms, 5)}
+                "algorithmic_flops": flops, "ms_per_launch": round(ms, 5),
+                # packed FP32 is not used: one FMA per lane per cycle is the usable rate
+                "frac_of_unpacked_fp32": round(tf / (FP32_VECTOR_PEAK_TFLOPS / 2), 4),
+                "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -346,6 +349,24 @@ def main():
     scatter_ms["adaptive_mean_size"] = round(float(size.mean().item()), 4)
     fwd_ms = stage_ms["estimate"] + stage_ms["gather"]
 
+    # the gather at R = 1 (9 pixels per block instead of 25) on the same buffers: the radius at
+    # which the gather is bound by HBM rather than by arithmetic
+    p1 = afr.Params(t_now=wl.t_now, radius=1)
+    afr.estimate_gradients(bufs[0], p1, out=stats[0])
+    afr.reconstruct(bufs[0], stats[0], p1, rgb=rgb_plain, want_aux=False)
+    torch.cuda.synchronize()
+    pe[0].record()
+    for i in range(n_plain):
+        afr.reconstruct(bufs[i % ROTATE], stats[i % ROTATE], p1, rgb=rgb_plain, want_aux=False)
+    pe[1].record()
+    torch.cuda.synchronize()
+    r1_ms = pe[0].elapsed_time(pe[1]) / n_plain
+    g_bytes = algorithmic_bytes("gather", n, n_binned, occupied, W, H, K, nt)
+    gather_r1 = {"ms": round(r1_ms, 5), "hbm_gbs": round(g_bytes / (r1_ms * 1e-3) / 1e9, 1),
+                 "hbm_frac": round(g_bytes / (r1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for r in range(ROTATE):  # statistics of the R = 2 parameters again
+        afr.estimate_gradients(bufs[r], p, out=stats[r])
+
     out = {
         "metric": "reconstructed Mpixel/s (build + estimate + gather per frame)",
         "value": round(W * H / (ms_step * 1e-3) / 1e6, 3),
@@ -369,6 +390,7 @@ def main():
         "samples_filtered_per_s": round(occupied / (fwd_ms * 1e-3), 1),
         "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
         "plain_reconstruct_ms": round(plain_ms, 5),
+        "gather_r1": gather_r1,
         "scatter_reconstruct_ms": scatter_ms,
         "roofline": roofline_entry(dom, dom_kernel, dom_bytes, stage_ms[dom], traffic, pairs),
         "copy_gbs_measured": round(copy_gbs, 1),
