@@ -501,8 +501,7 @@ def fwd_bwd(torch, afr, S, dev, frames):
         p = afr.Params(t_now=wl.t_now)
         st = afr.estimate_gradients(buf, p)
         rgb, aux = afr.reconstruct(buf, st, p)
-        d = rgb - gt
-        g = d / (d.numel() * torch.sqrt((d * d).mean()) * frames)
+        _, g = afr.rms_loss(rgb, gt, 1.0 / frames)   # gradient of the mean per-frame RMS error
         return afr.reconstruct_backward(buf, st, p, rgb, aux, g)
 
     frame(0)

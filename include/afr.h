@@ -286,6 +286,21 @@ afr_status afr_sampler_select(int32_t width, int32_t height, int32_t tile, const
                               void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * RMS error against a reference image (the per-frame error the evaluation of Sec. 7 reports, and the
+ * loss the filter parameters sigma and tau are fit on) and its gradient, for chaining into
+ * afr_reconstruct_backward.
+ *   loss = scale * sqrt(sum_i (img_i - ref_i)^2 / n),  grad_i = scale * (img_i - ref_i) / (n * rms)
+ * (grad 0 when rms is 0). Sums are FP64 in a fixed order, so results do not change between runs.
+ *   img, ref   device float [n] (any layout, the same for both)
+ *   loss       optional device double: receives the loss
+ *   grad       optional device float [n]: receives the gradient
+ *   ws         device workspace of afr_rms_workspace_bytes() bytes
+ * ------------------------------------------------------------------------------------------- */
+size_t afr_rms_workspace_bytes(void);
+afr_status afr_rms_loss(const float *img, const float *ref, int64_t n, double scale, double *loss,
+                        float *grad, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Crosshair gradients (Sec. 4.1, 4.2). A crosshair is a centre sample at (x, y, t), the four samples
  * taken at the same instant one pixel away, (x -/+ 1, y, t) and (x, y -/+ 1, t), and an earlier
  * sample taken at the same sub-pixel spot, (x, y, t0). afr_crosshairs gives each as a device int32

@@ -23,7 +23,7 @@ __all__ = [
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
     "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
     "SplatParams", "splat_sizes", "reconstruct_scatter", "SamplerParams", "sampler_stats",
-    "sampler_select", "sampler_tile_weights", "SAMPLER_GLOBALS",
+    "sampler_select", "sampler_tile_weights", "SAMPLER_GLOBALS", "rms_loss",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -112,6 +112,11 @@ def library():
                                                  vp, vp, P(vp)]
     lib.afr_estimate_gradients.restype = st
     lib.afr_estimate_gradients.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp]
+    lib.afr_rms_workspace_bytes.restype = ctypes.c_size_t
+    lib.afr_rms_workspace_bytes.argtypes = []
+    lib.afr_rms_loss.restype = st
+    lib.afr_rms_loss.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp,
+                                 ctypes.c_size_t, vp]
     lib.afr_sampler_workspace_bytes.restype = ctypes.c_size_t
     lib.afr_sampler_workspace_bytes.argtypes = [ctypes.c_int32]
     lib.afr_sampler_stats.restype = st
@@ -401,6 +406,29 @@ def estimate_gradients(buf: DeepBuffer, params: Params, out: Optional[torch.Tens
     _check(lib.afr_estimate_gradients(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc),
                                       _stream(stream)), "afr_estimate_gradients")
     return out
+
+
+def rms_loss(img: torch.Tensor, ref: torch.Tensor, scale: float = 1.0, want_grad: bool = True,
+             loss: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
+             stream=None):
+    """``(loss, grad)``: ``scale * RMS(img - ref)`` as a float64 device scalar tensor and its
+    gradient with respect to ``img`` (or None), see afr_rms_loss."""
+    lib = library()
+    if (img.dtype != torch.float32 or ref.dtype != torch.float32 or not img.is_contiguous()
+            or not ref.is_contiguous() or img.shape != ref.shape or img.device != ref.device):
+        raise AfrError("img and ref must be contiguous float32 device tensors of one shape")
+    dev = img.device
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+    if grad is None and want_grad:
+        grad = torch.empty_like(img)
+    wsb = lib.afr_rms_workspace_bytes()
+    ws = _workspace(wsb, dev, "rms")
+    n = img.numel()
+    _check(lib.afr_rms_loss(_ptr(img) if n else None, _ptr(ref) if n else None, n, float(scale),
+                            _ptr(loss), _ptr(grad) if (grad is not None and n) else None, _ptr(ws),
+                            wsb, _stream(stream)), "afr_rms_loss")
+    return loss, grad
 
 
 def sampler_stats(buf: DeepBuffer, stats: torch.Tensor, params: Params, sp: SamplerParams,

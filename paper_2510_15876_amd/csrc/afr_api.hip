@@ -73,6 +73,17 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
     return build_checked(s, out, ws, ws_bytes, dropped_dev, stream, stage_end);
 }
 
+size_t afr_rms_workspace_bytes(void) { return rms_ws_bytes(); }
+
+afr_status afr_rms_loss(const float *img, const float *ref, int64_t n, double scale, double *loss,
+                        float *grad, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || !ws) return AFR_E_INVALID;
+    if (n > 0 && (!img || !ref)) return AFR_E_INVALID;
+    if (!std::isfinite(scale)) return AFR_E_RANGE;
+    if (ws_bytes < rms_ws_bytes()) return AFR_E_NOMEM;
+    return from_hip(launch_rms_loss(img, ref, n, scale, loss, grad, ws, stream));
+}
+
 size_t afr_sampler_workspace_bytes(int32_t tiles) {
     if (tiles < 1) return 0;
     return sampler_ws_bytes(tiles);

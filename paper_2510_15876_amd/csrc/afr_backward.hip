@@ -466,7 +466,7 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             const float uy = (float)(n - R) + dy;
             const float dyn2 = uy * uy;
             const bool rok = jj >= 0 && jj < kTB;
-            float rx = 0.0f, ry = 0.0f, ra = 0.0f;
+            float rx = 0.0f, rh = 0.0f;  // sums of hwt dx^2 and of hwt over the row
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 const int ii = cc - m;
@@ -478,12 +478,11 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
                 gb += w * g4.z;
                 const float hwt = w * (g4.x * cr + g4.y * cg + g4.z * cb - g4.w);
                 rx += hwt * dx2[m];
-                ry += hwt;
-                ra += hwt;
+                rh += hwt;
             }
             Sx += (double)rx;
-            Sy += (double)ry * dyn2;
-            Sa += (double)ra * a2;
+            Sy += (double)rh * dyn2;
+            Sa += (double)rh * a2;
             // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2)
             yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
         }

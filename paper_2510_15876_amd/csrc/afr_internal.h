@@ -216,6 +216,10 @@ hipError_t launch_sampler_select(int32_t w, int32_t h, int32_t tile, const float
                                  const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
                                  void *ws, hipStream_t st);
 
+size_t rms_ws_bytes();
+hipError_t launch_rms_loss(const float *img, const float *ref, int64_t n, double scale,
+                           double *loss, float *grad, void *ws, hipStream_t st);
+
 size_t backward_ws_bytes(int32_t w, int32_t h, int32_t k, int32_t radius);
 hipError_t launch_backward(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                            const afr_params &p, const float *rgb, const float *aux,

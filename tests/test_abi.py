@@ -211,3 +211,14 @@ def test_sampler_tile_weights_validation(afr):
     assert lib.afr_sampler_tile_weights(64, 64, 8, 0x1000, 0x4000, 0, 0x2000, 0x3000, need - 1, None) == 4
     assert lib.afr_sampler_tile_weights(4096, 4096, 4, 0x1000, None, 3, 0x2000, 0x3000, 1 << 30, None) == 2
     assert lib.afr_sampler_tile_weights(64, 64, 8, None, None, 3, 0x2000, 0x3000, need, None) == 1
+
+
+def test_rms_loss_validation(afr):
+    lib = afr.library()
+    need = lib.afr_rms_workspace_bytes()
+    assert need > 0
+    assert lib.afr_rms_loss(0x1000, 0x2000, -1, 1.0, None, None, 0x3000, need, None) == 1
+    assert lib.afr_rms_loss(None, 0x2000, 10, 1.0, None, None, 0x3000, need, None) == 1
+    assert lib.afr_rms_loss(0x1000, 0x2000, 10, 1.0, None, None, None, need, None) == 1
+    assert lib.afr_rms_loss(0x1000, 0x2000, 10, float("nan"), None, None, 0x3000, need, None) == 2
+    assert lib.afr_rms_loss(0x1000, 0x2000, 10, 1.0, None, None, 0x3000, need - 1, None) == 4
