@@ -417,6 +417,13 @@ def main():
         err = float(np.abs(rgbs[0].cpu().numpy() - orgb).max())
         out["max_abs_err_vs_fp64"] = err
         out["accuracy_gate_1e-5"] = bool(err <= 1e-5)
+        # the storage error: the FP16-storage image against the FP64 reference on the FP32 buffer
+        ob32, _ = O.build_buffer(wl.stream, W, H, K, "fp32", wl.t_ref)
+        orgb32, _, _ = O.forward(ob32, O.Params(t_now=wl.t_now, radius=args.radius))
+        e16 = np.abs(rgbs[0].cpu().numpy() - orgb32)
+        out["fp16_storage_err_vs_fp64_fp32_buffer"] = {
+            "max": float(e16.max()), "p99": float(np.quantile(e16, 0.99)),
+            "mean": float(e16.mean()), "gate_2e-3": bool(e16.max() <= 2e-3)}
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(torch, afr, S, dev, args.frames)
