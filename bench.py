@@ -48,6 +48,9 @@ def _args():
     ap.add_argument("--no-crosshair", action="store_true", help="skip the crosshair-estimator leg")
     ap.add_argument("--sampler-frames", type=int, default=10,
                     help="frames of the closed-loop sampling leg (0 skips it)")
+    ap.add_argument("--two-stream-frames", type=int, default=None,
+                    help="frames of the two-stream leg (default 2 x steps; 0 skips it, as profiled "
+                         "runs do, since its kernels overlap and would skew per-kernel averages)")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
@@ -257,6 +260,7 @@ def main():
     stats = [torch.empty((afr.NSTAT,) + afr.tiles_shape(W, H, p.tile), device=dev) for _ in range(ROTATE)]
     rgbs = [torch.empty((3, H, W), device=dev) for _ in range(ROTATE)]
     drop = torch.zeros(1, dtype=torch.int64, device=dev)
+    drops2 = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(2)]
     nst = afr.build_stage_count()
 
     def step(r, ev=None, i=0):
@@ -313,6 +317,37 @@ def main():
     dom_kernel = kernel_of(dom, K, args.radius, tpw)
     traffic = read_traffic(dom_kernel)
     copy_gbs = copy_bandwidth(torch, dev)
+
+    # two streams (default priority), alternate frames: one frame's build (HBM-bound) can run beside
+    # another frame's gather (arithmetic- and LDS-bound); frames are independent
+    streams2 = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    n2 = 2 * args.steps if args.two_stream_frames is None else args.two_stream_frames
+
+    def two_stream_frames(n):
+        e2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        e2[0].record()
+        for s2 in streams2:
+            s2.wait_event(e2[0])
+        for i in range(n):
+            r = i % ROTATE
+            with torch.cuda.stream(streams2[i % 2]):
+                afr.build_deep_buffer(*streams[r], W, H, K, "fp16", wl.t_ref, out=bufs[r],
+                                      dropped=drops2[i % 2])
+                afr.estimate_gradients(bufs[r], p, out=stats[r])
+                afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
+        for s2 in streams2:
+            torch.cuda.current_stream().wait_stream(s2)
+        e2[1].record()
+        torch.cuda.synchronize()
+        return e2[0].elapsed_time(e2[1]) / n
+
+    two_streams = None
+    if n2 > 0:
+        two_stream_frames(2 * max(1, args.warmup))   # each stream's workspaces are allocated here
+        two_stream_ms = two_stream_frames(n2)
+        two_streams = {"ms_per_frame": round(two_stream_ms, 5),
+                       "mpixel_per_s": round(W * H / (two_stream_ms * 1e-3) / 1e6, 3)}
 
     # plain direct gather on the same buffers, for the plain-vs-tiled comparison
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -389,6 +424,7 @@ def main():
         "forward_mpixel_per_s": round(W * H / (fwd_ms * 1e-3) / 1e6, 3),
         "samples_filtered_per_s": round(occupied / (fwd_ms * 1e-3), 1),
         "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
+        "two_streams": two_streams,
         "plain_reconstruct_ms": round(plain_ms, 5),
         "gather_r1": gather_r1,
         "scatter_reconstruct_ms": scatter_ms,

@@ -325,11 +325,16 @@ def _stats_c(stats: torch.Tensor, tile: int) -> _TileStats:
 _ws_cache = {}
 
 
-def _workspace(nbytes: int, device, key: str) -> torch.Tensor:
-    k = (key, str(device))
+def _workspace(nbytes: int, device, key: str, stream=None) -> torch.Tensor:
+    """Scratch memory for one kind of call, kept per device and per stream: calls on different
+    streams may run at the same time and must not share a workspace. It is allocated on the stream
+    that uses it, so the allocator never hands it to other work while that stream still runs."""
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    k = (key, str(device), s.cuda_stream)
     t = _ws_cache.get(k)
     if t is None or t.numel() < nbytes:
-        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        with torch.cuda.stream(s):
+            t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         _ws_cache[k] = t
     return t
 
@@ -370,7 +375,7 @@ def build_deep_buffer(x, y, t, r, g, b, width: int, height: int, k: int, precisi
     s = _Samples(*(a.data_ptr() if n else None for a in xs), n,
                  *((a.data_ptr() if n else None) for a in vel))
     wsb = lib.afr_build_workspace_bytes(n, width, height, k)
-    ws = _workspace(wsb, dev, "build")
+    ws = _workspace(wsb, dev, "build", stream)
     bc = out._c()
     if stage_events is None:
         _check(lib.afr_build_deep_buffer(ctypes.byref(s), ctypes.byref(bc), _ptr(ws), wsb,
@@ -423,7 +428,7 @@ def rms_loss(img: torch.Tensor, ref: torch.Tensor, scale: float = 1.0, want_grad
     if grad is None and want_grad:
         grad = torch.empty_like(img)
     wsb = lib.afr_rms_workspace_bytes()
-    ws = _workspace(wsb, dev, "rms")
+    ws = _workspace(wsb, dev, "rms", stream)
     n = img.numel()
     _check(lib.afr_rms_loss(_ptr(img) if n else None, _ptr(ref) if n else None, n, float(scale),
                             _ptr(loss), _ptr(grad) if (grad is not None and n) else None, _ptr(ws),
@@ -442,7 +447,7 @@ def sampler_stats(buf: DeepBuffer, stats: torch.Tensor, params: Params, sp: Samp
     u = torch.empty((ty, tx), dtype=torch.float32, device=dev)
     g = torch.empty(8, dtype=torch.float64, device=dev)
     wsb = lib.afr_sampler_workspace_bytes(ty * tx)
-    ws = _workspace(wsb, dev, "sampler")
+    ws = _workspace(wsb, dev, "sampler", stream)
     bc, sc, pc = buf._c(), _stats_c(stats, params.tile), params._c()
     _check(lib.afr_sampler_stats(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
                                  ctypes.byref(sp._c()), _ptr(E), _ptr(u), _ptr(g), _ptr(ws), wsb,
@@ -464,7 +469,7 @@ def sampler_tile_weights(width: int, height: int, tile: int, E: torch.Tensor,
     if out is None:
         out = torch.empty_like(E)
     wsb = lib.afr_sampler_workspace_bytes(ty * tx)
-    ws = _workspace(wsb, E.device, "sampler")
+    ws = _workspace(wsb, E.device, "sampler", stream)
     _check(lib.afr_sampler_tile_weights(width, height, tile, _ptr(E), _ptr(globals_), int(n_parts),
                                         _ptr(out), _ptr(ws), wsb, _stream(stream)),
            "afr_sampler_tile_weights")
@@ -487,7 +492,7 @@ def sampler_select(width: int, height: int, tile: int, E: torch.Tensor, rnd: tor
     y = torch.empty(n, dtype=torch.float32, device=dev)
     t = torch.empty(n, dtype=torch.int32, device=dev) if want_tile else None
     wsb = lib.afr_sampler_workspace_bytes(ty * tx)
-    ws = _workspace(wsb, dev, "sampler")
+    ws = _workspace(wsb, dev, "sampler", stream)
     _check(lib.afr_sampler_select(width, height, tile, _ptr(E), n, _ptr(rnd) if n else None,
                                   _ptr(x) if n else None, _ptr(y) if n else None,
                                   _ptr(t) if (t is not None and n) else None, _ptr(ws), wsb,
@@ -569,7 +574,7 @@ def build_crosshair_buffer(samples, crosshairs, width: int, height: int, k: int,
     sc = _Samples(*(a.data_ptr() if n else None for a in xs), n)
     xc = _Crosshairs(*(a.data_ptr() if nx else None for a in ids), nx)
     wsb = lib.afr_crosshair_workspace_bytes(nx, width, height)
-    ws = _workspace(wsb, dev, "crosshair")
+    ws = _workspace(wsb, dev, "crosshair", stream)
     bc, pc = out._c(), params._c()
     _check(lib.afr_build_crosshair_buffer(ctypes.byref(sc), ctypes.byref(xc), ctypes.byref(pc),
                                           ctypes.byref(bc), _ptr(ws), wsb, _ptr(dropped),
@@ -717,7 +722,7 @@ def reconstruct_backward(buf: DeepBuffer, stats: torch.Tensor, params: Params, r
     if grad_params is None:
         grad_params = torch.empty(2, dtype=torch.float32, device=dev)
     wsb = lib.afr_backward_workspace_bytes(buf.width, buf.height, buf.k, params.radius)
-    ws = _workspace(wsb, dev, "backward")
+    ws = _workspace(wsb, dev, "backward", stream)
     bc, pc, sc = buf._c(colours), params._c(), _stats_c(stats, params.tile)
     grad_rgb = grad_rgb.contiguous().float()
     _check(lib.afr_reconstruct_backward(ctypes.byref(bc), ctypes.byref(sc), ctypes.byref(pc),
