@@ -9,9 +9,12 @@
 // For each slot plane k the wave first evaluates, for every source pixel of each tile's
 // (8+2R) x (8+2R) region, the 2R+1 values of X and of Y (three exponentials per axis with the
 // Gaussian recurrence X(m+1) = X(m) * rho * exp(-(2m+1)/(2 sx2)), rho = exp(-(ox - 1/2)/sx2)) and
-// P = Tm * (1, r, g, b), and stores them in LDS. Each lane then owns four output pixels of one tile
-// column and adds (X * Y) * P into four 4-channel accumulators: one multiply and four FMAs per
+// P = Tm * (1, r, g, b), and stores them in LDS. Each lane then owns ROWS output pixels of one tile
+// column and adds (X * Y) * P into 4-channel accumulators: one multiply and four FMAs per
 // (slot, pixel) pair, with every LDS index resolved at compile time.
+// With binary16 storage the temporal factor goes into Y instead (Y' = Y * Tm) and the colours stay in
+// LDS as the stored binary16 values, which the FMAs take as operands directly (mixed-precision FMA):
+// the same arithmetic count per pair from 16 instead of 24 bytes of LDS reads.
 //
 // Shift: a_ref is the smallest slot-0 age over the tile's source region (slot 0 is each pixel's
 // newest sample), so every Tm <= 1; the pixel's largest weight is at least exp(-(2R+1)^2 / (8 e_min^2))
@@ -24,6 +27,8 @@
 // result does not depend on launch shape. Workgroups are assigned so that each XCD's L2 holds a
 // contiguous band of the image (neighbouring workgroups share halo rows).
 #pragma once
+#include <type_traits>
+
 #include "afr_internal.h"
 
 namespace afr {
@@ -40,7 +45,9 @@ struct TiledParams {
     float t_now, dt_ref;
 };
 
-// LDS of one group evaluation. P: one float4 per source pixel of each tile's region (row pitch RW).
+// LDS of one group evaluation. P: one float4 per source pixel of each tile's region (row pitch RW);
+// with binary16 storage the same array holds each source pixel's three colours as they are stored
+// (one uint2: r | g << 16, b), at the same positions in uint2 units.
 // XY: per tile and offset m, the region's X values in columns [0, RW) and its Y values in columns
 // [RW, 2 RW) of rows with pitch XP. XP is 8 times an odd number, so an 8 x 8 block of lanes reading
 // (row + h, col + c) hits 64 distinct banks (and each half-wave 32), and tiles are XYS apart with
@@ -145,6 +152,7 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     constexpr int NM = 2 * R + 1;           // offsets per axis
     constexpr int ITEMS = (NP + LPT - 1) / LPT;
     constexpr int XP = XYLayout<R>::XP, XYM = XYLayout<R>::XYM;
+    constexpr bool kMix = std::is_same<S, __half>::value;  // colours kept as binary16 in LDS
     float4 *sP = sm.P;
 
     const int W = v.width, H = v.height;
@@ -226,6 +234,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
 
     float4 *tP = sP + my_t * PS;
     float2 *tPP = reinterpret_cast<float2 *>(sP);  // split layout (one tile per wave)
+    // binary16 colours: row pitch XP (one tile per wave) or the tile's plane of PS entries
+    uint2 *tC = reinterpret_cast<uint2 *>(sP) + (TPW == 1 ? 0 : my_t * PS);
     float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col) at row * XP + col
     float *tY = tX + RW;                          // Y at row * XP + RW + col
     for (int k = 0; k < kmax; ++k) {
@@ -240,10 +250,6 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 const float dy = on ? Codec<S>::dec(roy[it]) - 0.5f : 0.0f;
                 const float a = on ? Codec<S>::age(rta[it], p.t_now, p.dt_ref) : amin;
                 const float tm = fast_exp2(-((a - amin) * (a + amin)) * ct2);
-                const float4 P =
-                    on ? make_float4(tm, tm * Codec<S>::dec(rr[it]), tm * Codec<S>::dec(rg[it]),
-                                     tm * Codec<S>::dec(rb[it]))
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
                 // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
                 float X[NM], Y[NM];
                 const float ex = dx - (float)R, ey = dy - (float)R;
@@ -258,11 +264,27 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                     }
                 }
                 const int xy = (pix / RW) * XP + pix % RW;
-                if constexpr (TPW == 1) {
-                    tPP[xy] = make_float2(P.x, P.y);
-                    tPP[xy + RW] = make_float2(P.z, P.w);
+                if constexpr (kMix) {
+                    // Y' = Y * Tm (0 for an empty slot, whose colours are written as 0)
+                    const float tmv = on ? tm : 0.0f;
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) Y[m] *= tmv;
+                    const unsigned c0 = on ? ((unsigned)__half_as_ushort(rr[it]) |
+                                              ((unsigned)__half_as_ushort(rg[it]) << 16))
+                                           : 0u;
+                    const unsigned c1 = on ? (unsigned)__half_as_ushort(rb[it]) : 0u;
+                    tC[TPW == 1 ? xy : pix] = make_uint2(c0, c1);
                 } else {
-                    tP[pix] = P;
+                    const float4 P =
+                        on ? make_float4(tm, tm * Codec<S>::dec(rr[it]),
+                                         tm * Codec<S>::dec(rg[it]), tm * Codec<S>::dec(rb[it]))
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                    if constexpr (TPW == 1) {
+                        tPP[xy] = make_float2(P.x, P.y);
+                        tPP[xy + RW] = make_float2(P.z, P.w);
+                    } else {
+                        tP[pix] = P;
+                    }
                 }
 #pragma unroll
                 for (int m = 0; m < NM; ++m) {
@@ -289,23 +311,41 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
             for (int w = 0; w < NM; ++w) {
                 const int pix = (my_h * ROWS + vv) * RW + my_c + w;
                 const int xy = (my_h * ROWS + vv) * XP + my_c + w;
-                float4 P;
-                if constexpr (TPW == 1) {
-                    const float2 a = tPP[xy], b = tPP[xy + RW];
-                    P = make_float4(a.x, a.y, b.x, b.y);
-                } else {
-                    P = tP[pix];
-                }
                 const float x = tX[w * XYM + xy];
+                if constexpr (kMix) {
+                    const uint2 cw = tC[TPW == 1 ? xy : pix];
+                    const __half2 rg2 = __halves2half2(__ushort_as_half((unsigned short)cw.x),
+                                                       __ushort_as_half((unsigned short)(cw.x >> 16)));
+                    const __half bh = __ushort_as_half((unsigned short)cw.y);
 #pragma unroll
-                for (int u = 0; u < ROWS; ++u) {
-                    const int nn = vv - u;  // n + R
-                    if (nn >= 0 && nn <= 2 * R) {
-                        const float wgt = x * tY[nn * XYM + xy];
-                        part[u][0] += wgt * P.x;
-                        part[u][1] += wgt * P.y;
-                        part[u][2] += wgt * P.z;
-                        part[u][3] += wgt * P.w;
+                    for (int u = 0; u < ROWS; ++u) {
+                        const int nn = vv - u;  // n + R
+                        if (nn >= 0 && nn <= 2 * R) {
+                            const float wgt = x * tY[nn * XYM + xy];  // X * Y * Tm
+                            part[u][0] += wgt;
+                            part[u][1] = fmaf(wgt, __low2float(rg2), part[u][1]);
+                            part[u][2] = fmaf(wgt, __high2float(rg2), part[u][2]);
+                            part[u][3] = fmaf(wgt, __half2float(bh), part[u][3]);
+                        }
+                    }
+                } else {
+                    float4 P;
+                    if constexpr (TPW == 1) {
+                        const float2 a = tPP[xy], b = tPP[xy + RW];
+                        P = make_float4(a.x, a.y, b.x, b.y);
+                    } else {
+                        P = tP[pix];
+                    }
+#pragma unroll
+                    for (int u = 0; u < ROWS; ++u) {
+                        const int nn = vv - u;  // n + R
+                        if (nn >= 0 && nn <= 2 * R) {
+                            const float wgt = x * tY[nn * XYM + xy];
+                            part[u][0] += wgt * P.x;
+                            part[u][1] += wgt * P.y;
+                            part[u][2] += wgt * P.z;
+                            part[u][3] += wgt * P.w;
+                        }
                     }
                 }
             }
