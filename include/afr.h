@@ -163,6 +163,9 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
  * Gradient, density and filter-extent estimation per tile (Sec. 4, 4.1, 5.1).
  *
  * Per pixel: luminance L (Rec. 709 weights), age weight w = exp(-alpha a), age-weighted mean Lbar.
+ * Age weights are evaluated over the FP64 exponent range (relative precision about 2e-7 down to
+ * w = 2^-1022, ages of about 200 s at the default alpha); a pixel whose samples are all older than
+ * that has no weight and its mean, like the FP64 definition's, is undefined (NaN).
  * Spatial gradient: mean |Lbar_p - Lbar_q| over the filled 4-neighbours in x (resp. y). Temporal
  * gradient: slots split by rank into a newer and an older half, |L_new - L_old| divided by
  * max(a_old - a_new, dt_floor). Per tile: age-weighted means of the three gradients over the pixels

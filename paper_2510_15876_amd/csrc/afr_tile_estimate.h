@@ -122,6 +122,19 @@ struct PixAcc {
 
 __device__ inline PixAcc pix_zero() { return PixAcc{0, 0, 0, 0, 0, 0, 0, 0}; }
 
+// Age weight e^{-alpha a} (Sec. 4) over the FP64 exponent range: with x = alpha a log2(e) = n + f,
+// n an integer and f in [0, 1), the weight is 2^-f (float32, within 2 ulp) scaled exactly by 2^-n.
+// A float32 exponential of -alpha a would reach zero past about 30 s of age at alpha = 3.47 / s
+// (leaving a pixel whose samples are all that old with no weight); this form holds the weight's
+// relative precision down to 2^-1022 (ages of about 200 s).
+__device__ inline double age_weight(double alpha, double a) {
+#pragma clang fp contract(off)
+    const double x = alpha * a * 1.4426950408889634;
+    const double n = floor(x);
+    const int e = (int)fmin(fmax(n, -2000.0), 2000.0);
+    return ldexp((double)exp2f((float)(n - x)), -e);
+}
+
 // Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta.
 template <typename S>
 __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S ta, int k, int n) {
@@ -129,7 +142,7 @@ __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S t
     const double L = kLumR * (double)Codec<S>::dec(r) + kLumG * (double)Codec<S>::dec(g) +
                      kLumB * (double)Codec<S>::dec(b);
     const double a = Codec<S>::age64(ta, p.t_now, p.dt_ref);
-    const double w = (double)expf((float)(-p.alpha * a));
+    const double w = age_weight(p.alpha, a);
     m.s0 += w;
     m.s1 += w * L;
     m.s2 += w * L * L;

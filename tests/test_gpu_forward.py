@@ -5,9 +5,10 @@ Tolerances:
     colours (the target for plain FP32 output); the same bound holds end to end, statistics
     included, and for the FP16-storage buffer against the reference on the same FP16 buffer;
   * FP16 storage against the reference on the FP32 buffer: <= 2e-3 (storage quantisation);
-  * tile statistics: the estimator accumulates in FP64 but takes age weights from a float32
-    exponential (<= 2 ulp, 2.4e-7 relative) and stores float32, so gradients and means get
-    rtol 2e-6 with an absolute floor of 1e-7 / px (luminance in [0, 1]).
+  * tile statistics: the estimator accumulates in FP64; an age weight is 2^-n (exact) times a
+    float32 power of two of the fractional part (<= 2 ulp, 2.4e-7 relative), and the statistics
+    are stored as float32, so gradients and means get rtol 2e-6 with an absolute floor of
+    1e-7 / px (luminance in [0, 1]).
 """
 import numpy as np
 import pytest
@@ -114,6 +115,33 @@ def test_edge_geometries(form, w, h, k, radius, tile):
         assert np.abs(rgb.cpu().numpy() - orgb).max() <= 1e-5
         ga = aux.cpu().numpy()
         assert np.array_equal(ga[1] > 0, oaux[1] > 0)  # coverage agrees exactly
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_old_samples(precision):
+    """Samples up to 80 s old (stored ages up to 60 s, 20 s from the stream's reference time to the
+    reconstruction time): e^{-alpha a} drops below the float32 range past about 30 s, so the age
+    weights must be evaluated over the FP64 range for the statistics to match the reference."""
+    afr = afr_mod()
+    w, h, k = 40, 24, 6
+    rng = np.random.default_rng(80)
+    scene = S.DiscScene(w, h, rng, 6, 60000.0, speed=1e-4, radius=(3.0, 8.0))
+    s = S.uniform_stream(scene, w, h, w * h * 5, 60000.0, 60000.0, rng)
+    print(f"old samples {precision}", flush=True)
+    gbuf, _ = gpu_build(s, w, h, k, precision, 60000.0)
+    obuf, _ = O.build_buffer(s, w, h, k, precision, 60000.0)
+    gp, op = params(80000.0)
+    gst = afr.estimate_gradients(gbuf, gp)
+    ost = O.estimate(obuf, op)
+    g64 = gst.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(g64))
+    for i, n in enumerate(O.STAT_NAMES):
+        rtol, atol = _stat_tol(n)
+        np.testing.assert_allclose(g64[i], ost[i], rtol=rtol, atol=atol, err_msg=f"stat {n}")
+    for form in FORMS:
+        rgb, _ = reconstruct(form, gbuf, gst, gp)
+        orgb, _, _ = O.forward(obuf, op)
+        assert np.abs(rgb.cpu().numpy() - orgb).max() <= 1e-5
 
 
 def test_reference_statistics_round_trip_and_constants():
