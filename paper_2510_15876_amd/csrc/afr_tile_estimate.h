@@ -7,8 +7,9 @@
 // old-half means that give the temporal difference quotient, and the age sum. Results go to LDS.
 // Phase 2 gives each tile pixel its spatial gradients from the LDS neighbours and folds all
 // per-pixel terms of a tile into one accumulator per lane (pixel e on lane e mod 64); lanes are
-// combined by a fixed-shape butterfly within the wave and in wave order across waves. Luminance
-// variance merges per-pixel (weight, mean, M2) triples with the pairwise form of Welford's update.
+// combined by a fixed-shape butterfly within the wave and in wave order across waves. The luminance
+// mean and variance come from FP64 sums of omega, omega L and omega L^2 (in [0, 1] luminance the
+// cancellation in s2 / w - (s1 / w)^2 costs at most ~1e-16 absolute, far below the float32 output).
 //
 // Two drivers share these routines: a strip kernel (afr_estimate_gradients, tiles of edge <= 8)
 // where a workgroup covers a 32-pixel-wide strip of tiles, so that each wave reads whole image rows
@@ -35,7 +36,7 @@ constexpr double kLumR = 0.2126, kLumG = 0.7152, kLumB = 0.0722;
 struct Acc {
     double gx, wx, gy, wy, gt, wt;  // sums of Omega_p G(p) and Omega_p over defined pixels
     double n, sa;                   // slot count and age sum
-    double w, mean, m2;             // age-weighted luminance: weight, mean, sum of squared deviations
+    double w, s1, s2;               // age-weighted luminance: sums of omega, omega L, omega L^2
 };
 
 __device__ inline Acc acc_zero() { return Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; }
@@ -51,20 +52,9 @@ __device__ inline Acc acc_combine(const Acc &a, const Acc &b) {
     c.wt = a.wt + b.wt;
     c.n = a.n + b.n;
     c.sa = a.sa + b.sa;
-    if (b.w == 0.0) {
-        c.w = a.w;
-        c.mean = a.mean;
-        c.m2 = a.m2;
-    } else if (a.w == 0.0) {
-        c.w = b.w;
-        c.mean = b.mean;
-        c.m2 = b.m2;
-    } else {
-        c.w = a.w + b.w;
-        const double d = b.mean - a.mean;
-        c.mean = a.mean + d * (b.w / c.w);
-        c.m2 = a.m2 + b.m2 + d * d * (a.w * b.w / c.w);
-    }
+    c.w = a.w + b.w;
+    c.s1 = a.s1 + b.s1;
+    c.s2 = a.s2 + b.s2;
     return c;
 }
 
@@ -81,8 +71,8 @@ __device__ inline Acc acc_shfl_xor(const Acc &a, int m) {
     o.n = shfl_xor_d(a.n, m);
     o.sa = shfl_xor_d(a.sa, m);
     o.w = shfl_xor_d(a.w, m);
-    o.mean = shfl_xor_d(a.mean, m);
-    o.m2 = shfl_xor_d(a.m2, m);
+    o.s1 = shfl_xor_d(a.s1, m);
+    o.s2 = shfl_xor_d(a.s2, m);
     return o;
 }
 
@@ -156,20 +146,19 @@ __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S t
     }
 }
 
-// Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum, M2)
-// in LDS, row-major with a given pitch.
+// Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum,
+// sum omega L^2) in LDS, row-major with a given pitch.
 struct Region {
-    double *lbar, *om, *gt, *sa, *m2;
+    double *lbar, *om, *gt, *sa, *s2;
     int *n;
 };
 
 __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n, double dt_floor) {
 #pragma clang fp contract(off)
-    double om = 0.0, lb = 0.0, gt = -1.0, m2 = 0.0;
+    double om = 0.0, lb = 0.0, gt = -1.0;
     if (n > 0) {
         om = m.s0;
         lb = m.s1 / m.s0;
-        m2 = fmax(m.s2 - m.s1 * lb, 0.0);
     }
     if (n >= 2) {
         const int half = (n + 1) / 2;
@@ -181,7 +170,7 @@ __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n
     rg.lbar[h] = lb;
     rg.gt[h] = gt;
     rg.sa[h] = m.sa;
-    rg.m2[h] = m2;
+    rg.s2[h] = m.s2;
 }
 
 // ---- per-tile reduction (phase 2) ---------------------------------------------------------------
@@ -205,8 +194,8 @@ __device__ inline Acc pixel_acc(const Region &rg, int h, int rp) {
     a.n = n;
     a.sa = rg.sa[h];
     a.w = om;
-    a.mean = lb;
-    a.m2 = rg.m2[h];
+    a.s1 = om * lb;
+    a.s2 = rg.s2[h];
     return a;
 }
 
@@ -224,20 +213,45 @@ __device__ inline Acc wave_tile_acc(const Region &rg, int h0, int rp, int bw, in
     return acc;
 }
 
-// Tile statistics from the tile's accumulator; writes the stats planes and, if tparams is not NULL,
-// (sx2, sy2, kt2) to tparams.
+// Tile statistics from the tile's accumulator, evaluated by all lanes of one wave holding the same
+// accumulator: lanes 0, 1 and 2 take the three cube roots of the extents at once (the same operations
+// as extents()), and lane 0 writes the stats planes and, if tparams is not NULL, (sx2, sy2, kt2) to
+// tparams.
 __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileGeom &tg, int T,
-                                   int bw, int bh, float *stats, float *tparams) {
+                                   int bw, int bh, float *stats, float *tparams, int lane) {
 #pragma clang fp contract(off)
     const double gx = t.wx > 0.0 ? t.gx / t.wx : 0.0;
     const double gy = t.wy > 0.0 ? t.gy / t.wy : 0.0;
     const double gt = t.wt > 0.0 ? t.gt / t.wt : 0.0;
     const double area = (double)bw * bh;
     const double vol = t.n > 0.0 ? area * 2.0 * fmax(t.sa / t.n, p.age_floor) / t.n : INFINITY;
-    const double var = t.w > 0.0 ? t.m2 / t.w : 0.0;
-    const double lmean = t.w > 0.0 ? t.mean : 0.0;
-    double ex2, ey2, sx2, sy2, kt2;
-    extents(gx, gy, gt, vol, p, ex2, ey2, sx2, sy2, kt2);
+    const double lmean = t.w > 0.0 ? t.s1 / t.w : 0.0;
+    const double var = t.w > 0.0 ? fmax(t.s2 / t.w - lmean * lmean, 0.0) : 0.0;
+    const double hx = sqrt(gx * gx + p.g_floor * p.g_floor);
+    const double hy = sqrt(gy * gy + p.g_floor * p.g_floor);
+    const double u = p.tau * gt;
+    double ex2 = 0.0, ey2 = 0.0, kt2 = 0.0;
+    if (u != 0.0) {  // uniform over the wave
+        const double num = lane == 0 ? vol * hy * u : (lane == 1 ? vol * hx * u : u * u);
+        const double den = lane == 0 ? hx * hx : (lane == 1 ? hy * hy : vol * hx * hy);
+        const double c = cbrt(num / den);
+        const double cx = __shfl(c, 0, kWave), cy = __shfl(c, 1, kWave), ck = __shfl(c, 2, kWave);
+        ex2 = cx * cx;
+        ey2 = cy * cy;
+        kt2 = ck * ck;
+    }
+    const double zx = p.sigma * p.sigma * ex2, zy = p.sigma * p.sigma * ey2;
+    const double n2 = p.e_min * p.e_min;
+    double sx2, sy2;
+    if (isinf(p.e_max)) {
+        sx2 = n2 + zx;
+        sy2 = n2 + zy;
+    } else {
+        const double m2 = p.e_max * p.e_max;
+        sx2 = n2 + zx * m2 / (m2 + zx);
+        sy2 = n2 + zy * m2 / (m2 + zy);
+    }
+    if (lane != 0) return;
     const int nt = tg.nt;
     stats[AFR_STAT_GX * nt + T] = (float)gx;
     stats[AFR_STAT_GY * nt + T] = (float)gy;
@@ -318,7 +332,7 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
 template <int TB>
 struct Smem {
     static constexpr int kHalo = (TB + 2) * (TB + 2);
-    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
+    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], s2[kHalo];
     int n[kHalo];
     Acc wave[256 / kWave];
 };
@@ -330,7 +344,7 @@ struct Smem {
 template <typename S, int TB>
 __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int T,
                               float *stats, Smem<TB> &sm, float *tparams) {
-    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.s2, sm.n};
     const int B = tg.tile;
     const int i0 = (T % tg.tiles_x) * B, j0 = (T / tg.tiles_x) * B;
     const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
@@ -341,10 +355,10 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
     const Acc acc = wave_tile_acc(rg, rw + 1, rw, bw, bh, threadIdx.x, blockDim.x);
     if (lane == 0) sm.wave[wid] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {  // the first wave, every lane with the same sum
         Acc t = sm.wave[0];
         for (int w = 1; w < (int)(blockDim.x / kWave); ++w) t = acc_combine(t, sm.wave[w]);
-        tile_finish(t, p, tg, T, bw, bh, stats, tparams);
+        tile_finish(t, p, tg, T, bw, bh, stats, tparams, lane);
     }
     __syncthreads();  // the LDS scratch may be reused by the caller after this point
 }
@@ -358,7 +372,7 @@ constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
 
 struct StripSmem {
     double lbar[kStripRegion], om[kStripRegion], gt[kStripRegion], sa[kStripRegion],
-        m2[kStripRegion];
+        s2[kStripRegion];
     int n[kStripRegion];
 };
 
@@ -370,7 +384,7 @@ __host__ __device__ inline int strip_tiles(int B) { return kStripW / B; }
 template <typename S>
 __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int tx0,
                                int ty, float *stats, StripSmem &sm) {
-    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.s2, sm.n};
     const int B = tg.tile;
     const int ntile = min(strip_tiles(B), tg.tiles_x - tx0);
     const int i0 = tx0 * B, j0 = ty * B;
@@ -382,7 +396,7 @@ __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const Ti
     for (int t = wid; t < ntile; t += kStripThreads / kWave) {
         const int bw = min(B, v.width - (i0 + t * B)), bh = sh;
         const Acc acc = wave_tile_acc(rg, rp + 1 + t * B, rp, bw, bh, lane, kWave);
-        if (lane == 0) tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats, nullptr);
+        tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats, nullptr, lane);
     }
 }
 
