@@ -144,6 +144,28 @@ def test_old_samples(precision):
         assert np.abs(rgb.cpu().numpy() - orgb).max() <= 1e-5
 
 
+@pytest.mark.parametrize("w,h,radius", [(37, 23, 2), (72, 40, 2), (45, 17, 1), (24, 9, 0), (33, 30, 3)])
+def test_launch_shapes_give_identical_output(w, h, radius):
+    """One, two or four tiles per wave sum the same terms in the same order: colours and aux agree
+    bit for bit, including tile columns that do not fill a group."""
+    torch = torch_mod()
+    afr = afr_mod()
+    rng = np.random.default_rng(w * 7 + h)
+    scene = S.DiscScene(w, h, rng, 5, 40.0, speed=0.2, radius=(2.0, 7.0))
+    s = S.uniform_stream(scene, w, h, w * h * 6, 40.0, 40.0, rng)
+    print(f"launch shapes {w}x{h} R={radius}", flush=True)
+    for precision in ("fp32", "fp16"):
+        gbuf, _ = gpu_build(s, w, h, 8, precision, 40.0)
+        gp, op = params(41.0, radius=radius)
+        st = afr.estimate_gradients(gbuf, gp)
+        outs = [afr.reconstruct_launch(gbuf, st, gp, tpw) for tpw in (1, 2, 4)]
+        for rgb, aux in outs[1:]:
+            assert torch.equal(rgb, outs[0][0]) and torch.equal(aux, outs[0][1])
+        obuf, _ = O.build_buffer(s, w, h, 8, precision, 40.0)
+        orgb, _, _ = O.forward(obuf, op)
+        assert np.abs(outs[0][0].cpu().numpy() - orgb).max() <= 1e-5
+
+
 def test_reference_statistics_round_trip_and_constants():
     """A constant-colour buffer reproduces the constant through the GPU gather (north-star
     invariant), and the tiled and plain forms agree to float32 rounding.
