@@ -12,9 +12,11 @@
 // P = Tm * (1, r, g, b), and stores them in LDS. Each lane then owns ROWS output pixels of one tile
 // column and adds (X * Y) * P into 4-channel accumulators: one multiply and four FMAs per
 // (slot, pixel) pair, with every LDS index resolved at compile time.
-// With binary16 storage the temporal factor goes into Y instead (Y' = Y * Tm) and the colours stay in
-// LDS as the stored binary16 values, which the FMAs take as operands directly (mixed-precision FMA):
-// the same arithmetic count per pair from 16 instead of 24 bytes of LDS reads.
+// With binary16 storage the temporal factor goes into Y instead (Y' = Y * Tm, its exponent added to
+// that of Y(-R) before the recurrence) and the colours stay in LDS as the stored binary16 values, which
+// the FMAs take as operands directly (mixed-precision FMA): the same arithmetic count per pair from 16
+// instead of 24 bytes of LDS reads. Y'(-R) >= 2^-18 Y'(0) at R = 2 and the widths' floor, so a
+// subnormal Y'(-R) only carries weights below 2^-108, negligible next to the 1e-30 weight-sum floor.
 //
 // Shift: a_ref is the smallest slot-0 age over the tile's source region (slot 0 is each pixel's
 // newest sample), so every Tm <= 1; the pixel's largest weight is at least exp(-(2R+1)^2 / (8 e_min^2))
@@ -249,12 +251,14 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 const float dx = on ? Codec<S>::dec(rox[it]) - 0.5f : 0.0f;
                 const float dy = on ? Codec<S>::dec(roy[it]) - 0.5f : 0.0f;
                 const float a = on ? Codec<S>::age(rta[it], p.t_now, p.dt_ref) : amin;
-                const float tm = fast_exp2(-((a - amin) * (a + amin)) * ct2);
+                const float lt = -((a - amin) * (a + amin)) * ct2;  // log2 Tm
                 // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
                 float X[NM], Y[NM];
                 const float ex = dx - (float)R, ey = dy - (float)R;
                 X[0] = fast_exp2(-ex * ex * cx2);
-                Y[0] = fast_exp2(-ey * ey * cy2);
+                // binary16 storage: Y'(m) = Y(m) Tm from one exponential, 0 for an empty slot
+                Y[0] = kMix ? fast_exp2(on ? -ey * ey * cy2 + lt : -INFINITY)
+                            : fast_exp2(-ey * ey * cy2);
                 if (R > 0) {
                     const float rhox = fast_exp2(-2.0f * dx * cx2), rhoy = fast_exp2(-2.0f * dy * cy2);
 #pragma unroll
@@ -265,16 +269,14 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 }
                 const int xy = (pix / RW) * XP + pix % RW;
                 if constexpr (kMix) {
-                    // Y' = Y * Tm (0 for an empty slot, whose colours are written as 0)
-                    const float tmv = on ? tm : 0.0f;
-#pragma unroll
-                    for (int m = 0; m < NM; ++m) Y[m] *= tmv;
+                    // an empty slot's colours are written as 0 (its Y' is 0)
                     const unsigned c0 = on ? ((unsigned)__half_as_ushort(rr[it]) |
                                               ((unsigned)__half_as_ushort(rg[it]) << 16))
                                            : 0u;
                     const unsigned c1 = on ? (unsigned)__half_as_ushort(rb[it]) : 0u;
                     tC[TPW == 1 ? xy : pix] = make_uint2(c0, c1);
                 } else {
+                    const float tm = fast_exp2(lt);
                     const float4 P =
                         on ? make_float4(tm, tm * Codec<S>::dec(rr[it]),
                                          tm * Codec<S>::dec(rg[it]), tm * Codec<S>::dec(rb[it]))
