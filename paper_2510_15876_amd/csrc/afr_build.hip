@@ -37,7 +37,8 @@ constexpr int kChunkThreads = 512;  // two 512-thread scatter workgroups share a
 constexpr int kChunkPer = 8;        // while the other sorts and stores
 constexpr int kChunk = kChunkThreads * kChunkPer;  // samples per chunk
 constexpr int kWin = 2048;  // records staged in LDS per scatter window (64 KiB: two workgroups per CU)
-constexpr int kBinW = 64;                          // bin width, px
+constexpr int kBinW = 64;                          // bin width, px (a power of two)
+static_assert((kBinW & (kBinW - 1)) == 0, "bin width is a power of two");
 constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
 constexpr int kMaxBinPx = 2048;                    // pixels per bin (rows grow from 4 to 32)
 constexpr int kSelThreads = 256;
@@ -50,8 +51,9 @@ struct ValidCtx {
     int32_t fp16;
 };
 
+// Bins of bw x bh pixels, bw = kBinW and bh a power of two (bh = 1 << sbh).
 struct BinGeom {
-    int32_t bw, bh, nbx, nby, nb;
+    int32_t bw, bh, sbh, nbx, nby, nb;
 };
 
 // Validity: the position decides the home pixel (checked when binning); time, colour and the
@@ -98,8 +100,9 @@ __device__ inline void advect(float &x, float &y, float t, float vx, float vy, f
     y = __fadd_rn(y, __fmul_rn(vy, d));
 }
 
+// Bin of a position inside the image (x, y >= 0): shifts, since both bin edges are powers of two.
 __device__ inline int bin_of(float x, float y, const BinGeom &g) {
-    return ((int)floorf(y) / g.bh) * g.nbx + (int)floorf(x) / g.bw;
+    return (int)((unsigned)floorf(y) >> g.sbh) * g.nbx + (int)((unsigned)floorf(x) / kBinW);
 }
 
 // Order key of a sample: the float time mapped to an unsigned integer with the same order (-0 is
@@ -552,12 +555,12 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
     const int nrec = s1 - s0;
     const BinRecs recs{bucket.a + s0, bucket.b + s0, bucket.h + s0};
-    const int bx0 = (b % g.nbx) * g.bw, by0 = (b / g.nbx) * g.bh;
+    const int bx0 = (b % g.nbx) * kBinW, by0 = (b / g.nbx) * g.bh;
     const int W = out.width, H = out.height;
     const size_t hw = (size_t)W * H;
     const int rows = min(g.bh, H - by0);
     auto local_id = [&](float x, float y) {
-        return ((int)floorf(y) - by0) * g.bw + ((int)floorf(x) - bx0);
+        return ((int)floorf(y) - by0) * kBinW + ((int)floorf(x) - bx0);
     };
     for (int q = threadIdx.x; q <= npx; q += kSelThreads) poff[q] = 0;
     __syncthreads();
@@ -592,8 +595,8 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < rows * g.bw; q += kSelThreads) {
-            const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+        for (int q = threadIdx.x; q < rows * kBinW; q += kSelThreads) {
+            const int px = bx0 + q % kBinW, py = by0 + q / kBinW;
             if (px < W)
                 select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, oxy, poff[q],
                                       poff[q + 1]);
@@ -614,8 +617,8 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
     __syncthreads();
     for (int r0 = 0; r0 < rows;) {
         int r1 = r0 + 1;
-        while (r1 < rows && poff[(r1 + 1) * g.bw] - poff[r0 * g.bw] <= kListCap) ++r1;
-        const int q0 = r0 * g.bw, q1 = r1 * g.bw;
+        while (r1 < rows && poff[(r1 + 1) * kBinW] - poff[r0 * kBinW] <= kListCap) ++r1;
+        const int q0 = r0 * kBinW, q1 = r1 * kBinW;
         const int lo = poff[q0], hi = poff[q1];
         __syncthreads();  // every thread has read the bounds before the fill moves them
         if (hi - lo <= kListCap && nrec <= 65536) {
@@ -631,14 +634,14 @@ __global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out,
             }
             __syncthreads();
             for (int q = q0 + threadIdx.x; q < q1; q += kSelThreads) {
-                const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+                const int px = bx0 + q % kBinW, py = by0 + q / kBinW;
                 if (px < W)
                     select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, oxy,
                                           q == q0 ? 0 : poff[q - 1] - lo, poff[q] - lo);
             }
         } else {
             for (int q = q0 + threadIdx.x; q < q1; q += kSelThreads) {
-                const int px = bx0 + q % g.bw, py = by0 + q / g.bw;
+                const int px = bx0 + q % kBinW, py = by0 + q / kBinW;
                 if (px < W) select_pixel_scan<S>(out, (size_t)py * W + px, hw, recs, nrec, px, py);
             }
         }
@@ -679,8 +682,11 @@ BinGeom bin_geom(int32_t w, int32_t h) {
     g.bw = kBinW;
     g.nbx = (w + g.bw - 1) / g.bw;
     g.bh = 4;
-    while ((size_t)g.nbx * ((h + g.bh - 1) / g.bh) > (size_t)kMaxBins && g.bw * g.bh < kMaxBinPx)
+    g.sbh = 2;
+    while ((size_t)g.nbx * ((h + g.bh - 1) / g.bh) > (size_t)kMaxBins && g.bw * g.bh < kMaxBinPx) {
         g.bh *= 2;
+        ++g.sbh;
+    }
     g.nby = (h + g.bh - 1) / g.bh;
     g.nb = g.nbx * g.nby;
     return g;
