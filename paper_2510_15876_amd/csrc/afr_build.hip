@@ -417,9 +417,10 @@ __device__ inline void store_slot(const afr_deep_buffer &out, size_t o, const Bi
 constexpr int kListSlots = kListCap + kListCap / 16;
 __device__ inline int swz(int l) { return l + (l >> 4); }
 
-// Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: insertion into a
-// descending register list (one unsigned compare and selects per entry, the same instruction stream
-// in every lane). Larger K: repeated maximum scans. The selected records are then loaded together.
+// Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: a pixel with at
+// most KMAX entries sorts them in registers with a bitonic network; one with more inserts each into
+// a descending register list (one unsigned compare and selects per entry and position). Larger K:
+// repeated maximum scans. The selected records are then loaded together.
 template <typename S, int KMAX>
 __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t hw,
                                     const BinRecs &recs, const unsigned long long *keys,
@@ -434,19 +435,52 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
             top[k] = 0ull;
             tp[k] = 0;
         }
-        for (int l = l0; l < l1; ++l) {
-            unsigned long long c = keys[swz(l)];
-            int ce = l;  // list index of the candidate
-            nvalid += c != 0ull;
+        if (l1 - l0 <= KMAX) {
+            // All candidates fit the register list: load them (0 pads) and sort descending with a
+            // bitonic network, KMAX/2 log2(KMAX) (log2(KMAX) + 1) / 2 compare-exchanges instead of
+            // KMAX per candidate. Valid keys are distinct (they hold the stream index), so the
+            // order is the same as the insertion's.
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                const unsigned long long a = top[k];
-                const int ae = tp[k];
-                const bool gt = c > a;
-                top[k] = gt ? c : a;
-                tp[k] = gt ? ce : ae;
-                c = gt ? a : c;
-                ce = gt ? ae : ce;
+                const int l = l0 + k;
+                top[k] = l < l1 ? keys[swz(l)] : 0ull;
+                tp[k] = l;
+                nvalid += top[k] != 0ull;
+            }
+#pragma unroll
+            for (int size = 2; size <= KMAX; size <<= 1)
+#pragma unroll
+                for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                    for (int i = 0; i < KMAX; ++i) {
+                        const int j = i ^ stride;
+                        if (j > i) {
+                            // descending blocks where bit `size` of i is clear, ascending otherwise,
+                            // so that the last merge leaves the whole list descending
+                            const unsigned long long a = top[i], b = top[j];
+                            const bool sw = (i & size) == 0 ? a < b : a > b;
+                            const int ea = tp[i], eb = tp[j];
+                            top[i] = sw ? b : a;
+                            top[j] = sw ? a : b;
+                            tp[i] = sw ? eb : ea;
+                            tp[j] = sw ? ea : eb;
+                        }
+                    }
+        } else {
+            for (int l = l0; l < l1; ++l) {
+                unsigned long long c = keys[swz(l)];
+                int ce = l;  // list index of the candidate
+                nvalid += c != 0ull;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    const unsigned long long a = top[k];
+                    const int ae = tp[k];
+                    const bool gt = c > a;
+                    top[k] = gt ? c : a;
+                    tp[k] = gt ? ce : ae;
+                    c = gt ? a : c;
+                    ce = gt ? ae : ce;
+                }
             }
         }
         const int n = min(nvalid, K);
