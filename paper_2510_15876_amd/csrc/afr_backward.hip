@@ -383,16 +383,22 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     BufView<S> v, BwdParams p, TileGeom tg, const float *__restrict__ stats, TiledWs ws) {
     using G = RegionGeom<R>;
     constexpr int RW = G::RW, NP = G::NP, NM = G::NM, NW = G::ITEMS;
-    __shared__ float4 s_gk[kTB * kTB];
+    // (g', k') of the tile's pixels on a grid padded by 2R zeros on every side (tile-local rows and
+    // columns -2R .. 8 + 2R - 1): a slot reads its 2R+1 x 2R+1 pixels at fixed offsets, and pixels
+    // outside the tile (or the image) contribute nothing without a test
+    constexpr int GP = kTB + 4 * R;
+    __shared__ float4 s_gk[GP * GP];
     __shared__ double s_red[2][NW];
     const int T = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = T % tg.tiles_x, ty = T / tg.tiles_x;
     const int W = v.width, H = v.height, K = v.k;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const size_t hw = (size_t)W * H;
-    if (tid < kTB * kTB) {
-        const int i = tx * kTB + tid % kTB, j = ty * kTB + tid / kTB;
-        s_gk[tid] = (i < W && j < H) ? ws.gk[(size_t)j * W + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int e = tid; e < GP * GP; e += NW * kWave) {
+        const int li = e % GP - 2 * R, lj = e / GP - 2 * R;
+        const int i = tx * kTB + li, j = ty * kTB + lj;
+        const bool inside = li >= 0 && li < kTB && lj >= 0 && lj < kTB && i < W && j < H;
+        s_gk[e] = inside ? ws.gk[(size_t)j * W + i] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     const float sx2 = stats[AFR_STAT_SX2 * tg.nt + T], sy2 = stats[AFR_STAT_SY2 * tg.nt + T];
     const float kt2 = stats[AFR_STAT_KT2 * tg.nt + T];
@@ -404,6 +410,9 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     for (int m = 0; m < 2 * R; ++m) gxm[m] = __builtin_amdgcn_exp2f(-(float)(2 * (m - R) + 1) * cx2);
     const int pix = tid;
     const int rr_ = pix / RW, cc = pix % RW;
+    // the slot's pixel at row offset n, column offset m is s_gk[(rr_ - n + 2R) GP + cc - m + 2R];
+    // lanes past the region read from the origin (their weights are 0)
+    const float4 *gk0 = s_gk + (pix < NP ? rr_ * GP + cc : 0);
     const int qx = tx * kTB - R + cc, qy = ty * kTB - R + rr_;
     const bool in = pix < NP && qx >= 0 && qx < W && qy >= 0 && qy < H;
     const unsigned q = in ? (unsigned)(qy * W + qx) : 0u;
@@ -462,17 +471,14 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         float gr = 0.0f, gg = 0.0f, gb = 0.0f;
 #pragma unroll 1
         for (int n = 0; n < NM; ++n) {
-            const int jj = rr_ - n;  // tile-local row of the pixel at row offset n
             const float uy = (float)(n - R) + dy;
             const float dyn2 = uy * uy;
-            const bool rok = jj >= 0 && jj < kTB;
+            const float4 *grow = gk0 + (2 * R - n) * GP + 2 * R;
             float rx = 0.0f, rh = 0.0f;  // sums of hwt dx^2 and of hwt over the row
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-                const int ii = cc - m;
-                const bool ok = rok && ii >= 0 && ii < kTB;
-                const float w = ok ? X[m] * yv : 0.0f;
-                const float4 g4 = s_gk[ok ? jj * kTB + ii : 0];
+                const float w = X[m] * yv;
+                const float4 g4 = grow[-m];
                 gr += w * g4.x;
                 gg += w * g4.y;
                 gb += w * g4.z;
