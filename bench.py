@@ -119,12 +119,14 @@ STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gat
 
 
 def kernel_of(stage, k, radius, tpw):
-    """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name)."""
-    return {"bin_count": "k_bin_count<false>", "bin_scan": "k_scan_blocks+k_scan_add",
-            "bin_scatter": "k_bin_scatter<false>",
+    """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name). The
+    count and scatter kernels also carry the samples per thread the library picks for the launch
+    (from the sample count and the CU count), written here as a trailing '*'."""
+    return {"bin_count": "k_bin_count<false,*>", "bin_scan": "k_scan_blocks+k_scan_add",
+            "bin_scatter": "k_bin_scatter<false,*>",
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),
-            "estimate": "k_estimate<__half>",
+            "estimate": "k_estimate_strip<__half>",
             "gather": "k_reconstruct_tiled<__half,%d,%d>" % (radius, tpw)}[stage]
 SINGLE_KERNEL = ("bin_scatter", "bin_select", "estimate", "gather")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_k16_fp16.txt")
@@ -139,6 +141,19 @@ def csrc_digest():
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
+
+
+def resolve_kernel(kernel, names=None):
+    """A name ending in '*>' (any last template argument) resolved against the kernels of the PMC
+    summary when exactly one matches; otherwise the name as given."""
+    if not kernel.endswith("*>"):
+        return kernel
+    if names is None:
+        names = []
+        if os.path.exists(TRAFFIC_FILE):
+            names = [l.split()[1] for l in open(TRAFFIC_FILE) if l.startswith("kernel ")]
+    hits = [n for n in names if n.startswith(kernel[:-2])]
+    return hits[0] if len(hits) == 1 else kernel
 
 
 def read_traffic(kernel):
@@ -158,6 +173,7 @@ def read_traffic(kernel):
         elif line.startswith("kernel "):
             _, name, fk, wk = line.split()
             rows[name] = (float(fk), float(wk))
+    kernel = resolve_kernel(kernel, rows)
     if vals.get("digest") != csrc_digest() or kernel not in rows or "f_fetch" not in vals:
         return None
     fk, wk = rows[kernel]
@@ -314,7 +330,7 @@ def main():
     dom_bytes = algorithmic_bytes(dom, n, n_binned, occupied, W, H, K, nt)
     dom_gbs = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
     pairs = gather_pairs(bufs[0].count.cpu().numpy(), args.radius)
-    dom_kernel = kernel_of(dom, K, args.radius, tpw)
+    dom_kernel = resolve_kernel(kernel_of(dom, K, args.radius, tpw))
     traffic = read_traffic(dom_kernel)
     copy_gbs = copy_bandwidth(torch, dev)
 

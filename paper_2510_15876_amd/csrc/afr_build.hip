@@ -34,8 +34,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = kScanThreads * kScanItems;
 constexpr int kChunkThreads = 512;  // two 512-thread scatter workgroups share a CU, so one loads
-constexpr int kChunkPer = 8;        // while the other sorts and stores
-constexpr int kChunk = kChunkThreads * kChunkPer;  // samples per chunk
+                                    // while the other sorts and stores
+// Samples per thread (PER) of the count and scatter kernels, chosen per launch (pick_per): a chunk
+// is kChunkThreads * PER samples.
+constexpr int kPerMin = 6, kPerMax = 10;
 constexpr int kWin = 2048;  // records staged in LDS per scatter window (64 KiB: two workgroups per CU)
 constexpr int kBinW = 64;                          // bin width, px (a power of two)
 static_assert((kBinW & (kBinW - 1)) == 0, "bin width is a power of two");
@@ -118,10 +120,11 @@ __device__ inline unsigned long long order_key(float t, int i) {
 __device__ inline int key_index(unsigned long long key) { return (int)(unsigned)(key & 0xffffffffu); }
 
 // MOTION: the stream carries velocities and positions are reprojected first.
-template <bool MOTION>
+template <bool MOTION, int kChunkPer>
 __global__ __launch_bounds__(kChunkThreads) void k_bin_count(afr_samples s, ValidCtx c, BinGeom g,
                                                              int32_t *ht, int nchunks,
                                                              int32_t *bad_tab) {
+    constexpr int kChunk = kChunkThreads * kChunkPer;
     __shared__ int hist[kMaxBins];
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) hist[b] = 0;
     const int chunk = xcd_remap(blockIdx.x, gridDim.x);
@@ -267,10 +270,11 @@ __device__ inline unsigned pack_half2(__half lo, __half hi) {
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
 // position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
 // destination, is recomputed from its own x, y.
-template <bool MOTION>
+template <bool MOTION, int kChunkPer>
 __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
                                                                const int32_t *ot, int nchunks,
                                                                Bucket bucket, int32_t *bad_tab) {
+    constexpr int kChunk = kChunkThreads * kChunkPer;
     extern __shared__ uint4 scat_lds[];  // 16-byte aligned for the staged records
     int *scat_sm = reinterpret_cast<int *>(scat_lds);
     int *tab = scat_sm;  // [nb]
@@ -736,24 +740,52 @@ BinGeom bin_geom(int32_t w, int32_t h) {
     return g;
 }
 
-int64_t n_chunks(int64_t n) { return std::max<int64_t>(1, (n + kChunk - 1) / kChunk); }
+int64_t n_chunks(int64_t n, int per) {
+    const int64_t chunk = (int64_t)kChunkThreads * per;
+    return std::max<int64_t>(1, (n + chunk - 1) / chunk);
+}
+
+// Samples per thread for a launch over n samples. Two scatter workgroups are resident per CU, so the
+// chunks run in ceil(chunks / (2 CUs)) rounds, and a round takes time in proportion to the chunk
+// size; a partial last round costs a whole one. Take the size with the least rounds x size (the
+// larger on a tie: a shorter offset table). The result never depends on the chunk size.
+int pick_per(int64_t n) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    const int64_t slots = 2 * (int64_t)cus;
+    int best = 8;
+    int64_t best_cost = INT64_MAX;
+    for (int per = kPerMin; per <= kPerMax; per += 2) {
+        const int64_t cost = ((n_chunks(n, per) + slots - 1) / slots) * per;
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = per;
+        }
+    }
+    return best;
+}
 
 }  // namespace
 
 bool build_supported(int32_t w, int32_t h) { return bin_geom(w, h).nb <= kMaxBins; }
 
+// Workspace tables are sized for the smallest chunk (the most chunks) a launch can choose.
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
     const BinGeom g = bin_geom(w, h);
-    const int64_t len = (int64_t)g.nb * n_chunks(n);
+    const int64_t len = (int64_t)g.nb * n_chunks(n, kPerMin);
     const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     return align_up((size_t)(len + 1) * 4) + align_up((size_t)(nsb + 1) * 4) +
-           align_up((size_t)2 * n_chunks(n) * 4) + 2 * align_up(nn * sizeof(KeyXY)) + align_up(8);
+           align_up((size_t)2 * n_chunks(n, kPerMin) * 4) + 2 * align_up(nn * sizeof(KeyXY)) +
+           align_up(8);
 }
 
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     const BinGeom g = bin_geom(w, h);
-    const int64_t len = (int64_t)g.nb * n_chunks(n);
+    const int64_t len = (int64_t)g.nb * n_chunks(n, kPerMin);
     const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     char *p = static_cast<char *>(ws);
@@ -763,7 +795,7 @@ BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     o.bsum = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)(nsb + 1) * 4);
     o.bad = reinterpret_cast<int32_t *>(p);
-    p += align_up((size_t)2 * n_chunks(n) * 4);
+    p += align_up((size_t)2 * n_chunks(n, kPerMin) * 4);
     o.bucket = p;
     p += 2 * align_up(nn * sizeof(KeyXY));
     o.dropped_internal = reinterpret_cast<unsigned long long *>(p);
@@ -775,20 +807,38 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     auto mark = [&](int i) { return stage_end ? hipEventRecord(stage_end[i], st) : hipSuccess; };
     const ValidCtx c{out.width, out.height, out.t_ref, out.precision == AFR_FP16 ? 1 : 0};
     const BinGeom g = bin_geom(out.width, out.height);
-    const int64_t nch = n_chunks(s.n);
+    const int per = pick_per(s.n);
+    const int64_t nch = n_chunks(s.n, per);
     const int64_t len = (int64_t)g.nb * nch;
     const int nsb = (int)((len + kScanBlock - 1) / kScanBlock);
     const size_t half = align_up((size_t)(s.n > 0 ? s.n : 1) * sizeof(KeyXY));
     char *pay = static_cast<char *>(ws.bucket) + half;
     const Bucket bucket{static_cast<KeyXY *>(ws.bucket), reinterpret_cast<float4 *>(pay),
                         reinterpret_cast<uint2 *>(pay)};
-    if (s.n > 0) {
-        if (s.vx)
-            k_bin_count<true><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
-                                                                  ws.bad);
+    // count and scatter with PER samples per thread, with or without reprojection
+    auto chunked = [&](auto per_c, bool count) {
+        constexpr int P = decltype(per_c)::value;
+        const size_t shmem = count ? 0 : (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
+        if (count && s.vx)
+            k_bin_count<true, P><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
+                                                                     ws.bad);
+        else if (count)
+            k_bin_count<false, P><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets,
+                                                                      (int)nch, ws.bad);
+        else if (s.vx)
+            k_bin_scatter<true, P><<<(int)nch, kChunkThreads, shmem, st>>>(
+                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
         else
-            k_bin_count<false><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
-                                                                   ws.bad);
+            k_bin_scatter<false, P><<<(int)nch, kChunkThreads, shmem, st>>>(
+                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+    };
+    auto launch_chunked = [&](bool count) {
+        if (per == 6) chunked(std::integral_constant<int, 6>{}, count);
+        else if (per == 10) chunked(std::integral_constant<int, 10>{}, count);
+        else chunked(std::integral_constant<int, 8>{}, count);
+    };
+    if (s.n > 0) {
+        launch_chunked(true);
     } else {  // no samples: every (bin, chunk) count of the single empty chunk is zero, none dropped
         k_fill_zero<<<std::max(1, std::min((int)((len + 255) / 256), 1024)), 256, 0, st>>>(ws.offsets,
                                                                                        len);
@@ -799,14 +849,7 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     k_scan_blocks<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.offsets, ws.bsum);
     k_scan_add<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.bsum, nsb);
     if ((e = mark(1)) != hipSuccess) return e;
-    const size_t scat_shmem =
-        (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
-    if (s.n > 0 && s.vx)
-        k_bin_scatter<true><<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets,
-                                                                         (int)nch, bucket, ws.bad);
-    else if (s.n > 0)
-        k_bin_scatter<false><<<(int)nch, kChunkThreads, scat_shmem, st>>>(s, c, g, ws.offsets,
-                                                                          (int)nch, bucket, ws.bad);
+    if (s.n > 0) launch_chunked(false);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     e = out.precision == AFR_FP16
             ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st)
