@@ -167,8 +167,9 @@ def test_launch_shapes_give_identical_output(w, h, radius):
 
 
 def test_reference_statistics_round_trip_and_constants():
-    """A constant-colour buffer reproduces the constant through the GPU gather (north-star
-    invariant), and the tiled and plain forms agree to float32 rounding.
+    """A constant-colour buffer reproduces the constant through the GPU gather (a normalised
+    average of equal colours is that colour), and the tiled and plain forms agree to float32
+    rounding.
 
     Bound: the tiled form sums each slot plane's <= (2R+1)^2 terms in float32 and adds the plane
     partials with compensation, so numerator and denominator each carry <= ((2R+1)^2 + 4) u relative
