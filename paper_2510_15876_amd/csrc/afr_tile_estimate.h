@@ -7,9 +7,8 @@
 // old-half means that give the temporal difference quotient, and the age sum. Results go to LDS.
 // Phase 2 gives each tile pixel its spatial gradients from the LDS neighbours and folds all
 // per-pixel terms of a tile into one accumulator per lane (pixel e on lane e mod 64); lanes are
-// combined by a fixed-shape butterfly within the wave and in wave order across waves. The luminance
-// mean and variance come from FP64 sums of omega, omega L and omega L^2 (in [0, 1] luminance the
-// cancellation in s2 / w - (s1 / w)^2 costs at most ~1e-16 absolute, far below the float32 output).
+// combined by a fixed-shape butterfly within the wave and in wave order across waves. Luminance
+// variance merges per-pixel (weight, mean, M2) triples with the pairwise form of Welford's update.
 //
 // Two drivers share these routines: a strip kernel (afr_estimate_gradients, tiles of edge <= 8)
 // where a workgroup covers a 32-pixel-wide strip of tiles, so that each wave reads whole image rows
@@ -36,7 +35,7 @@ constexpr double kLumR = 0.2126, kLumG = 0.7152, kLumB = 0.0722;
 struct Acc {
     double gx, wx, gy, wy, gt, wt;  // sums of Omega_p G(p) and Omega_p over defined pixels
     double n, sa;                   // slot count and age sum
-    double w, s1, s2;               // age-weighted luminance: sums of omega, omega L, omega L^2
+    double w, mean, m2;             // age-weighted luminance: weight, mean, sum of squared deviations
 };
 
 __device__ inline Acc acc_zero() { return Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; }
@@ -52,9 +51,22 @@ __device__ inline Acc acc_combine(const Acc &a, const Acc &b) {
     c.wt = a.wt + b.wt;
     c.n = a.n + b.n;
     c.sa = a.sa + b.sa;
-    c.w = a.w + b.w;
-    c.s1 = a.s1 + b.s1;
-    c.s2 = a.s2 + b.s2;
+    if (b.w == 0.0) {
+        c.w = a.w;
+        c.mean = a.mean;
+        c.m2 = a.m2;
+    } else if (a.w == 0.0) {
+        c.w = b.w;
+        c.mean = b.mean;
+        c.m2 = b.m2;
+    } else {
+        // pairwise (Chan et al.) form of Welford's update, one division
+        c.w = a.w + b.w;
+        const double r = 1.0 / c.w;
+        const double d = b.mean - a.mean;
+        c.mean = a.mean + d * (b.w * r);
+        c.m2 = a.m2 + b.m2 + d * d * (a.w * b.w * r);
+    }
     return c;
 }
 
@@ -71,8 +83,8 @@ __device__ inline Acc acc_shfl_xor(const Acc &a, int m) {
     o.n = shfl_xor_d(a.n, m);
     o.sa = shfl_xor_d(a.sa, m);
     o.w = shfl_xor_d(a.w, m);
-    o.s1 = shfl_xor_d(a.s1, m);
-    o.s2 = shfl_xor_d(a.s2, m);
+    o.mean = shfl_xor_d(a.mean, m);
+    o.m2 = shfl_xor_d(a.m2, m);
     return o;
 }
 
@@ -146,19 +158,20 @@ __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S t
     }
 }
 
-// Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum,
-// sum omega L^2) in LDS, row-major with a given pitch.
+// Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum, M2)
+// in LDS, row-major with a given pitch.
 struct Region {
-    double *lbar, *om, *gt, *sa, *s2;
+    double *lbar, *om, *gt, *sa, *m2;
     int *n;
 };
 
 __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n, double dt_floor) {
 #pragma clang fp contract(off)
-    double om = 0.0, lb = 0.0, gt = -1.0;
+    double om = 0.0, lb = 0.0, gt = -1.0, m2 = 0.0;
     if (n > 0) {
         om = m.s0;
         lb = m.s1 / m.s0;
+        m2 = fmax(m.s2 - m.s1 * lb, 0.0);
     }
     if (n >= 2) {
         const int half = (n + 1) / 2;
@@ -170,7 +183,7 @@ __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n
     rg.lbar[h] = lb;
     rg.gt[h] = gt;
     rg.sa[h] = m.sa;
-    rg.s2[h] = m.s2;
+    rg.m2[h] = m2;
 }
 
 // ---- per-tile reduction (phase 2) ---------------------------------------------------------------
@@ -194,8 +207,8 @@ __device__ inline Acc pixel_acc(const Region &rg, int h, int rp) {
     a.n = n;
     a.sa = rg.sa[h];
     a.w = om;
-    a.s1 = om * lb;
-    a.s2 = rg.s2[h];
+    a.mean = lb;
+    a.m2 = rg.m2[h];
     return a;
 }
 
@@ -213,10 +226,11 @@ __device__ inline Acc wave_tile_acc(const Region &rg, int h0, int rp, int bw, in
     return acc;
 }
 
-// Tile statistics from the tile's accumulator, evaluated by all lanes of one wave holding the same
-// accumulator: lanes 0, 1 and 2 take the three cube roots of the extents at once (the same operations
-// as extents()), and lane 0 writes the stats planes and, if tparams is not NULL, (sx2, sy2, kt2) to
-// tparams.
+// Tile statistics from the tile's accumulator, evaluated by all lanes of one wave: the gradient,
+// count and age sums are plain sums, equal in every lane after the butterfly, so lanes 0, 1 and 2
+// take the three cube roots of the extents at once (the same operations as extents()); lane 0's
+// luminance moments are the wave's, and lane 0 writes the stats planes and, if tparams is not NULL,
+// (sx2, sy2, kt2) to tparams.
 __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileGeom &tg, int T,
                                    int bw, int bh, float *stats, float *tparams, int lane) {
 #pragma clang fp contract(off)
@@ -225,8 +239,8 @@ __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileG
     const double gt = t.wt > 0.0 ? t.gt / t.wt : 0.0;
     const double area = (double)bw * bh;
     const double vol = t.n > 0.0 ? area * 2.0 * fmax(t.sa / t.n, p.age_floor) / t.n : INFINITY;
-    const double lmean = t.w > 0.0 ? t.s1 / t.w : 0.0;
-    const double var = t.w > 0.0 ? fmax(t.s2 / t.w - lmean * lmean, 0.0) : 0.0;
+    const double var = t.w > 0.0 ? t.m2 / t.w : 0.0;
+    const double lmean = t.w > 0.0 ? t.mean : 0.0;
     const double hx = sqrt(gx * gx + p.g_floor * p.g_floor);
     const double hy = sqrt(gy * gy + p.g_floor * p.g_floor);
     const double u = p.tau * gt;
@@ -332,7 +346,7 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
 template <int TB>
 struct Smem {
     static constexpr int kHalo = (TB + 2) * (TB + 2);
-    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], s2[kHalo];
+    double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
     int n[kHalo];
     Acc wave[256 / kWave];
 };
@@ -344,7 +358,7 @@ struct Smem {
 template <typename S, int TB>
 __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int T,
                               float *stats, Smem<TB> &sm, float *tparams) {
-    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.s2, sm.n};
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
     const int B = tg.tile;
     const int i0 = (T % tg.tiles_x) * B, j0 = (T / tg.tiles_x) * B;
     const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
@@ -372,7 +386,7 @@ constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
 
 struct StripSmem {
     double lbar[kStripRegion], om[kStripRegion], gt[kStripRegion], sa[kStripRegion],
-        s2[kStripRegion];
+        m2[kStripRegion];
     int n[kStripRegion];
 };
 
@@ -384,7 +398,7 @@ __host__ __device__ inline int strip_tiles(int B) { return kStripW / B; }
 template <typename S>
 __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int tx0,
                                int ty, float *stats, StripSmem &sm) {
-    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.s2, sm.n};
+    const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
     const int B = tg.tile;
     const int ntile = min(strip_tiles(B), tg.tiles_x - tx0);
     const int i0 = tx0 * B, j0 = ty * B;
