@@ -408,6 +408,12 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     float gxm[NM];
 #pragma unroll
     for (int m = 0; m < 2 * R; ++m) gxm[m] = __builtin_amdgcn_exp2f(-(float)(2 * (m - R) + 1) * cx2);
+    // Recurrences start from the smallest value of a row and need it in float32's range: Y(-R) >=
+    // 2^-(R+1/2)^2 cy2 normal, (R + 1/2)^2 cy2 <= 120; X(-R) carries Tm, and a product below the
+    // subnormal range would drop the larger X values too (at most 2^((R+1/2)^2 cx2) times larger), so
+    // the X recurrence is kept to (R + 1/2)^2 cx2 <= 20. Narrower tiles evaluate every value directly.
+    constexpr float kR2 = (R + 0.5f) * (R + 0.5f);
+    const bool xrec = kR2 * cx2 <= 20.0f, yrec = kR2 * cy2 <= 120.0f;
     const int pix = tid;
     const int rr_ = pix / RW, cc = pix % RW;
     // the slot's pixel at row offset n, column offset m is s_gk[(rr_ - n + 2R) GP + cc - m + 2R];
@@ -451,11 +457,19 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         // are visited one at a time with Y advanced by its recurrence.
         float X[NM], dx2[NM];
         const float ex = dx - (float)R, ey = dy - (float)R;
-        X[0] = __builtin_amdgcn_exp2f(-ex * ex * cx2) * tm;
-        if (R > 0) {
-            const float rhox = __builtin_amdgcn_exp2f(-2.0f * dx * cx2);
+        if (xrec) {
+            X[0] = __builtin_amdgcn_exp2f(-ex * ex * cx2) * tm;
+            if (R > 0) {
+                const float rhox = __builtin_amdgcn_exp2f(-2.0f * dx * cx2);
 #pragma unroll
-            for (int m = 0; m < 2 * R; ++m) X[m + 1] = X[m] * rhox * gxm[m];
+                for (int m = 0; m < 2 * R; ++m) X[m + 1] = X[m] * rhox * gxm[m];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const float e = dx + (float)(m - R);
+                X[m] = __builtin_amdgcn_exp2f(-e * e * cx2) * tm;
+            }
         }
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
@@ -489,8 +503,13 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             Sx += (double)rx;
             Sy += (double)rh * dyn2;
             Sa += (double)rh * a2;
-            // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2)
-            yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
+            // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2), or its own exponential
+            if (yrec) {
+                yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
+            } else {
+                const float e = dy + (float)(n + 1 - R);
+                yv = __builtin_amdgcn_exp2f(-e * e * cy2);
+            }
         }
         if (on) {
             float *pt = ws.part + ((size_t)T * K + k) * 3 * NP + pix;

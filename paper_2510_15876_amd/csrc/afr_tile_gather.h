@@ -15,8 +15,9 @@
 // With binary16 storage the temporal factor goes into Y instead (Y' = Y * Tm, its exponent added to
 // that of Y(-R) before the recurrence) and the colours stay in LDS as the stored binary16 values, which
 // the FMAs take as operands directly (mixed-precision FMA): the same arithmetic count per pair from 16
-// instead of 24 bytes of LDS reads. Y'(-R) >= 2^-18 Y'(0) at R = 2 and the widths' floor, so a
-// subnormal Y'(-R) only carries weights below 2^-108, negligible next to the 1e-30 weight-sum floor.
+// instead of 24 bytes of LDS reads. The recurrences start from the smallest value of the row, which
+// must not underflow: tiles narrower than that bound (and, for the folded Y', than a tighter one)
+// evaluate each value from its own exponential instead (see xrec, yrec).
 //
 // Shift: a_ref is the smallest slot-0 age over the tile's source region (slot 0 is each pixel's
 // newest sample), so every Tm <= 1; the pixel's largest weight is at least exp(-(2R+1)^2 / (8 e_min^2))
@@ -177,6 +178,15 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
         gxm[m] = fast_exp2(-(float)(2 * (m - R) + 1) * cx2);
         gym[m] = fast_exp2(-(float)(2 * (m - R) + 1) * cy2);
     }
+    // The recurrence needs its starting value X(-R) >= 2^-(R+1/2)^2 c to stay in float32's normal
+    // range: (R + 1/2)^2 c <= 120. With binary16 storage Y'(-R) also carries Tm: a Y'(-R) below the
+    // subnormal range then drops the source's other Y' values too, which are at most
+    // 2^((R+1/2)^2 cy2) times larger, so the folded recurrence is kept to (R + 1/2)^2 cy2 <= 20
+    // (lost weights < 2^-129 of the region reference, below every normalised pixel's resolution). The
+    // default width floor (0.5 px) gives 18 at R = 2. Narrower tiles take one exponential per value.
+    constexpr float kR2 = (R + 0.5f) * (R + 0.5f);
+    const bool xrec = kR2 * cx2 <= 120.0f;
+    const bool yrec = kR2 * cy2 <= (kMix ? 20.0f : 120.0f);
 
     // Items: this lane's source pixels of its tile region; address and depth are loop invariant.
     int iq[ITEMS], icnt[ITEMS];
@@ -252,19 +262,41 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 const float dy = on ? Codec<S>::dec(roy[it]) - 0.5f : 0.0f;
                 const float a = on ? Codec<S>::age(rta[it], p.t_now, p.dt_ref) : amin;
                 const float lt = -((a - amin) * (a + amin)) * ct2;  // log2 Tm
-                // X[m] = exp2(-((m - R) + dx)^2 cx2), upward from the smallest value X[0]
+                // X[m] = exp2(-((m - R) + dx)^2 cx2): upward from the smallest value X[0] by the
+                // recurrence, or each from its own exponential for tiles too narrow for it
                 float X[NM], Y[NM];
                 const float ex = dx - (float)R, ey = dy - (float)R;
-                X[0] = fast_exp2(-ex * ex * cx2);
-                // binary16 storage: Y'(m) = Y(m) Tm from one exponential, 0 for an empty slot
-                Y[0] = kMix ? fast_exp2(on ? -ey * ey * cy2 + lt : -INFINITY)
-                            : fast_exp2(-ey * ey * cy2);
-                if (R > 0) {
-                    const float rhox = fast_exp2(-2.0f * dx * cx2), rhoy = fast_exp2(-2.0f * dy * cy2);
+                if (xrec) {
+                    X[0] = fast_exp2(-ex * ex * cx2);
+                    if (R > 0) {
+                        const float rhox = fast_exp2(-2.0f * dx * cx2);
 #pragma unroll
-                    for (int m = 0; m < 2 * R; ++m) {
-                        X[m + 1] = X[m] * rhox * gxm[m];
-                        Y[m + 1] = Y[m] * rhoy * gym[m];
+                        for (int m = 0; m < 2 * R; ++m) X[m + 1] = X[m] * rhox * gxm[m];
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) {
+                        const float e = dx + (float)(m - R);
+                        X[m] = fast_exp2(-e * e * cx2);
+                    }
+                }
+                // binary16 storage: Y'(m) = Y(m) Tm, 0 for an empty slot; with the recurrence Tm's
+                // exponent joins Y(0)'s, evaluated 2^32 up and scaled back so that it keeps
+                // subnormal values (see the top of the file)
+                const float lt_on = on ? lt : -INFINITY;
+                if (yrec) {
+                    Y[0] = kMix ? fast_exp2(-ey * ey * cy2 + lt_on + 32.0f) * 0x1p-32f
+                                : fast_exp2(-ey * ey * cy2);
+                    if (R > 0) {
+                        const float rhoy = fast_exp2(-2.0f * dy * cy2);
+#pragma unroll
+                        for (int m = 0; m < 2 * R; ++m) Y[m + 1] = Y[m] * rhoy * gym[m];
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) {
+                        const float e = dy + (float)(m - R);
+                        Y[m] = fast_exp2(-e * e * cy2 + (kMix ? lt_on : 0.0f));
                     }
                 }
                 const int xy = (pix / RW) * XP + pix % RW;

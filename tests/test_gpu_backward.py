@@ -204,3 +204,27 @@ def test_backward_pixels_evaluated_directly():
     aux = _adjoint_case(s, w, h, k, "fp32", t_now, 2, edit_stats=big_kt2, seed=9)
     # pixels of the corner tile evaluated directly carry their own (very negative) maximum exponent
     assert (aux[0][:8, :8] < -80.0).sum() > 10
+
+
+@pytest.mark.parametrize("sx2,sy2,kt2,precision", [(0.01, 0.02, None, "fp32"), (0.015, 0.01, None, "fp16"),
+                                                   (0.0625, 0.0625, 0.05, "fp32"),
+                                                   (0.0625, 0.09, 0.05, "fp16")])
+def test_narrow_widths(sx2, sy2, kt2, precision):
+    """Spatial standard deviations of 0.1 to 0.3 px (statistics supplied by the caller, below the
+    default width floor): the weights of the far offsets fall far below float32's range while the
+    near ones stay large, so the separable factors cannot be carried upward from the smallest one.
+    With a temporal sensitivity on top, old samples get small but non-negligible weights. The tiled
+    forward and adjoint must still match the reference."""
+    w, h, k = 40, 24, 4
+    rng = np.random.default_rng(91)
+    scene = S.DiscScene(w, h, rng, 8, 40.0, speed=0.3, radius=(2.0, 7.0))
+    s = S.stratified_stream(scene, w, h, k, 40.0, 40.0, rng)
+    print(f"narrow widths sx2={sx2} sy2={sy2} kt2={kt2} {precision}", flush=True)
+
+    def narrow(ost):
+        ost[O.STAT["sx2"]] = sx2
+        ost[O.STAT["sy2"]] = sy2
+        if kt2 is not None:
+            ost[O.STAT["kt2"]] = kt2
+
+    _adjoint_case(s, w, h, k, precision, 40.0, 2, edit_stats=narrow, seed=5)
