@@ -134,7 +134,8 @@ __device__ inline double age_weight(double alpha, double a) {
     const double x = alpha * a * 1.4426950408889634;
     const double n = floor(x);
     const int e = (int)fmin(fmax(n, -2000.0), 2000.0);
-    return ldexp((double)exp2f((float)(n - x)), -e);
+    // n - x lies in (-1, 0]: the hardware exponential needs no range handling there
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(n - x)), -e);
 }
 
 // Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta.
