@@ -414,6 +414,11 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     // the X recurrence is kept to (R + 1/2)^2 cx2 <= 20. Narrower tiles evaluate every value directly.
     constexpr float kR2 = (R + 0.5f) * (R + 0.5f);
     const bool xrec = kR2 * cx2 <= 20.0f, yrec = kR2 * cy2 <= 120.0f;
+    // Row offsets n with a pixel of the tile for some slot of this wave: a slot in region row r
+    // reaches tile rows r - n in [0, 8) only. The wave's slots span region rows r_lo .. r_hi, so
+    // rows outside [max(0, r_lo - 7), min(2R, r_hi)] add exact zeros for every lane and are skipped.
+    const int r_lo = (wid * kWave) / RW, r_hi = min(NP - 1, wid * kWave + kWave - 1) / RW;
+    const int n_lo = max(0, r_lo - (kTB - 1)), n_hi = min(2 * R, r_hi);
     const int pix = tid;
     const int rr_ = pix / RW, cc = pix % RW;
     // the slot's pixel at row offset n, column offset m is s_gk[(rr_ - n + 2R) GP + cc - m + 2R];
@@ -456,7 +461,7 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
         // X for the 2R+1 column offsets (times the temporal factor), kept in registers; the rows
         // are visited one at a time with Y advanced by its recurrence.
         float X[NM], dx2[NM];
-        const float ex = dx - (float)R, ey = dy - (float)R;
+        const float ex = dx - (float)R;
         if (xrec) {
             X[0] = __builtin_amdgcn_exp2f(-ex * ex * cx2) * tm;
             if (R > 0) {
@@ -477,14 +482,16 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             dx2[m] = ux * ux;
         }
         const float rhoy = __builtin_amdgcn_exp2f(-2.0f * dy * cy2);
-        float yv = __builtin_amdgcn_exp2f(-ey * ey * cy2);
+        // first row offset this wave needs (see n_lo below), its Y directly
+        const float ey0 = dy + (float)(n_lo - R);
+        float yv = __builtin_amdgcn_exp2f(-ey0 * ey0 * cy2);
         // The a^2 factor of the tau terms enters as a^2 - amin^2: for every pixel the pi-weighted sum
         // of h over its slots is zero, so a constant offset of a^2 changes nothing but the
         // rounding, and this one keeps the factor small wherever a weight is not negligible.
         const float a2 = da2;
         float gr = 0.0f, gg = 0.0f, gb = 0.0f;
 #pragma unroll 1
-        for (int n = 0; n < NM; ++n) {
+        for (int n = n_lo; n <= n_hi; ++n) {
             const float uy = (float)(n - R) + dy;
             const float dyn2 = uy * uy;
             const float4 *grow = gk0 + (2 * R - n) * GP + 2 * R;
