@@ -6,12 +6,12 @@
 namespace afr {
 namespace {
 
+// One tile per wave at R <= 2 keeps five waves per SIMD (at most 96 VGPRs): the LDS of 19 such
+// workgroups fits a CU, enough for every tile of a 640x480 image to be resident at once.
 template <typename S, int R, int TPW>
-__global__ __launch_bounds__(kWave) void k_reconstruct_tiled(BufView<S> v, gat::TiledParams p,
-                                                            TileGeom tg,
-                                                            const float *__restrict__ stats,
-                                                            float *__restrict__ rgb,
-                                                            float *__restrict__ aux, int gx) {
+__global__ __launch_bounds__(kWave, (TPW == 1 && R <= 2) ? 5 : 1) void k_reconstruct_tiled(
+    BufView<S> v, gat::TiledParams p, TileGeom tg, const float *__restrict__ stats,
+    float *__restrict__ rgb, float *__restrict__ aux, int gx) {
     __shared__ gat::Smem<R, TPW> sm;
     __shared__ float tparam[3 * TPW];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);

@@ -250,9 +250,12 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     uint2 *tC = reinterpret_cast<uint2 *>(sP) + (TPW == 1 ? 0 : my_t * PS);
     float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col) at row * XP + col
     float *tY = tX + RW;                          // Y at row * XP + RW + col
-    for (int k = 0; k < kmax; ++k) {
-        // Separable factors of plane k for this tile's source region. A slot beyond its pixel's
-        // count (or a pixel outside the image) gets P = 0 and finite dummy factors.
+    // Separable factors of plane k for this tile's source region. A slot beyond its pixel's count
+    // (or a pixel outside the image) gets P = 0 and finite dummy factors. REC: the recurrences (every
+    // tile of the wave allows them, the usual case: one branch-free instruction stream); otherwise
+    // every factor from its own exponential.
+    auto factors = [&](int k, auto rec_c) {
+        constexpr bool REC = decltype(rec_c)::value;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int pix = sub + it * LPT;
@@ -262,41 +265,33 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 const float dy = on ? Codec<S>::dec(roy[it]) - 0.5f : 0.0f;
                 const float a = on ? Codec<S>::age(rta[it], p.t_now, p.dt_ref) : amin;
                 const float lt = -((a - amin) * (a + amin)) * ct2;  // log2 Tm
-                // X[m] = exp2(-((m - R) + dx)^2 cx2): upward from the smallest value X[0] by the
-                // recurrence, or each from its own exponential for tiles too narrow for it
-                float X[NM], Y[NM];
-                const float ex = dx - (float)R, ey = dy - (float)R;
-                if (xrec) {
-                    X[0] = fast_exp2(-ex * ex * cx2);
-                    if (R > 0) {
-                        const float rhox = fast_exp2(-2.0f * dx * cx2);
-#pragma unroll
-                        for (int m = 0; m < 2 * R; ++m) X[m + 1] = X[m] * rhox * gxm[m];
-                    }
-                } else {
-#pragma unroll
-                    for (int m = 0; m < NM; ++m) {
-                        const float e = dx + (float)(m - R);
-                        X[m] = fast_exp2(-e * e * cx2);
-                    }
-                }
                 // binary16 storage: Y'(m) = Y(m) Tm, 0 for an empty slot; with the recurrence Tm's
                 // exponent joins Y(0)'s, evaluated 2^32 up and scaled back so that it keeps
                 // subnormal values (see the top of the file)
                 const float lt_on = on ? lt : -INFINITY;
-                if (yrec) {
+                // X[m] = exp2(-((m - R) + dx)^2 cx2): upward from the smallest value X[0] by the
+                // recurrence, or each from its own exponential
+                float X[NM], Y[NM];
+                if constexpr (REC) {
+                    const float ex = dx - (float)R, ey = dy - (float)R;
+                    X[0] = fast_exp2(-ex * ex * cx2);
                     Y[0] = kMix ? fast_exp2(-ey * ey * cy2 + lt_on + 32.0f) * 0x1p-32f
                                 : fast_exp2(-ey * ey * cy2);
                     if (R > 0) {
+                        const float rhox = fast_exp2(-2.0f * dx * cx2);
                         const float rhoy = fast_exp2(-2.0f * dy * cy2);
 #pragma unroll
-                        for (int m = 0; m < 2 * R; ++m) Y[m + 1] = Y[m] * rhoy * gym[m];
+                        for (int m = 0; m < 2 * R; ++m) {
+                            X[m + 1] = X[m] * rhox * gxm[m];
+                            Y[m + 1] = Y[m] * rhoy * gym[m];
+                        }
                     }
                 } else {
 #pragma unroll
                     for (int m = 0; m < NM; ++m) {
-                        const float e = dy + (float)(m - R);
-                        Y[m] = fast_exp2(-e * e * cy2 + (kMix ? lt_on : 0.0f));
+                        const float ex = dx + (float)(m - R), ey = dy + (float)(m - R);
+                        X[m] = fast_exp2(-ex * ex * cx2);
+                        Y[m] = fast_exp2(-ey * ey * cy2 + (kMix ? lt_on : 0.0f));
                     }
                 }
                 const int xy = (pix / RW) * XP + pix % RW;
@@ -327,6 +322,13 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 }
             }
         }
+    };
+    const bool rec = __all(xrec && yrec);  // uniform over the wave
+    for (int k = 0; k < kmax; ++k) {
+        if (rec)
+            factors(k, std::true_type{});
+        else
+            factors(k, std::false_type{});
         __syncthreads();
         // Plane k+1 is loaded in the same scheduling region as plane k's accumulation (no branch
         // around it: after the last plane it reloads plane K-1, unused), so the accumulation
