@@ -43,9 +43,12 @@ constexpr int kBinW = 64;                          // bin width, px (a power of 
 static_assert((kBinW & (kBinW - 1)) == 0, "bin width is a power of two");
 constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
 constexpr int kMaxBinPx = 2048;                    // pixels per bin (rows grow from 4 to 32)
-constexpr int kSelThreads = 256;
-constexpr int kSelPer = 20;
-constexpr int kListCap = kSelThreads * kSelPer;    // records sorted in LDS per select pass
+constexpr int kListCap = 5120;                     // records sorted in LDS per select pass
+// Select workgroup: 512 threads while the per-pixel top-K stays small (KMAX <= 16; the sweep and the
+// LDS sort then have twice the waves to overlap, at the same LDS per bin), else 256 (register lists
+// of 32 or 64 keys need the registers).
+template <int KMAX>
+constexpr int sel_threads() { return KMAX <= 16 ? 512 : 256; }
 
 struct ValidCtx {
     int32_t w, h;
@@ -582,10 +585,11 @@ __device__ inline KeyXY load_key_xy(const KeyXY *r) { return *r; }
 // positions in the bin (u16) and, for binary16 buffers, their encoded offsets (u32), each with
 // kListSlots entries (kListCap records plus the pads of swz).
 template <typename S, int KMAX>
-__global__ __launch_bounds__(kSelThreads) void k_bin_select(afr_deep_buffer out, BinGeom g,
+__global__ __launch_bounds__(sel_threads<KMAX>()) void k_bin_select(afr_deep_buffer out, BinGeom g,
                                                             const int32_t *ot, int nchunks,
                                                             Bucket bucket, const int32_t *bad_tab,
                                                             unsigned long long *dropped) {
+    constexpr int kSelThreads = sel_threads<KMAX>(), kSelPer = kListCap / kSelThreads;
     extern __shared__ uint4 sel_lds[];  // 16-byte aligned for the key list
     int *sel_sm = reinterpret_cast<int *>(sel_lds);
     if (blockIdx.x == 0) {  // dropped samples: the per-chunk counts of the count and scatter passes
@@ -710,13 +714,18 @@ hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int
                          int nchunks, Bucket bucket, const int32_t *bad_tab,
                          unsigned long long *dropped, hipStream_t st) {
     const size_t shmem = select_shmem<S>(g);
-    const dim3 grid(g.nb), block(kSelThreads);
-    if (out.k <= 4) k_bin_select<S, 4><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
-    else if (out.k <= 8) k_bin_select<S, 8><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
-    else if (out.k <= 16) k_bin_select<S, 16><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
-    else if (out.k <= 32) k_bin_select<S, 32><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
-    else if (out.k <= 64) k_bin_select<S, 64><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
-    else k_bin_select<S, 256><<<grid, block, shmem, st>>>(out, g, ot, nchunks, bucket, bad_tab, dropped);
+    const dim3 grid(g.nb);
+    auto go = [&](auto kmax_c) {
+        constexpr int KM = decltype(kmax_c)::value;
+        k_bin_select<S, KM><<<grid, dim3(sel_threads<KM>()), shmem, st>>>(out, g, ot, nchunks,
+                                                                        bucket, bad_tab, dropped);
+    };
+    if (out.k <= 4) go(std::integral_constant<int, 4>{});
+    else if (out.k <= 8) go(std::integral_constant<int, 8>{});
+    else if (out.k <= 16) go(std::integral_constant<int, 16>{});
+    else if (out.k <= 32) go(std::integral_constant<int, 32>{});
+    else if (out.k <= 64) go(std::integral_constant<int, 64>{});
+    else go(std::integral_constant<int, 256>{});
     return hipGetLastError();
 }
 
