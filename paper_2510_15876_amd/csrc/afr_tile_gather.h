@@ -51,16 +51,19 @@ struct TiledParams {
 // LDS of one group evaluation. P: one float4 per source pixel of each tile's region (row pitch RW);
 // with binary16 storage the same array holds each source pixel's three colours as they are stored
 // (one uint2: r | g << 16, b), at the same positions in uint2 units.
-// XY: per tile and offset m, the region's X values in columns [0, RW) and its Y values in columns
-// [RW, 2 RW) of rows with pitch XP. XP is 8 times an odd number, so an 8 x 8 block of lanes reading
-// (row + h, col + c) hits 64 distinct banks (and each half-wave 32), and tiles are XYS apart with
-// XYS = 8 (mod 64), which puts the lane blocks of up to four tiles on disjoint banks.
+// XY: per tile and region row, the 2R+1 offsets m one after another (pitch XP), each with the row's X
+// values in columns [0, RW) and its Y values in columns [RW, 2 RW): X(row, col, m) at
+// row * RP + m * XP + col with RP = (2R+1) XP. A lane's X and Y reads of one source row then lie
+// within a few hundred bytes, so they pair into two-address reads with little address arithmetic,
+// and RP modulo 64 is an odd multiple of 8 at every R, so an 8 x 8 block of lanes reading
+// (row + h, col + c) hits 64 distinct banks. Tiles are XYS apart with XYS = 8 (mod 64), which puts
+// the lane blocks of up to four tiles on disjoint banks.
 template <int R>
 struct XYLayout {
     static constexpr int RW = 8 + 2 * R, NM = 2 * R + 1;
     static constexpr int XP = (2 * RW <= 24) ? 24 : 40;
-    static constexpr int XYM = RW * XP;                                 // one offset m
-    static constexpr int XYS = (NM * XYM + 55) / 64 * 64 + 8;           // one tile
+    static constexpr int RP = NM * XP;                                  // one region row
+    static constexpr int XYS = (RW * RP + 55) / 64 * 64 + 8;            // one tile
 };
 // P: with one tile per wave, (P.x, P.y) and (P.z, P.w) of region (row, col) are float2s at
 // row * XP + col and row * XP + RW + col, so the 64-bit reads of an 8 x 8 lane block hit distinct
@@ -154,7 +157,7 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     constexpr int PS = NP + 5;              // padded plane stride (spreads tiles over LDS banks)
     constexpr int NM = 2 * R + 1;           // offsets per axis
     constexpr int ITEMS = (NP + LPT - 1) / LPT;
-    constexpr int XP = XYLayout<R>::XP, XYM = XYLayout<R>::XYM;
+    constexpr int XP = XYLayout<R>::XP, RP = XYLayout<R>::RP;
     constexpr bool kMix = std::is_same<S, __half>::value;  // colours kept as binary16 in LDS
     float4 *sP = sm.P;
 
@@ -248,8 +251,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     float2 *tPP = reinterpret_cast<float2 *>(sP);  // split layout (one tile per wave)
     // binary16 colours: row pitch XP (one tile per wave) or the tile's plane of PS entries
     uint2 *tC = reinterpret_cast<uint2 *>(sP) + (TPW == 1 ? 0 : my_t * PS);
-    float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col) at row * XP + col
-    float *tY = tX + RW;                          // Y at row * XP + RW + col
+    float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col, m) at row * RP + m * XP + col
+    float *tY = tX + RW;                          // Y at row * RP + m * XP + RW + col
     // Separable factors of plane k for this tile's source region. A slot beyond its pixel's count
     // (or a pixel outside the image) gets P = 0 and finite dummy factors. REC: the recurrences (every
     // tile of the wave allows them, the usual case: one branch-free instruction stream); otherwise
@@ -295,6 +298,7 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                     }
                 }
                 const int xy = (pix / RW) * XP + pix % RW;
+                const int xyt = (pix / RW) * RP + pix % RW;
                 if constexpr (kMix) {
                     // an empty slot's colours are written as 0 (its Y' is 0)
                     const unsigned c0 = on ? ((unsigned)__half_as_ushort(rr[it]) |
@@ -317,8 +321,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                 }
 #pragma unroll
                 for (int m = 0; m < NM; ++m) {
-                    tX[m * XYM + xy] = X[m];
-                    tY[m * XYM + xy] = Y[m];
+                    tX[xyt + m * XP] = X[m];
+                    tY[xyt + m * XP] = Y[m];
                 }
             }
         }
@@ -347,7 +351,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
             for (int w = 0; w < NM; ++w) {
                 const int pix = (my_h * ROWS + vv) * RW + my_c + w;
                 const int xy = (my_h * ROWS + vv) * XP + my_c + w;
-                const float x = tX[w * XYM + xy];
+                const int xyt = (my_h * ROWS + vv) * RP + my_c + w;
+                const float x = tX[xyt + w * XP];
                 if constexpr (kMix) {
                     const uint2 cw = tC[TPW == 1 ? xy : pix];
                     const __half2 rg2 = __halves2half2(__ushort_as_half((unsigned short)cw.x),
@@ -357,7 +362,7 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                     for (int u = 0; u < ROWS; ++u) {
                         const int nn = vv - u;  // n + R
                         if (nn >= 0 && nn <= 2 * R) {
-                            const float wgt = x * tY[nn * XYM + xy];  // X * Y * Tm
+                            const float wgt = x * tY[xyt + nn * XP];  // X * Y * Tm
                             part[u][0] += wgt;
                             part[u][1] = fmaf(wgt, __low2float(rg2), part[u][1]);
                             part[u][2] = fmaf(wgt, __high2float(rg2), part[u][2]);
@@ -376,7 +381,7 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
                     for (int u = 0; u < ROWS; ++u) {
                         const int nn = vv - u;  // n + R
                         if (nn >= 0 && nn <= 2 * R) {
-                            const float wgt = x * tY[nn * XYM + xy];
+                            const float wgt = x * tY[xyt + nn * XP];
                             part[u][0] += wgt * P.x;
                             part[u][1] += wgt * P.y;
                             part[u][2] += wgt * P.z;
