@@ -11,8 +11,10 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name,precision", [("c1", "fp32"), ("c1", "fp16"), ("c2", "fp32"),
-                                            ("c0", "fp32"), ("c3", "fp16")])
+                                            ("c0", "fp32"), ("c3", "fp16"), ("c4", "fp32")])
 def test_build_matches_reference(name, precision):
+    """Every chunk size the launch picks is covered: 6 samples per thread for the small workloads,
+    8 for c4 (2.1M samples), 10 for c3 (4.9M) on a 256-CU device."""
     wl = workload(name)
     print(f"build parity {name} {precision} {wl.width}x{wl.height} K={wl.k} n={len(wl.stream)}",
           flush=True)
