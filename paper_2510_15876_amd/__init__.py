@@ -323,6 +323,7 @@ def _stats_c(stats: torch.Tensor, tile: int) -> _TileStats:
 
 
 _ws_cache = {}
+_WS_CACHE_MAX = 64  # entries (kind x device x stream); the oldest go first beyond this
 
 
 def _workspace(nbytes: int, device, key: str, stream=None) -> torch.Tensor:
@@ -331,11 +332,15 @@ def _workspace(nbytes: int, device, key: str, stream=None) -> torch.Tensor:
     that uses it, so the allocator never hands it to other work while that stream still runs."""
     s = torch.cuda.current_stream(device) if stream is None else stream
     k = (key, str(device), s.cuda_stream)
-    t = _ws_cache.get(k)
+    t = _ws_cache.pop(k, None)
     if t is None or t.numel() < nbytes:
         with torch.cuda.stream(s):
             t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        _ws_cache[k] = t
+    _ws_cache[k] = t  # most recently used last
+    while len(_ws_cache) > _WS_CACHE_MAX:
+        # a dropped workspace returns to its own stream's pool, so work queued on that stream
+        # still finishes before the memory is handed out again
+        _ws_cache.pop(next(iter(_ws_cache)))
     return t
 
 
