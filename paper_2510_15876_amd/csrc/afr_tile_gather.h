@@ -254,9 +254,8 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
     float *tX = sm.XY + my_t * XYLayout<R>::XYS;  // X of region (row, col, m) at row * RP + m * XP + col
     float *tY = tX + RW;                          // Y at row * RP + m * XP + RW + col
     // Separable factors of plane k for this tile's source region. A slot beyond its pixel's count
-    // (or a pixel outside the image) gets P = 0 and finite dummy factors. REC: the recurrences (every
-    // tile of the wave allows them, the usual case: one branch-free instruction stream); otherwise
-    // every factor from its own exponential.
+    // (or a pixel outside the image) gets P = 0 and finite dummy factors. REC: the recurrences (the
+    // tile allows them, the usual case); otherwise every factor from its own exponential.
     auto factors = [&](int k, auto rec_c) {
         constexpr bool REC = decltype(rec_c)::value;
 #pragma unroll
@@ -327,9 +326,15 @@ __device__ void gather_group(const BufView<S> &v, const TiledParams &p, const Ti
             }
         }
     };
-    const bool rec = __all(xrec && yrec);  // uniform over the wave
+    // The choice is the tile's own, so a tile evaluates the same way whichever tiles share its wave.
+    // When every tile of the wave allows the recurrences (the usual case) one branch-free instruction
+    // stream runs; a wave holding tiles of both kinds runs each form on its own lanes.
+    const bool rec_t = xrec && yrec;
+    const bool rec = __all(rec_t);  // uniform over the wave
     for (int k = 0; k < kmax; ++k) {
         if (rec)
+            factors(k, std::true_type{});
+        else if (TPW > 1 && rec_t)
             factors(k, std::true_type{});
         else
             factors(k, std::false_type{});

@@ -166,6 +166,36 @@ def test_launch_shapes_give_identical_output(w, h, radius):
         assert np.abs(outs[0][0].cpu().numpy() - orgb).max() <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_launch_shapes_identical_with_mixed_widths(precision):
+    """Tiles side by side on both sides of the width bound below which the separable factors are
+    evaluated one exponential each (every other tile column 0.1 px wide in x, every fourth tile
+    column narrow in y): a wave that holds tiles of both kinds evaluates each tile as a wave of its
+    own would, so one, two and four tiles per wave give the same bits, and the output matches the
+    reference on the same statistics."""
+    torch = torch_mod()
+    afr = afr_mod()
+    w, h, k = 72, 40, 6
+    rng = np.random.default_rng(5150)
+    scene = S.DiscScene(w, h, rng, 6, 40.0, speed=0.2, radius=(2.0, 7.0))
+    s = S.uniform_stream(scene, w, h, w * h * 5, 40.0, 40.0, rng)
+    print(f"launch shapes, mixed widths {precision}", flush=True)
+    gbuf, _ = gpu_build(s, w, h, k, precision, 40.0)
+    obuf, _ = O.build_buffer(s, w, h, k, precision, 40.0)
+    gp, op = params(41.0)
+    ost = O.estimate(obuf, op)
+    ost[O.STAT["sx2"]][:, 0::2] = 0.01
+    ost[O.STAT["sy2"]][:, 1::4] = 0.015
+    st = stats_to_gpu(ost)
+    outs = [afr.reconstruct_launch(gbuf, st, gp, tpw) for tpw in (1, 2, 4)]
+    for rgb, aux in outs[1:]:
+        assert torch.equal(rgb, outs[0][0]) and torch.equal(aux, outs[0][1])
+    orgb, _ = O.reconstruct(obuf, stats_f32_as_f64(ost), op)
+    err = np.abs(outs[0][0].cpu().numpy() - orgb).max()
+    print(f"  max |C - C_ref| = {err:.3g}", flush=True)
+    assert err <= 1e-5
+
+
 def test_reference_statistics_round_trip_and_constants():
     """A constant-colour buffer reproduces the constant through the GPU gather (a normalised
     average of equal colours is that colour), and the tiled and plain forms agree to float32
