@@ -38,7 +38,7 @@ constexpr int kChunkThreads = 512;  // two 512-thread scatter workgroups share a
 // Samples per thread (PER) of the count and scatter kernels, chosen per launch (pick_per): a chunk
 // is kChunkThreads * PER samples.
 constexpr int kPerMin = 6, kPerMax = 10;
-constexpr int kWin = 2048;  // records staged in LDS per scatter window (64 KiB: two workgroups per CU)
+constexpr int kWin = 2048;  // records staged in LDS per scatter window (64 KiB, binary16: 48 KiB)
 constexpr int kBinW = 64;                          // bin width, px (a power of two)
 static_assert((kBinW & (kBinW - 1)) == 0, "bin width is a power of two");
 constexpr int kMaxBins = 4096;                     // LDS capacity of the per-chunk bin tables
@@ -272,8 +272,10 @@ __device__ inline unsigned pack_half2(__half lo, __half hi) {
 
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
 // position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
-// destination, is recomputed from its own x, y.
-template <bool MOTION, int kChunkPer>
+// destination, is recomputed from its own x, y. H: binary16 buffer, whose payload is encoded to its
+// four halves as soon as the record is loaded, so the record holds fewer registers and is staged in
+// 24 instead of 32 bytes.
+template <bool MOTION, int kChunkPer, bool H>
 __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
                                                                const int32_t *ot, int nchunks,
                                                                Bucket bucket, int32_t *bad_tab) {
@@ -286,7 +288,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
     // loop reads each array in order
     unsigned long long *skey = reinterpret_cast<unsigned long long *>(scat_sm + ((g.nb + 3) & ~3));
     float2 *sxy = reinterpret_cast<float2 *>(skey + kWin);
-    float4 *spl = reinterpret_cast<float4 *>(sxy + kWin);
+    float4 *spl = reinterpret_cast<float4 *>(sxy + kWin);  // binary32 payload
+    uint2 *sph = reinterpret_cast<uint2 *>(sxy + kWin);    // binary16 payload
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) tab[b] = 0;
     const int chunk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)chunk * kChunk;
@@ -304,6 +307,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
     }
     __syncthreads();
     int bin[kChunkPer], sp[kChunkPer];
+    uint2 hp[H ? kChunkPer : 1];
     int bad = 0;
 #pragma unroll
     for (int j = 0; j < kChunkPer; ++j) {
@@ -314,6 +318,10 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         rec[j].key = ok ? order_key(rec[j].t, (int)i) : 0ull;
         bin[j] = in ? bin_of(rec[j].x, rec[j].y, g) : -1;
         sp[j] = in ? atomicAdd(&tab[bin[j]], 1) : 0;  // rank inside the bin
+        if constexpr (H)
+            hp[j] = make_uint2(pack_half2(Codec<__half>::enc_time(rec[j].t, c.t_ref),
+                                          Codec<__half>::enc(rec[j].r)),
+                               pack_half2(Codec<__half>::enc(rec[j].g), Codec<__half>::enc(rec[j].b)));
     }
     __syncthreads();
     const int nvalid = block_scan_lds<kChunkThreads>(tab, tab, g.nb);  // bin offsets, in place
@@ -332,22 +340,22 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
             if (bin[j] >= 0 && q >= 0 && q < kWin) {
                 skey[q] = rec[j].key;
                 sxy[q] = make_float2(rec[j].x, rec[j].y);
-                spl[q] = make_float4(rec[j].t, rec[j].r, rec[j].g, rec[j].b);
+                if constexpr (H)
+                    sph[q] = hp[j];
+                else
+                    spl[q] = make_float4(rec[j].t, rec[j].r, rec[j].g, rec[j].b);
             }
         }
         __syncthreads();
         const int nw = min(kWin, nvalid - w0);
         for (int q = threadIdx.x; q < nw; q += kChunkThreads) {
             const float2 xy = sxy[q];
-            const float4 e = spl[q];
             const int d = tab[bin_of(xy.x, xy.y, g)] + w0 + q;
             bucket.a[d] = KeyXY{skey[q], xy.x, xy.y};
-            if (c.fp16)
-                bucket.h[d] = make_uint2(
-                    pack_half2(Codec<__half>::enc_time(e.x, c.t_ref), Codec<__half>::enc(e.y)),
-                    pack_half2(Codec<__half>::enc(e.z), Codec<__half>::enc(e.w)));
+            if constexpr (H)
+                bucket.h[d] = sph[q];
             else
-                bucket.b[d] = e;
+                bucket.b[d] = spl[q];
         }
         __syncthreads();
     }
@@ -827,18 +835,27 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     // count and scatter with PER samples per thread, with or without reprojection
     auto chunked = [&](auto per_c, bool count) {
         constexpr int P = decltype(per_c)::value;
-        const size_t shmem = count ? 0 : (size_t)((g.nb + 3) & ~3) * sizeof(int) + kWin * sizeof(Record);
+        const bool H = out.precision == AFR_FP16;
+        const size_t shmem = count ? 0
+                                   : (size_t)((g.nb + 3) & ~3) * sizeof(int) +
+                                         kWin * (H ? sizeof(KeyXY) + sizeof(uint2) : sizeof(Record));
         if (count && s.vx)
             k_bin_count<true, P><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets, (int)nch,
                                                                      ws.bad);
         else if (count)
             k_bin_count<false, P><<<(int)nch, kChunkThreads, 0, st>>>(s, c, g, ws.offsets,
                                                                       (int)nch, ws.bad);
+        else if (s.vx && H)
+            k_bin_scatter<true, P, true><<<(int)nch, kChunkThreads, shmem, st>>>(
+                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
         else if (s.vx)
-            k_bin_scatter<true, P><<<(int)nch, kChunkThreads, shmem, st>>>(
+            k_bin_scatter<true, P, false><<<(int)nch, kChunkThreads, shmem, st>>>(
+                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+        else if (H)
+            k_bin_scatter<false, P, true><<<(int)nch, kChunkThreads, shmem, st>>>(
                 s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
         else
-            k_bin_scatter<false, P><<<(int)nch, kChunkThreads, shmem, st>>>(
+            k_bin_scatter<false, P, false><<<(int)nch, kChunkThreads, shmem, st>>>(
                 s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
     };
     auto launch_chunked = [&](bool count) {

@@ -13,8 +13,10 @@ __global__ __launch_bounds__(TB <= 8 ? 64 : 256) void k_estimate(BufView<S> v, e
     est::estimate_tile<S, TB>(v, p, tg, xcd_remap(blockIdx.x, gridDim.x), stats, sm, nullptr);
 }
 
+// Five waves per SIMD (at most 96 VGPRs): a 640 x 480 image's 1200 strips are then all resident at
+// once; two slot planes per load chunk keep the moments within that budget.
 template <typename S>
-__global__ __launch_bounds__(est::kStripThreads) void k_estimate_strip(BufView<S> v,
+__global__ __launch_bounds__(est::kStripThreads, 5) void k_estimate_strip(BufView<S> v,
                                                                         est::EstParams p,
                                                                         TileGeom tg, int sx,
                                                                         float *stats) {

@@ -382,7 +382,7 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
 
 constexpr int kStripThreads = 256;
 constexpr int kStripW = 32;                                  // pixels
-constexpr int kStripRegion = (kStripW + 2) * (8 + 2);        // region pixels, at most 660
+constexpr int kStripRegion = (kStripW + 2) * (8 + 2);        // region pixels, at most 340
 constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
 
 struct StripSmem {
@@ -405,7 +405,7 @@ __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const Ti
     const int i0 = tx0 * B, j0 = ty * B;
     const int sw = min(ntile * B, v.width - i0), sh = min(B, v.height - j0);
     const int rp = sw + 2;
-    region_moments<S, kStripItems, 4>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
+    region_moments<S, kStripItems, 2>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int t = wid; t < ntile; t += kStripThreads / kWave) {
