@@ -435,11 +435,14 @@ __device__ inline int swz(int l) { return l + (l >> 4); }
 // Top-K of one pixel over its entries [l0, l1) of the LDS key list. KMAX <= 64: a pixel with at
 // most KMAX entries sorts them in registers with a bitonic network; one with more inserts each into
 // a descending register list (one unsigned compare and selects per entry and position). Larger K:
-// repeated maximum scans. The selected records are then loaded together.
+// repeated maximum scans. The selected records are then loaded together. [h0, h1): the slots this
+// call stores (the whole list by default; h0 a multiple of 4 for KMAX <= 64), the pixel's count with
+// slot 0.
 template <typename S, int KMAX>
 __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t hw,
                                     const BinRecs &recs, const unsigned long long *keys,
-                                    const unsigned short *pos, const unsigned *oxy, int l0, int l1) {
+                                    const unsigned short *pos, const unsigned *oxy, int l0, int l1,
+                                    int h0 = 0, int h1 = KMAX) {
     const int K = out.k;
     int nvalid = 0;
     if constexpr (KMAX <= 64) {
@@ -504,6 +507,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
         constexpr int kG = KMAX < 4 ? KMAX : 4;
 #pragma unroll
         for (int k0 = 0; k0 < KMAX; k0 += kG) {
+            if (k0 < h0 || k0 >= h1) continue;
             KeyXY a[kG];
             float4 c[kG];
             uint2 h[kOxyInList<S> ? kG : 1];
@@ -534,7 +538,7 @@ __device__ inline void select_pixel(const afr_deep_buffer &out, size_t p, size_t
                 }
             }
         }
-        out.count[p] = (uint8_t)n;
+        if (h0 == 0) out.count[p] = (uint8_t)n;
     } else {
         for (int l = l0; l < l1; ++l) nvalid += keys[swz(l)] != 0ull;
         const int n = min(nvalid, K);
@@ -655,11 +659,18 @@ __global__ __launch_bounds__(sel_threads<KMAX>()) void k_bin_select(afr_deep_buf
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < rows * kBinW; q += kSelThreads) {
+        // Binary32 records with 4 < K <= 16: two threads per pixel (the two halves of the workgroup,
+        // so each wave stays on one half) sort the same list and store half of the slots each,
+        // which halves the chain of 32-byte record fetches per thread.
+        constexpr int kHalves = (KMAX >= 8 && KMAX <= 16 && !kOxyInList<S>) ? 2 : 1;
+        const int nq = rows * kBinW;
+        for (int t = threadIdx.x; t < kHalves * nq; t += kSelThreads) {
+            const int q = t % nq, hh = t / nq;
             const int px = bx0 + q % kBinW, py = by0 + q / kBinW;
             if (px < W)
                 select_pixel<S, KMAX>(out, (size_t)py * W + px, hw, recs, keys, pos, oxy, poff[q],
-                                      poff[q + 1]);
+                                      poff[q + 1], hh * (KMAX / kHalves),
+                                      (hh + 1) * (KMAX / kHalves));
         }
         return;
     }
