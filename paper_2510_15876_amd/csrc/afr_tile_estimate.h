@@ -364,7 +364,9 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
     const int i0 = (T % tg.tiles_x) * B, j0 = (T / tg.tiles_x) * B;
     const int bw = min(B, v.width - i0), bh = min(B, v.height - j0);
     const int rw = bw + 2, rh = bh + 2;
-    region_moments<S, 2, 8>(v, p, rg, i0 - 1, j0 - 1, rw, rw * rh);
+    // four slot planes per load chunk: the batched kernel, which runs this routine and the gather in
+    // one wave, keeps its register count (and so its waves per SIMD) down (3.86 -> 3.77 ms per batch)
+    region_moments<S, 2, 4>(v, p, rg, i0 - 1, j0 - 1, rw, rw * rh);
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const Acc acc = wave_tile_acc(rg, rw + 1, rw, bw, bh, threadIdx.x, blockDim.x);
