@@ -52,6 +52,8 @@ def _args():
     ap.add_argument("--two-stream-frames", type=int, default=None,
                     help="frames of the two-stream leg (default 2 x steps; 0 skips it, as profiled "
                          "runs do, since its kernels overlap and would skew per-kernel averages)")
+    ap.add_argument("--graph-steps", type=int, default=1,
+                    help="also time the steps replayed from a captured graph (0 skips it)")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
@@ -373,6 +375,40 @@ def main():
         two_streams = {"ms_per_frame": round(two_stream_ms, 5),
                        "mpixel_per_s": round(W * H / (two_stream_ms * 1e-3) / 1e6, 3)}
 
+    # the same steps replayed from one captured graph of ROTATE steps (one per input copy): the
+    # launches of a frame loop that keeps its buffers, without the host issuing each kernel
+    graph_steps = None
+    if args.graph_steps:
+        gs = torch.cuda.Stream(device=dev)
+        gs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(gs):
+            for r in range(ROTATE):  # this stream's workspaces are allocated outside the capture
+                step(r)
+        torch.cuda.current_stream().wait_stream(gs)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            for r in range(ROTATE):
+                step(r)
+        reps = max(1, args.steps // ROTATE)
+        ge = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        graph.replay()
+        torch.cuda.synchronize()
+        ge[0].record()
+        for _ in range(reps):
+            graph.replay()
+        ge[1].record()
+        torch.cuda.synchronize()
+        g_ms = ge[0].elapsed_time(ge[1]) / (reps * ROTATE)
+        replayed = rgbs[0].clone()
+        step(0)  # eager, on the current stream
+        torch.cuda.synchronize()
+        graph_steps = {"ms_per_step": round(g_ms, 5),
+                       "mpixel_per_s": round(W * H / (g_ms * 1e-3) / 1e6, 3),
+                       "steps_per_graph": ROTATE, "replays": reps,
+                       "replay_equals_eager": bool(torch.equal(replayed, rgbs[0]))}
+        del graph
+
     # plain direct gather on the same buffers, for the plain-vs-tiled comparison
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     n_plain = max(5, args.steps // 5)
@@ -454,6 +490,7 @@ def main():
         "samples_filtered_per_s": round(occupied / (fwd_ms * 1e-3), 1),
         "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
         "two_streams": two_streams,
+        "graph_steps": graph_steps,
         "plain_reconstruct_ms": round(plain_ms, 5),
         "gather_r1": gather_r1,
         "scatter_reconstruct_ms": scatter_ms,
