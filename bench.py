@@ -60,6 +60,11 @@ def _args():
                     help="print a text summary of a rocprofv3 --stats kernel table and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="print per-kernel averages of every counter in these rocprofv3 --pmc "
+                         "counter_collection.csv files (one pass each) and exit; the command that "
+                         "made them goes in --summary-command")
+    ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
     return ap.parse_args()
 
 
@@ -118,6 +123,55 @@ def pmc_summary(fetch_csv, write_csv, command, copy_kib=262144):
     return "\n".join(out)
 
 
+def counter_summary(csvs, command, radius=2):
+    """Per-kernel averages (per dispatch) of every SQ/TCC counter found in the given rocprofv3
+    counter-collection CSVs, and for the gather kernels the per-pair and per-cycle ratios the design
+    notes quote: VALU wave-instructions per (slot, pixel) pair-wave (a pair-wave is 64 pairs), LDS
+    instructions per pair-wave, bank-conflict share of LDS-active cycles and the share of wave
+    cycles spent waiting for an instruction to issue. Pairs come from the 640x480 K=16 workload."""
+    import csv
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            vals[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    import afr_scenes as S
+    wl = S.make_workload("c3")
+    x, y = wl.stream.arrays()[:2]
+    W, H, K = wl.width, wl.height, wl.k
+    inside = (x >= 0) & (x < W) & (y >= 0) & (y < H)
+    cnt = np.bincount((np.floor(y[inside]).astype(np.int64) * W + np.floor(x[inside]).astype(np.int64)),
+                      minlength=W * H)
+    count = np.minimum(cnt, K).reshape(H, W)
+    pairs = {r: gather_pairs(count, r) for r in (1, 2)}
+    out = ["# rocprofv3 counters per dispatch (average over dispatches), 640x480 K=16 FP16 workload",
+           "# command (one rocprofv3 --pmc pass per counter group): " + command,
+           "# (slot, pixel) pairs of the gather: R=1 %d, R=2 %d" % (pairs[1], pairs[2]),
+           "# kernel | counter | mean per dispatch | dispatches"]
+    for k in sorted(vals):
+        if not k.startswith("k_"):
+            continue
+        for c in sorted(vals[k]):
+            v = vals[k][c]
+            out.append("%-40s %-24s %16.1f %5d" % (k, c, float(np.mean(v)), len(v)))
+        d = {c: float(np.mean(v)) for c, v in vals[k].items()}
+        if "gather" in k or "reconstruct_tiled" in k:
+            import re
+            m = re.search(r"<[^,]+,(\d)", k)
+            r = int(m.group(1)) if m else radius
+            pw = pairs.get(r, pairs[2]) / 64.0
+            if "SQ_INSTS_VALU" in d:
+                out.append("%-40s %-24s %16.3f" % (k, "=VALU_per_pair_wave", d["SQ_INSTS_VALU"] / pw))
+            if "SQ_INSTS_LDS" in d:
+                out.append("%-40s %-24s %16.3f" % (k, "=LDS_per_pair_wave", d["SQ_INSTS_LDS"] / pw))
+        if "SQ_WAIT_INST_ANY" in d and d.get("SQ_WAVE_CYCLES"):
+            out.append("%-40s %-24s %16.3f" % (k, "=wait_inst_share", d["SQ_WAIT_INST_ANY"] / d["SQ_WAVE_CYCLES"]))
+        if "SQ_LDS_BANK_CONFLICT" in d and d.get("SQ_LDS_IDX_ACTIVE"):
+            out.append("%-40s %-24s %16.3f" % (k, "=bank_conflict_share",
+                                               d["SQ_LDS_BANK_CONFLICT"] / d["SQ_LDS_IDX_ACTIVE"]))
+    return "\n".join(out)
+
+
 STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gather")
 
 
@@ -130,7 +184,7 @@ def kernel_of(stage, k, radius, tpw):
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),
             "estimate": "k_estimate_strip<__half>",
-            "gather": "k_reconstruct_tiled<__half,%d,%d>" % (radius, tpw)}[stage]
+            "gather": "k_gather<__half,%d,%d>" % (radius, tpw)}[stage]
 SINGLE_KERNEL = ("bin_scatter", "bin_select", "estimate", "gather")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_k16_fp16.txt")
 
@@ -252,6 +306,9 @@ def main():
         return
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary))
+        return
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary, args.summary_command, args.radius))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU layout "

@@ -53,7 +53,7 @@ typedef enum afr_precision {
     AFR_FP32 = 0,           /* ox, oy, t, r, g, b stored as float; tage holds the time t        */
     AFR_FP16 = 1            /* stored as IEEE binary16 (round to nearest even); tage holds the   */
                             /* age relative to t_ref, age_ref = t_ref - t, so recent samples get */
-                            /* the finest quantisation                                           */
+                            /* the finest quantisation; slots are 12-byte records (see below)    */
 } afr_precision;
 
 /* A stream of samples (Sec. 4.2: the sampler streams every sample to the reconstructor). Device
@@ -75,13 +75,22 @@ typedef struct afr_samples {
 /* Per-pixel deep buffer (Sec. 4): pixel p keeps count[p] <= K slots, newest first. For every filled
  * slot: ox = x - floor(x), oy = y - floor(y) in [0, 1], tage (see afr_precision) and the colour.
  * Empty slots hold zeros. src (optional, may be NULL) receives the stream index of each slot or -1;
- * it maps slot gradients back to stream samples. */
+ * it maps slot gradients back to stream samples.
+ *
+ * Slot s = k H W + y W + x (slot plane k of pixel (x, y)) is stored
+ *   AFR_FP32: in six planes, field f of slot s at ((float *)f)[s];
+ *   AFR_FP16: as a 12-byte record of six binary16 values in the order (ox, oy, r, g, b, age_ref),
+ *             records [K][H][W] one after another starting at ox (4-byte aligned); the six field
+ *             pointers address the first record's fields, so oy = ox + 1, r = ox + 2, g = ox + 3,
+ *             b = ox + 4, tage = ox + 5 as binary16 pointers, and field f of slot s is at
+ *             ((binary16 *)f)[6 s]. One 12-byte load fetches a whole slot; any other
+ *             arrangement of the six pointers is AFR_E_INVALID. */
 typedef struct afr_deep_buffer {
     int32_t width, height;  /* pixels, >= 1                                                     */
     int32_t k;              /* slots per pixel, 1..255                                           */
     int32_t precision;      /* afr_precision                                                     */
     float t_ref;            /* stream reference time: samples with t > t_ref are dropped         */
-    void *ox, *oy, *tage, *r, *g, *b; /* [K][H][W] of float (AFR_FP32) or binary16 (AFR_FP16)    */
+    void *ox, *oy, *tage, *r, *g, *b; /* fields, laid out as above                               */
     uint8_t *count;         /* [H][W]                                                            */
     int32_t *src;           /* [K][H][W] or NULL                                                 */
 } afr_deep_buffer;
@@ -372,11 +381,20 @@ afr_status afr_reconstruct_plain(const afr_deep_buffer *buf, const afr_tile_stat
                                  const afr_params *params, float *rgb, float *aux,
                                  hipStream_t stream);
 
+/* Statistics and gather in one launch: the same result as afr_estimate_gradients (into stats)
+ * followed by afr_reconstruct, bit for bit, with the deep buffer read by one kernel per group of
+ * tiles that first reduces the group's statistics and then gathers it (8 px tiles; other tile sizes
+ * run the two steps one after the other).
+ *   stats  receives every statistic plane (overwritten), as afr_estimate_gradients
+ *   rgb    [3][H][W] float output;  aux  [2][H][W] float output or NULL */
+afr_status afr_forward(const afr_deep_buffer *buf, const afr_params *params, afr_tile_stats *stats,
+                       float *rgb, float *aux, hipStream_t stream);
+
 /* afr_reconstruct with an explicit launch shape: tiles_per_wave (1, 2 or 4; 0 = the library's choice)
- * statistics tiles are processed side by side by one 64-lane wave. The shape changes only how work is
- * spread over lanes: every pixel sums the same terms in the same order, so all shapes give bit-identical
- * output. Used by the tuner; shapes the kernel does not support for the given radius fall back to a
- * supported one. */
+ * statistics tiles side by side are processed by one workgroup, one 64-lane wave per tile (R >= 3
+ * allows at most 2). The shape changes only how work is spread over waves: every pixel sums the same
+ * terms in the same order, so all shapes give bit-identical output. Used by the tuner; shapes the
+ * kernel does not support for the given radius fall back to a supported one. */
 afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_stats *stats,
                                   const afr_params *params, int32_t tiles_per_wave, float *rgb,
                                   float *aux, hipStream_t stream);

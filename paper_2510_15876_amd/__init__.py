@@ -19,7 +19,8 @@ import torch
 
 __all__ = [
     "AfrError", "Params", "DeepBuffer", "STAT_NAMES", "NSTAT", "STAT", "library", "lib_path",
-    "build_deep_buffer", "estimate_gradients", "reconstruct", "reconstruct_plain", "reconstruct_launch",
+    "build_deep_buffer", "estimate_gradients", "forward", "reconstruct", "reconstruct_plain",
+    "reconstruct_launch",
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
     "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
     "SplatParams", "splat_sizes", "reconstruct_scatter", "SamplerParams", "sampler_stats",
@@ -164,6 +165,8 @@ def library():
     lib.afr_reconstruct_launch.restype = st
     lib.afr_reconstruct_launch.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), ctypes.c_int32,
                                            vp, vp, vp]
+    lib.afr_forward.restype = st
+    lib.afr_forward.argtypes = [P(_DeepBuffer), P(_Params), P(_TileStats), vp, vp, vp]
     lib.afr_backward_workspace_bytes.restype = ctypes.c_size_t
     lib.afr_backward_workspace_bytes.argtypes = [ctypes.c_int32] * 4
     lib.afr_reconstruct_backward.restype = st
@@ -267,11 +270,15 @@ def tiles_shape(width: int, height: int, tile: int):
 
 
 class DeepBuffer:
-    """Per-pixel deep buffer in device memory: ``planes[6, K, H, W]`` (ox, oy, tage, r, g, b; plane k
-    holds every pixel's k-th newest sample), ``count[H, W]`` (uint8), ``src[K, H, W]`` (int32 stream
-    index, -1 when empty)."""
+    """Per-pixel deep buffer in device memory (plane k holds every pixel's k-th newest sample),
+    ``count[H, W]`` (uint8) and ``src[K, H, W]`` (int32 stream index, -1 when empty).
+
+    ``planes`` is ``[6, K, H, W]`` float32 (ox, oy, tage, r, g, b) for FP32 storage, and for FP16
+    storage ``[K, H, W, 6]`` binary16 slot records in the order (ox, oy, r, g, b, tage), the layout
+    of afr.h. ``field(name)`` returns a ``[K, H, W]`` view of one field either way."""
 
     FIELDS = ("ox", "oy", "tage", "r", "g", "b")
+    RECORD = ("ox", "oy", "r", "g", "b", "tage")  # binary16 slot record order
 
     def __init__(self, width: int, height: int, k: int, precision: str = "fp32",
                  t_ref: float = 0.0, device="cuda", with_src: bool = True):
@@ -280,16 +287,25 @@ class DeepBuffer:
         self.width, self.height, self.k = int(width), int(height), int(k)
         self.precision = precision
         self.t_ref = float(t_ref)
-        dt = torch.float16 if precision == "fp16" else torch.float32
-        self.planes = torch.empty((6, self.k, self.height, self.width), dtype=dt, device=device)
+        if precision == "fp16":
+            self.planes = torch.empty((self.k, self.height, self.width, 6), dtype=torch.float16,
+                                      device=device)
+        else:
+            self.planes = torch.empty((6, self.k, self.height, self.width), dtype=torch.float32,
+                                      device=device)
         self.count = torch.empty((self.height, self.width), dtype=torch.uint8, device=device)
         self.src = (torch.empty((self.k, self.height, self.width), dtype=torch.int32, device=device)
                     if with_src else None)
 
     def field(self, name: str) -> torch.Tensor:
+        if self.precision == "fp16":
+            return self.planes[..., self.RECORD.index(name)]
         return self.planes[self.FIELDS.index(name)]
 
     def colours(self) -> torch.Tensor:
+        """The colour fields as ``[3, K, H, W]`` (a view; not contiguous for FP16 records)."""
+        if self.precision == "fp16":
+            return self.planes[..., 2:5].permute(3, 0, 1, 2)
         return self.planes[3:6]
 
     def clone(self) -> "DeepBuffer":
@@ -303,6 +319,14 @@ class DeepBuffer:
 
     def _c(self, colours: Optional[torch.Tensor] = None) -> _DeepBuffer:
         p = self.planes
+        src = None if self.src is None else _ptr(self.src).value
+        if self.precision == "fp16":
+            if colours is not None:
+                raise AfrError("replacement colours need an FP32 buffer (FP16 slots are records)")
+            b = p.data_ptr()  # record fields 2 bytes apart: ox, oy, r, g, b, tage
+            return _DeepBuffer(self.width, self.height, self.k, PRECISIONS[self.precision],
+                               self.t_ref, b, b + 2, b + 10, b + 4, b + 6, b + 8,
+                               _ptr(self.count).value, src)
         c = p[3:6] if colours is None else colours
         if colours is not None and (colours.dtype != p.dtype or tuple(colours.shape) != tuple(p[3:6].shape)):
             raise AfrError("replacement colours must match the buffer's colour planes")
@@ -312,8 +336,7 @@ class DeepBuffer:
         step = c[0].numel() * c.element_size()
         return _DeepBuffer(self.width, self.height, self.k, PRECISIONS[self.precision],
                            self.t_ref, p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr(),
-                           base, base + step, base + 2 * step, _ptr(self.count).value,
-                           None if self.src is None else _ptr(self.src).value)
+                           base, base + step, base + 2 * step, _ptr(self.count).value, src)
 
 
 def _stats_c(stats: torch.Tensor, tile: int) -> _TileStats:
@@ -622,6 +645,25 @@ def reconstruct(buf: DeepBuffer, stats: torch.Tensor, params: Params, rgb=None, 
     return _reconstruct("afr_reconstruct", buf, stats, params, rgb, aux, want_aux, stream, colours)
 
 
+def forward(buf: DeepBuffer, params: Params, stats: Optional[torch.Tensor] = None, rgb=None,
+            aux=None, want_aux: bool = True, stream=None):
+    """Statistics and gather in one launch (afr_forward): ``(stats, rgb, aux or None)``, equal bit
+    for bit to ``estimate_gradients`` followed by ``reconstruct``."""
+    lib = library()
+    dev = buf.planes.device
+    ty, tx = tiles_shape(buf.width, buf.height, params.tile)
+    if stats is None:
+        stats = torch.empty((NSTAT, ty, tx), dtype=torch.float32, device=dev)
+    if rgb is None:
+        rgb = torch.empty((3, buf.height, buf.width), dtype=torch.float32, device=dev)
+    if aux is None and want_aux:
+        aux = torch.empty((2, buf.height, buf.width), dtype=torch.float32, device=dev)
+    bc, pc, sc = buf._c(), params._c(), _stats_c(stats, params.tile)
+    _check(lib.afr_forward(ctypes.byref(bc), ctypes.byref(pc), ctypes.byref(sc), _ptr(rgb),
+                           _ptr(aux), _stream(stream)), "afr_forward")
+    return stats, rgb, aux
+
+
 def reconstruct_launch(buf: DeepBuffer, stats: torch.Tensor, params: Params, tiles_per_wave: int,
                        rgb=None, aux=None, want_aux: bool = True, stream=None, colours=None):
     """LDS-tiled gather with an explicit launch shape (bit-identical output for every shape)."""
@@ -738,39 +780,44 @@ def reconstruct_backward(buf: DeepBuffer, stats: torch.Tensor, params: Params, r
 
 
 class ReconstructFn(torch.autograd.Function):
-    """Differentiable estimate + gather.
+    """Differentiable gather.
 
-    Inputs: slot colours ``[3, K, H, W]`` (the buffer's colour planes or a replacement of the same
-    dtype), ``sigma`` and ``tau`` (0-d float tensors). Tile statistics are recomputed from the buffer
-    at the given sigma and tau and treated as constants (stop-gradient) in the adjoint, matching
-    ``afr_reconstruct_backward``. Gradients flow to the colours and to sigma and tau.
+    Inputs: slot colours ``[3, K, H, W]`` (a replacement for the colours of an FP32 buffer, or, with
+    ``own`` set, the buffer's own colours, which are then read from the buffer), ``sigma`` and
+    ``tau`` (0-d float tensors). The tile statistics are estimated from the buffer's stored samples
+    at the given sigma and tau and are constants of the gather (stop-gradient), as in
+    ``afr_reconstruct_backward``: the forward is exactly the gather the adjoint differentiates, and
+    gradients flow to the colours and to sigma and tau.
     """
 
     @staticmethod
-    def forward(ctx, colours, sigma, tau, buf: DeepBuffer, params: Params, form: str = "tiled"):
+    def forward(ctx, colours, sigma, tau, buf: DeepBuffer, params: Params, form: str = "tiled",
+                own: bool = False):
         p = params.with_(sigma=float(sigma), tau=float(tau))
-        colours = colours.detach().contiguous()
-        stats = estimate_gradients(buf, p, colours=colours)
+        ctx.colour_dtype = colours.dtype
+        colours = None if own else colours.detach().contiguous()
+        stats = estimate_gradients(buf, p)
         fn = reconstruct if form == "tiled" else reconstruct_plain
         rgb, aux = fn(buf, stats, p, colours=colours)
-        ctx.save_for_backward(colours, rgb, aux, stats)
-        ctx.buf, ctx.params = buf, p
-        ctx.colour_dtype = colours.dtype
+        ctx.save_for_backward(rgb, aux, stats, *(() if colours is None else (colours,)))
+        ctx.buf, ctx.params, ctx.own = buf, p, own
         return rgb
 
     @staticmethod
     def backward(ctx, grad_rgb):
-        colours, rgb, aux, stats = ctx.saved_tensors
+        rgb, aux, stats = ctx.saved_tensors[:3]
+        colours = None if ctx.own else ctx.saved_tensors[3]
         gslot, gpar = reconstruct_backward(ctx.buf, stats, ctx.params, rgb, aux, grad_rgb,
                                            colours=colours)
         gc = gslot.to(ctx.colour_dtype) if ctx.needs_input_grad[0] else None
         gs = gpar[0] if ctx.needs_input_grad[1] else None
         gt = gpar[1] if ctx.needs_input_grad[2] else None
-        return gc, gs, gt, None, None, None
+        return gc, gs, gt, None, None, None, None
 
 
 def reconstruct_differentiable(buf: DeepBuffer, params: Params, sigma, tau, colours=None,
                                form: str = "tiled"):
-    """``rgb = ReconstructFn(colours, sigma, tau)``; colours default to the buffer's own planes."""
-    c = buf.colours() if colours is None else colours
-    return ReconstructFn.apply(c, sigma, tau, buf, params, form)
+    """``rgb = ReconstructFn(colours, sigma, tau)``; colours default to the buffer's own."""
+    if colours is None:
+        return ReconstructFn.apply(buf.colours(), sigma, tau, buf, params, form, True)
+    return ReconstructFn.apply(colours, sigma, tau, buf, params, form, False)

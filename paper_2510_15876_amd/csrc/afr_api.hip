@@ -214,8 +214,21 @@ afr_status afr_reconstruct(const afr_deep_buffer *buf, const afr_tile_stats *sta
     AFR_TRY(check_stats(stats, buf, params));
     if (!rgb) return AFR_E_INVALID;
     const int tuned = tuned_tiles_per_wave(*buf, params->radius);
-    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, tuned ? tuned : 2, rgb, aux,
-                                             stream));
+    return from_hip(launch_reconstruct_tiled(*buf, *stats, *params,
+                                             tuned ? tuned : default_tiles_per_group(params->radius),
+                                             rgb, aux, stream));
+}
+
+afr_status afr_forward(const afr_deep_buffer *buf, const afr_params *params, afr_tile_stats *stats,
+                       float *rgb, float *aux, hipStream_t stream) {
+    AFR_TRY(check_buffer(buf));
+    AFR_TRY(check_params(params, buf));
+    AFR_TRY(check_stats(stats, buf, params));
+    if (!rgb) return AFR_E_INVALID;
+    const int tuned = tuned_tiles_per_wave(*buf, params->radius);
+    return from_hip(launch_forward(*buf, *params, *stats,
+                                   tuned ? tuned : default_tiles_per_group(params->radius), rgb, aux,
+                                   stream));
 }
 
 afr_status afr_reconstruct_tune(const afr_deep_buffer *buf, const afr_tile_stats *stats,
@@ -236,7 +249,7 @@ afr_status afr_reconstruct_tune(const afr_deep_buffer *buf, const afr_tile_stats
     afr_status st = AFR_OK;
     const int shapes[3] = {1, 2, 4};
     for (int s = 0; s < 3 && st == AFR_OK; ++s) {
-        if (shapes[s] == 4 && params->radius > 3) continue;
+        if (shapes[s] > default_tiles_per_group(params->radius)) continue;
         constexpr int kReps = 5;
         st = from_hip(launch_reconstruct_tiled(*buf, *stats, *params, shapes[s], rgb, nullptr, stream));
         if (st == AFR_OK && hipEventRecord(e0, stream) != hipSuccess) st = AFR_E_DEVICE;
@@ -271,7 +284,9 @@ afr_status afr_reconstruct_launch(const afr_deep_buffer *buf, const afr_tile_sta
     if (!rgb) return AFR_E_INVALID;
     if (tiles_per_wave < 0 || tiles_per_wave > 4) return AFR_E_RANGE;
     const int tuned = tuned_tiles_per_wave(*buf, params->radius);
-    const int tpw = tiles_per_wave == 0 ? (tuned ? tuned : 2) : tiles_per_wave;
+    const int tpw = tiles_per_wave == 0
+                        ? (tuned ? tuned : default_tiles_per_group(params->radius))
+                        : tiles_per_wave;
     return from_hip(launch_reconstruct_tiled(*buf, *stats, *params, tpw, rgb, aux, stream));
 }
 

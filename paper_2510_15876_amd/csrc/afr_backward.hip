@@ -9,7 +9,7 @@
 // atomics: every sum runs in a fixed order.
 //
 // Tiled form (8 px statistics tiles, the layout of the tiled gather). The weight of slot s for pixel
-// p of tile T factors as X_T(s, m) Y_T(s, n) Tm_T(s) (see afr_tile_gather.h), and with
+// p of tile T factors as X_T(s, m) Y_T(s, n) Tm_T(s) (see afr_gather.h), and with
 //   s_p = exp(shift_T - m_p) / W_p,  g'_p = g(p, .) s_p,  k'_p = (g(p, .) . C_p) s_p
 // the two sums become, per pair, w = X Y Tm:
 //   colour gradient of s += w g'_p,    parameter terms += w (g'_p . c_s - k'_p) dE/dtheta,
@@ -112,14 +112,14 @@ __global__ __launch_bounds__(kBX *kBY) void k_bwd_pixel(BufView<S> v, BwdParams 
                     const float bx = (float)(qx - i) - 0.5f, by = (float)(qy - j) - 0.5f;
                     for (int k = 0; k < n; ++k) {
                         const size_t s = (size_t)k * hw + q;
-                        const float dx = bx + Codec<S>::dec(v.ox[s]);
-                        const float dy = by + Codec<S>::dec(v.oy[s]);
-                        const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                        const float dx = bx + Codec<S>::dec(fld(v.ox, s));
+                        const float dy = by + Codec<S>::dec(fld(v.oy, s));
+                        const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                         const float e = -(dx * dx * c.cx + dy * dy * c.cy + a * a * c.ct);
                         const float pi = expf(e - m) * inv;
-                        const float h = g0 * (Codec<S>::dec(v.r[s]) - C0) +
-                                        g1 * (Codec<S>::dec(v.g[s]) - C1) +
-                                        g2 * (Codec<S>::dec(v.b[s]) - C2);
+                        const float h = g0 * (Codec<S>::dec(fld(v.r, s)) - C0) +
+                                        g1 * (Codec<S>::dec(fld(v.g, s)) - C1) +
+                                        g2 * (Codec<S>::dec(fld(v.b, s)) - C2);
                         const float ph = pi * h;
                         ax += ph * dx * dx;
                         ay += ph * dy * dy;
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(kBX *kBY) void k_bwd_sample(BufView<S> v, BwdParams
         const size_t s = (size_t)k * hw + q;
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
         if (k < n) {
-            const float ox = Codec<S>::dec(v.ox[s]), oy = Codec<S>::dec(v.oy[s]);
-            const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+            const float ox = Codec<S>::dec(fld(v.ox, s)), oy = Codec<S>::dec(fld(v.oy, s));
+            const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
             for (int py = py0; py <= py1; ++py)
                 for (int px = px0; px <= px1; ++px) {
                     const size_t pp = (size_t)py * W + px;
@@ -295,14 +295,14 @@ __device__ inline void direct_param_terms(const BufView<S> &v, const BwdParams &
             const float bx = (float)(qx - i) - 0.5f, by = (float)(qy - j) - 0.5f;
             for (int k = 0; k < n; ++k) {
                 const size_t s = (size_t)k * hw + q;
-                const float dx = bx + Codec<S>::dec(v.ox[s]);
-                const float dy = by + Codec<S>::dec(v.oy[s]);
-                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float dx = bx + Codec<S>::dec(fld(v.ox, s));
+                const float dy = by + Codec<S>::dec(fld(v.oy, s));
+                const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                 const float e = -(dx * dx * c.cx + dy * dy * c.cy + a * a * c.ct);
                 const float pi = expf(e - m) * inv;
-                const float h = g0 * (Codec<S>::dec(v.r[s]) - C0) +
-                                g1 * (Codec<S>::dec(v.g[s]) - C1) +
-                                g2 * (Codec<S>::dec(v.b[s]) - C2);
+                const float h = g0 * (Codec<S>::dec(fld(v.r, s)) - C0) +
+                                g1 * (Codec<S>::dec(fld(v.g, s)) - C1) +
+                                g2 * (Codec<S>::dec(fld(v.b, s)) - C2);
                 const double ph = (double)(pi * h);
                 ax += ph * (double)(dx * dx);
                 ay += ph * (double)(dy * dy);
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_prep(BufView<S> v, BwdParams p, T
         const int qx = tx * kTB - R + pix % G::RW, qy = ty * kTB - R + pix / G::RW;
         if (pix < G::NP && qx >= 0 && qx < W && qy >= 0 && qy < H) {
             const size_t q = (size_t)qy * W + qx;
-            if (v.count[q] > 0) amin = fminf(amin, Codec<S>::age(v.ta[q], p.t_now, p.dt_ref));
+            if (v.count[q] > 0) amin = fminf(amin, Codec<S>::age(fld(v.ta, q), p.t_now, p.dt_ref));
         }
     }
     amin = wave_min_f(amin);
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     const int qx = tx * kTB - R + cc, qy = ty * kTB - R + rr_;
     const bool in = pix < NP && qx >= 0 && qx < W && qy >= 0 && qy < H;
     const unsigned q = in ? (unsigned)(qy * W + qx) : 0u;
-    const unsigned ioff = q * (unsigned)sizeof(S);
+    const unsigned ioff = q * (unsigned)(sizeof(S) * Slots<S>::kStride);
     const int icnt = in ? v.count[q] : 0;
     int kmax = icnt;
 #pragma unroll
@@ -435,7 +435,10 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     __syncthreads();  // s_gk visible
     S rox, roy, rta, rr, rg, rb;
     auto load_plane = [&](int k) {
-        const size_t base = (size_t)k * hw, bytes = hw * sizeof(S);
+        // a binary16 slot is a 12-byte record: each field's descriptor starts at its field of the
+        // plane's first record and steps by the record size
+        const size_t base = (size_t)k * hw * Slots<S>::kStride;
+        const size_t bytes = hw * sizeof(S) * Slots<S>::kStride;
         rox = plane_load<S>(plane_rsrc(v.ox + base, bytes), ioff);
         roy = plane_load<S>(plane_rsrc(v.oy + base, bytes), ioff);
         rta = plane_load<S>(plane_rsrc(v.ta + base, bytes), ioff);
@@ -586,8 +589,8 @@ __global__ __launch_bounds__(kBX *kBY) void k_bwd_slots(BufView<S> v, BwdParams 
                 s2 += pt[2 * NP];
             }
             if (anyflag) {  // exact terms from pixels evaluated directly
-                const float ox = Codec<S>::dec(v.ox[s]), oy = Codec<S>::dec(v.oy[s]);
-                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float ox = Codec<S>::dec(fld(v.ox, s)), oy = Codec<S>::dec(fld(v.oy, s));
+                const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                 for (int py = max(0, qy - R); py <= min(H - 1, qy + R); ++py)
                     for (int px = max(0, qx - R); px <= min(W - 1, qx + R); ++px) {
                         const size_t pp = (size_t)py * W + px;

@@ -1,8 +1,8 @@
 // Batched reconstruction in one persistent launch, and the launch-shape tuner.
 //
-// A work item is (batch item, group of TPW statistics tiles in one tile row). The workgroup that
-// takes it first evaluates the statistics of its own tiles (est::estimate_tile, the code of
-// afr_estimate_gradients) and then gathers them (gat::gather_group, the code of afr_reconstruct), so
+// A work item is (batch item, group of TPG statistics tiles in one tile row). The workgroup that
+// takes it first evaluates the statistics of its own tiles (est::estimate_strip, the code of
+// afr_estimate_gradients) and then gathers them (gat::gather_strip, the code of afr_reconstruct), so
 // no work item depends on another and nothing spins. The grid is sized to the number of resident
 // workgroups; each workgroup loops taking the next item from a counter until the counter passes
 // the last item, which every wave reaches. A one-thread kernel resets the counter before each run,
@@ -14,8 +14,8 @@
 #include <tuple>
 #include <vector>
 
+#include "afr_gather.h"
 #include "afr_tile_estimate.h"
-#include "afr_tile_gather.h"
 
 namespace afr {
 namespace {
@@ -52,16 +52,16 @@ __device__ inline BufView<S> item_view(const DevItem &d) {
 
 __global__ void k_batch_reset(int *counter) { *counter = 0; }
 
-template <typename S, int R, int TPW>
-__global__ __launch_bounds__(kWave) void k_batch(const DevItem *__restrict__ items, int n,
-                                                const int *__restrict__ first,
-                                                int *__restrict__ counter) {
-    constexpr size_t kEst = sizeof(est::Smem<8>), kGat = sizeof(gat::Smem<R, TPW>);
+template <typename S, int R, int TPG>
+__global__ __launch_bounds__(64 * TPG) void k_batch(const DevItem *__restrict__ items, int n,
+                                                   const int *__restrict__ first,
+                                                   int *__restrict__ counter) {
+    constexpr size_t kEst = sizeof(est::StripSmem<TPG>), kGat = sizeof(gat::Smem<S, R, TPG>);
     __shared__ __align__(16) unsigned char raw[kEst > kGat ? kEst : kGat];
-    __shared__ float tparam[3 * TPW];
+    __shared__ float tparam[3 * TPG];
     __shared__ int s_item;
-    est::Smem<8> &esm = *reinterpret_cast<est::Smem<8> *>(raw);
-    gat::Smem<R, TPW> &gsm = *reinterpret_cast<gat::Smem<R, TPW> *>(raw);
+    est::StripSmem<TPG> &esm = *reinterpret_cast<est::StripSmem<TPG> *>(raw);
+    gat::Smem<S, R, TPG> &gsm = *reinterpret_cast<gat::Smem<S, R, TPG> *>(raw);
     const int total = first[n];
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -77,21 +77,17 @@ __global__ __launch_bounds__(kWave) void k_batch(const DevItem *__restrict__ ite
         }
         const DevItem &d = items[lo];
         const BufView<S> v = item_view<S>(d);
-        const int gx = (d.tg.tiles_x + TPW - 1) / TPW;
+        const int gx = (d.tg.tiles_x + TPG - 1) / TPG;
         const int local = w - first[lo];
-        const int tx0 = (local % gx) * TPW, ty = local / gx;
-        for (int t = 0; t < TPW; ++t) {
-            if (tx0 + t < d.tg.tiles_x) {
-                est::estimate_tile<S, 8>(v, d.ep, d.tg, ty * d.tg.tiles_x + tx0 + t, d.stats, esm,
-                                      tparam + 3 * t);
-            } else if (threadIdx.x == 0) {  // lanes of a missing tile write nothing
-                tparam[3 * t] = 1.0f;
-                tparam[3 * t + 1] = 1.0f;
-                tparam[3 * t + 2] = 0.0f;
-            }
+        const int tx0 = (local % gx) * TPG, ty = local / gx;
+        if (threadIdx.x < TPG && tx0 + (int)threadIdx.x >= d.tg.tiles_x) {  // no such tile
+            tparam[3 * threadIdx.x] = 1.0f;
+            tparam[3 * threadIdx.x + 1] = 1.0f;
+            tparam[3 * threadIdx.x + 2] = 0.0f;
         }
+        est::estimate_strip<S, TPG>(v, d.ep, d.tg, tx0, ty, d.stats, esm, tparam);
         __syncthreads();
-        gat::gather_group<S, R, TPW>(v, d.tp, d.tg, tx0, ty, gsm, tparam, d.rgb, d.aux);
+        gat::gather_strip<S, R, TPG>(v, d.tp, d.tg, tx0, ty, gsm, tparam, d.rgb, d.aux);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -100,7 +96,7 @@ using KernelFn = void (*)(const DevItem *, int, const int *, int *);
 
 template <typename S, int R>
 KernelFn kernel_for(int tpw) {
-    if (tpw == 4 && R <= 3) return k_batch<S, R, (R <= 3 ? 4 : 2)>;
+    if (tpw == 4 && R <= 2) return k_batch<S, R, (R <= 2 ? 4 : 2)>;
     if (tpw >= 2) return k_batch<S, R, 2>;
     return k_batch<S, R, 1>;
 }
@@ -122,7 +118,7 @@ KernelFn batch_kernel(int precision, int R, int tpw) {
 
 int shape_index(int tpw) { return tpw == 1 ? 0 : (tpw == 2 ? 1 : 2); }
 
-bool shape_supported(int tpw, int R) { return tpw == 1 || tpw == 2 || (tpw == 4 && R <= 3); }
+bool shape_supported(int tpw, int R) { return tpw == 1 || tpw == 2 || (tpw == 4 && R <= 2); }
 
 size_t table_bytes(int n) { return align_up((size_t)n * sizeof(DevItem)); }
 size_t first_bytes(int n) { return align_up((size_t)(n + 1) * sizeof(int)); }
@@ -184,7 +180,7 @@ afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tile
         if (it.params.tile != 8 || it.params.radius != R || it.buf.precision != prec)
             return AFR_E_UNSUPPORTED;
     }
-    const int tpw = tiles_per_wave == 0 ? 2 : tiles_per_wave;
+    const int tpw = tiles_per_wave == 0 ? (R <= 2 ? 4 : 2) : tiles_per_wave;
     if (!shape_supported(tpw, R)) return AFR_E_RANGE;
 
     // Larger items first: the last items taken are the smallest, which evens the tail.
@@ -247,7 +243,8 @@ afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tile
         if (!shape_supported(kShapes[s], R)) continue;
         int per_cu = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])), kWave, 0);
+            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])),
+            kWave * kShapes[s], 0);
         b->grid[s] = std::max(1, std::min(b->total[s], std::max(1, per_cu) * cus));
     }
     if (e == hipSuccess) e = hipMemcpy(b->d_items, table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
@@ -266,7 +263,7 @@ afr_status afr_batch_run(const afr_batch *b, hipStream_t stream) {
     const int s = shape_index(b->tpw);
     k_batch_reset<<<1, 1, 0, stream>>>(b->d_counter);
     KernelFn fn = batch_kernel(b->precision, b->radius, b->tpw);
-    hipLaunchKernelGGL(fn, dim3(b->grid[s]), dim3(kWave), 0, stream, b->d_items, b->n,
+    hipLaunchKernelGGL(fn, dim3(b->grid[s]), dim3(kWave * b->tpw), 0, stream, b->d_items, b->n,
                        b->d_first[s], b->d_counter);
     return hipGetLastError() == hipSuccess ? AFR_OK : AFR_E_DEVICE;
 }

@@ -318,10 +318,10 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         rec[j].key = ok ? order_key(rec[j].t, (int)i) : 0ull;
         bin[j] = in ? bin_of(rec[j].x, rec[j].y, g) : -1;
         sp[j] = in ? atomicAdd(&tab[bin[j]], 1) : 0;  // rank inside the bin
-        if constexpr (H)
-            hp[j] = make_uint2(pack_half2(Codec<__half>::enc_time(rec[j].t, c.t_ref),
-                                          Codec<__half>::enc(rec[j].r)),
-                               pack_half2(Codec<__half>::enc(rec[j].g), Codec<__half>::enc(rec[j].b)));
+        if constexpr (H)  // the binary16 slot record's last two words: (r, g), (b, age_ref)
+            hp[j] = make_uint2(pack_half2(Codec<__half>::enc(rec[j].r), Codec<__half>::enc(rec[j].g)),
+                               pack_half2(Codec<__half>::enc(rec[j].b),
+                                          Codec<__half>::enc_time(rec[j].t, c.t_ref)));
     }
     __syncthreads();
     const int nvalid = block_scan_lds<kChunkThreads>(tab, tab, g.nb);  // bin offsets, in place
@@ -367,21 +367,33 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
 template <typename S>
 __device__ inline void store_record(const afr_deep_buffer &out, size_t o, int e, const KeyXY &a,
                                     const float4 &c) {
-    S *ox = static_cast<S *>(out.ox), *oy = static_cast<S *>(out.oy);
-    S *ta = static_cast<S *>(out.tage), *r = static_cast<S *>(out.r);
-    S *g = static_cast<S *>(out.g), *b = static_cast<S *>(out.b);
-    if (e >= 0) {
-        ox[o] = Codec<S>::enc(a.x - floorf(a.x));
-        oy[o] = Codec<S>::enc(a.y - floorf(a.y));
-        ta[o] = Codec<S>::enc_time(c.x, out.t_ref);
-        r[o] = Codec<S>::enc(c.y);
-        g[o] = Codec<S>::enc(c.z);
-        b[o] = Codec<S>::enc(c.w);
-        if (out.src) out.src[o] = key_index(a.key);
+    if constexpr (std::is_same<S, __half>::value) {  // one 12-byte slot record
+        uint3 w = make_uint3(0u, 0u, 0u);
+        if (e >= 0) {
+            w.x = (unsigned)__half_as_ushort(Codec<__half>::enc(a.x - floorf(a.x))) |
+                  ((unsigned)__half_as_ushort(Codec<__half>::enc(a.y - floorf(a.y))) << 16);
+            w.y = (unsigned)__half_as_ushort(Codec<__half>::enc(c.y)) |
+                  ((unsigned)__half_as_ushort(Codec<__half>::enc(c.z)) << 16);
+            w.z = (unsigned)__half_as_ushort(Codec<__half>::enc(c.w)) |
+                  ((unsigned)__half_as_ushort(Codec<__half>::enc_time(c.x, out.t_ref)) << 16);
+        }
+        reinterpret_cast<uint3 *>(out.ox)[o] = w;
     } else {
-        ox[o] = oy[o] = ta[o] = r[o] = g[o] = b[o] = Codec<S>::enc(0.0f);
-        if (out.src) out.src[o] = -1;
+        S *ox = static_cast<S *>(out.ox), *oy = static_cast<S *>(out.oy);
+        S *ta = static_cast<S *>(out.tage), *r = static_cast<S *>(out.r);
+        S *g = static_cast<S *>(out.g), *b = static_cast<S *>(out.b);
+        if (e >= 0) {
+            ox[o] = Codec<S>::enc(a.x - floorf(a.x));
+            oy[o] = Codec<S>::enc(a.y - floorf(a.y));
+            ta[o] = Codec<S>::enc_time(c.x, out.t_ref);
+            r[o] = Codec<S>::enc(c.y);
+            g[o] = Codec<S>::enc(c.z);
+            b[o] = Codec<S>::enc(c.w);
+        } else {
+            ox[o] = oy[o] = ta[o] = r[o] = g[o] = b[o] = Codec<S>::enc(0.0f);
+        }
     }
+    if (out.src) out.src[o] = e >= 0 ? key_index(a.key) : -1;
 }
 
 // Binary16 mode: the select keeps each listed record's encoded offsets (ox | oy << 16) in LDS, so
@@ -394,17 +406,10 @@ __device__ inline unsigned encode_oxy(float x, float y) {
            ((unsigned)__half_as_ushort(Codec<__half>::enc(y - floorf(y))) << 16);
 }
 
-// Stores a kept binary16 record from its encoded offsets, stream index and encoded payload.
+// Stores a kept binary16 slot record from its encoded offsets, stream index and encoded payload.
 __device__ inline void store_record_oxy(const afr_deep_buffer &out, size_t o, unsigned oxy, int src,
                                         const uint2 &h) {
-    auto lo = [](unsigned v) { return __ushort_as_half((unsigned short)(v & 0xffffu)); };
-    auto hi = [](unsigned v) { return __ushort_as_half((unsigned short)(v >> 16)); };
-    static_cast<__half *>(out.ox)[o] = lo(oxy);
-    static_cast<__half *>(out.oy)[o] = hi(oxy);
-    static_cast<__half *>(out.tage)[o] = lo(h.x);
-    static_cast<__half *>(out.r)[o] = hi(h.x);
-    static_cast<__half *>(out.g)[o] = lo(h.y);
-    static_cast<__half *>(out.b)[o] = hi(h.y);
+    reinterpret_cast<uint3 *>(out.ox)[o] = make_uint3(oxy, h.x, h.y);
     if (out.src) out.src[o] = src;
 }
 

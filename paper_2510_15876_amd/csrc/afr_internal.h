@@ -48,6 +48,27 @@ struct Codec<__half> {
     __device__ static __half enc_time(float t, float t_ref) { return __float2half_rn(t_ref - t); }
 };
 
+// Slot layout: binary32 buffers keep each field in its own [K][H][W] plane; binary16 buffers keep
+// each slot as one 12-byte record (ox, oy, r, g, b, age_ref), so the field pointers step by six
+// elements from slot to slot.
+template <typename S>
+struct Slots;
+template <>
+struct Slots<float> {
+    static constexpr int kStride = 1;
+};
+template <>
+struct Slots<__half> {
+    static constexpr int kStride = 6;
+    static constexpr int kBytes = 12;
+};
+
+// Field value of slot s (slot plane k of pixel q: s = k W H + q) through its field pointer.
+template <typename S>
+__device__ inline S fld(const S *f, size_t s) {
+    return f[s * Slots<S>::kStride];
+}
+
 // ---- device views -----------------------------------------------------------------------------
 template <typename S>
 struct BufView {
@@ -95,10 +116,20 @@ inline afr_status check_buffer(const afr_deep_buffer *b) {
     if (b->width < 1 || b->height < 1) return AFR_E_RANGE;
     if (b->k < 1 || b->k > 255) return AFR_E_RANGE;
     if (b->precision != AFR_FP32 && b->precision != AFR_FP16) return AFR_E_RANGE;
-    // every flat slot index must fit in int32 arithmetic on the device
+    // every flat slot index must fit in int32 arithmetic on the device, and the buffer-resource
+    // loads address one slot plane with 32-bit byte offsets: a plane stays below 2^31 bytes
     if ((int64_t)b->width * b->height * b->k >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    const int64_t slot_bytes = b->precision == AFR_FP16 ? 12 : 4;
+    if ((int64_t)b->width * b->height * slot_bytes >= (int64_t(1) << 31)) return AFR_E_RANGE;
     if (!finite(b->t_ref)) return AFR_E_RANGE;
     if (!b->ox || !b->oy || !b->tage || !b->r || !b->g || !b->b || !b->count) return AFR_E_INVALID;
+    if (b->precision == AFR_FP16) {  // one array of 12-byte records, fields at 2-byte steps
+        const char *o = static_cast<const char *>(b->ox);
+        if (reinterpret_cast<uintptr_t>(o) % 4 != 0 || static_cast<const char *>(b->oy) != o + 2 ||
+            static_cast<const char *>(b->r) != o + 4 || static_cast<const char *>(b->g) != o + 6 ||
+            static_cast<const char *>(b->b) != o + 8 || static_cast<const char *>(b->tage) != o + 10)
+            return AFR_E_INVALID;
+    }
     return AFR_OK;
 }
 
@@ -140,7 +171,7 @@ struct BuildWs {
 };
 // Buffer-resource loads of one slot plane: the descriptor (SGPRs) holds the plane's base address
 // and byte size, each lane passes only a 32-bit byte offset, and a load at or past the size returns
-// zero instead of touching memory. Plane sizes are < 2^31 bytes (width * height < 2^29).
+// zero instead of touching memory. Plane sizes are < 2^31 bytes (check_buffer enforces it).
 constexpr int kBufferWord3 = 0x00020000;  // gfx9 family: raw (untyped) 32-bit data
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, size_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
@@ -155,6 +186,16 @@ __device__ inline float plane_load<float>(__amdgpu_buffer_rsrc_t r, unsigned byt
 template <>
 __device__ inline __half plane_load<__half>(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
     return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+}
+
+// Two and three consecutive 32-bit words (4-byte aligned offset) through the same descriptor.
+__device__ inline uint2 load_u32x2(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    return make_uint2(v[0], v[1]);
+}
+__device__ inline uint3 load_u32x3(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, byte_off, 0, 0);
+    return make_uint3(v[0], v[1], v[2]);
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (physical id b runs on XCD b % 8). Give XCD x the
@@ -183,10 +224,17 @@ hipError_t launch_estimate(const afr_deep_buffer &buf, const afr_params &p, cons
 
 hipError_t launch_reconstruct_plain(const afr_deep_buffer &buf, const afr_tile_stats &stats,
                                     const afr_params &p, float *rgb, float *aux, hipStream_t st);
-// tiles_per_wave: launch shape of the tiled gather (1, 2 or 4); it does not change the result.
+// tiles_per_group: launch shape of the tiled gather (1, 2 or 4 tiles, one wave each, per workgroup;
+// R >= 3 takes at most 2); it does not change the result.
 hipError_t launch_reconstruct_tiled(const afr_deep_buffer &buf, const afr_tile_stats &stats,
-                                    const afr_params &p, int tiles_per_wave, float *rgb, float *aux,
-                                    hipStream_t st);
+                                    const afr_params &p, int tiles_per_group, float *rgb,
+                                    float *aux, hipStream_t st);
+// Statistics and gather of each tile group in one launch (8 px tiles; other sizes run the two steps).
+hipError_t launch_forward(const afr_deep_buffer &buf, const afr_params &p,
+                          const afr_tile_stats &stats, int tiles_per_group, float *rgb, float *aux,
+                          hipStream_t st);
+// The library's default group for a radius (the largest the LDS allows).
+int default_tiles_per_group(int radius);
 
 size_t crosshair_ws_bytes(int64_t n, int32_t w, int32_t h);
 hipError_t launch_crosshair_build(const afr_samples &s, const afr_crosshairs &xh,

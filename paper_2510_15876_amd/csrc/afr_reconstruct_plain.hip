@@ -38,9 +38,9 @@ __global__ __launch_bounds__(256) void k_reconstruct_plain(BufView<S> v, RecPara
             const float bx = (float)(qx - i) - 0.5f, by = (float)(qy - j) - 0.5f;
             for (int k = 0; k < n; ++k) {
                 const size_t s = (size_t)k * hw + q;
-                const float dx = bx + Codec<S>::dec(v.ox[s]);
-                const float dy = by + Codec<S>::dec(v.oy[s]);
-                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float dx = bx + Codec<S>::dec(fld(v.ox, s));
+                const float dy = by + Codec<S>::dec(fld(v.oy, s));
+                const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                 const float e = -(dx * dx * cx + dy * dy * cy + a * a * ct);
                 emax = fmaxf(emax, e);
             }
@@ -59,15 +59,15 @@ __global__ __launch_bounds__(256) void k_reconstruct_plain(BufView<S> v, RecPara
             const float bx = (float)(qx - i) - 0.5f, by = (float)(qy - j) - 0.5f;
             for (int k = 0; k < n; ++k) {
                 const size_t s = (size_t)k * hw + q;
-                const float dx = bx + Codec<S>::dec(v.ox[s]);
-                const float dy = by + Codec<S>::dec(v.oy[s]);
-                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float dx = bx + Codec<S>::dec(fld(v.ox, s));
+                const float dy = by + Codec<S>::dec(fld(v.oy, s));
+                const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                 const float e = -(dx * dx * cx + dy * dy * cy + a * a * ct);
                 const float w = expf(e - emax);
                 ws += w;
-                cr += w * Codec<S>::dec(v.r[s]);
-                cg += w * Codec<S>::dec(v.g[s]);
-                cb += w * Codec<S>::dec(v.b[s]);
+                cr += w * Codec<S>::dec(fld(v.r, s));
+                cg += w * Codec<S>::dec(fld(v.g, s));
+                cb += w * Codec<S>::dec(fld(v.b, s));
             }
         }
     const float inv = 1.0f / ws;

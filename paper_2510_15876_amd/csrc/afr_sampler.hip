@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kWave) void k_smp_tiles(BufView<S> v, double t_now,
         const int c = v.count[px];
         for (int k = 0; k < c; ++k) {
             n += 1.0;
-            a += Codec<S>::age64(v.ta[(size_t)k * plane + px], t_now, dt_ref);
+            a += Codec<S>::age64(fld(v.ta, (size_t)k * plane + px), t_now, dt_ref);
         }
     }
 #pragma unroll

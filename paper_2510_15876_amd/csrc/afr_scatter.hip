@@ -108,13 +108,13 @@ __global__ __launch_bounds__(kSThreads) void k_scatter(BufView<S> v, ScatterPara
             if (ax0 > ax1 || ay0 > ay1) continue;
             for (int k = 0; k < n; ++k) {
                 const size_t s = (size_t)k * plane + q;
-                const float ox = Codec<S>::dec(v.ox[s]), oy = Codec<S>::dec(v.oy[s]);
-                const float a = Codec<S>::age(v.ta[s], p.t_now, p.dt_ref);
+                const float ox = Codec<S>::dec(fld(v.ox, s)), oy = Codec<S>::dec(fld(v.oy, s));
+                const float a = Codec<S>::age(fld(v.ta, s), p.t_now, p.dt_ref);
                 float cr = 0.0f, cg = 0.0f, cb = 0.0f;
                 if (pass == 1) {
-                    cr = Codec<S>::dec(v.r[s]);
-                    cg = Codec<S>::dec(v.g[s]);
-                    cb = Codec<S>::dec(v.b[s]);
+                    cr = Codec<S>::dec(fld(v.r, s));
+                    cg = Codec<S>::dec(fld(v.g, s));
+                    cb = Codec<S>::dec(fld(v.b, s));
                 }
                 for (int yy = ay0; yy <= ay1; ++yy) {
                     const float dy = splat_offset(qy, yy, oy);

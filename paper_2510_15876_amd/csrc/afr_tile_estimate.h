@@ -306,7 +306,6 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
         kmax = max(kmax, n_[it]);
     }
     for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
-    const size_t bytes = hw * sizeof(S);
     PixAcc m[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) m[it] = pix_zero();
@@ -315,16 +314,31 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             const int k = min(k0 + j, v.k - 1);  // planes past K are never used
-            const size_t base = (size_t)k * hw;
-            const auto rr = plane_rsrc(v.r + base, bytes), rg_ = plane_rsrc(v.g + base, bytes);
-            const auto rb = plane_rsrc(v.b + base, bytes), rt = plane_rsrc(v.ta + base, bytes);
+            if constexpr (std::is_same<S, __half>::value) {
+                // the record's last two words: (r, g), (b, age_ref)
+                const size_t bytes = hw * Slots<__half>::kBytes;
+                const auto rs = plane_rsrc(v.ox + (size_t)k * hw * Slots<__half>::kStride, bytes);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) {
-                const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
-                cr[j][it] = plane_load<S>(rr, off);
-                cg[j][it] = plane_load<S>(rg_, off);
-                cb[j][it] = plane_load<S>(rb, off);
-                ct[j][it] = plane_load<S>(rt, off);
+                for (int it = 0; it < ITEMS; ++it) {
+                    const unsigned off = (unsigned)px_[it] * Slots<__half>::kBytes + 4u;
+                    const uint2 w = load_u32x2(rs, off);
+                    cr[j][it] = __ushort_as_half((unsigned short)(w.x & 0xffffu));
+                    cg[j][it] = __ushort_as_half((unsigned short)(w.x >> 16));
+                    cb[j][it] = __ushort_as_half((unsigned short)(w.y & 0xffffu));
+                    ct[j][it] = __ushort_as_half((unsigned short)(w.y >> 16));
+                }
+            } else {
+                const size_t base = (size_t)k * hw, bytes = hw * sizeof(S);
+                const auto rr = plane_rsrc(v.r + base, bytes), rg_ = plane_rsrc(v.g + base, bytes);
+                const auto rb = plane_rsrc(v.b + base, bytes), rt = plane_rsrc(v.ta + base, bytes);
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) {
+                    const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
+                    cr[j][it] = plane_load<S>(rr, off);
+                    cg[j][it] = plane_load<S>(rg_, off);
+                    cb[j][it] = plane_load<S>(rb, off);
+                    ct[j][it] = plane_load<S>(rt, off);
+                }
             }
         }
 #pragma unroll
@@ -382,38 +396,48 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
 
 // ---- strip driver (tiles of edge <= 8) ----------------------------------------------------------
 
-constexpr int kStripThreads = 256;
-constexpr int kStripW = 32;                                  // pixels
-constexpr int kStripRegion = (kStripW + 2) * (8 + 2);        // region pixels, at most 340
-constexpr int kStripItems = (kStripRegion + kStripThreads - 1) / kStripThreads;
+// A strip of TILES 8 px tiles (fewer when tiles are smaller: 8 TILES pixels wide) of one tile row,
+// evaluated by a workgroup of 64 TILES threads. The region is the strip plus a one-pixel halo.
+template <int TILES>
+struct Strip {
+    static constexpr int THREADS = 64 * TILES;
+    static constexpr int W = 8 * TILES;                             // pixels
+    static constexpr int REGION = (W + 2) * (8 + 2);                // region pixels
+    static constexpr int ITEMS = (REGION + THREADS - 1) / THREADS;  // per thread
+};
 
+template <int TILES>
 struct StripSmem {
-    double lbar[kStripRegion], om[kStripRegion], gt[kStripRegion], sa[kStripRegion],
-        m2[kStripRegion];
-    int n[kStripRegion];
+    static constexpr int N = Strip<TILES>::REGION;
+    double lbar[N], om[N], gt[N], sa[N], m2[N];
+    int n[N];
 };
 
 // Tiles per strip and strips per tile row for tile edge B <= 8.
-__host__ __device__ inline int strip_tiles(int B) { return kStripW / B; }
+__host__ __device__ inline int strip_tiles(int B, int tiles) { return 8 * tiles / B; }
 
-// Evaluates the tiles tx0 .. tx0 + strip_tiles(B) - 1 of tile row ty with a 256-thread workgroup.
-// Each tile is reduced by one wave in the per-tile routine's order (pixel e on lane e).
-template <typename S>
+// Evaluates the tiles tx0 .. tx0 + strip_tiles(B, TILES) - 1 of tile row ty with a 64 TILES-thread
+// workgroup. Each tile is reduced by one wave in the per-tile routine's order (pixel e on lane e), so
+// the statistics do not depend on TILES. If tparams is not NULL (LDS), wave t's lane 0 also stores
+// the (sx2, sy2, kt2) of tile tx0 + t there, visible after the caller's next barrier.
+template <typename S, int TILES>
 __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int tx0,
-                               int ty, float *stats, StripSmem &sm) {
+                               int ty, float *stats, StripSmem<TILES> &sm, float *tparams) {
+    using ST = Strip<TILES>;
     const Region rg{sm.lbar, sm.om, sm.gt, sm.sa, sm.m2, sm.n};
     const int B = tg.tile;
-    const int ntile = min(strip_tiles(B), tg.tiles_x - tx0);
+    const int ntile = min(strip_tiles(B, TILES), tg.tiles_x - tx0);
     const int i0 = tx0 * B, j0 = ty * B;
     const int sw = min(ntile * B, v.width - i0), sh = min(B, v.height - j0);
     const int rp = sw + 2;
-    region_moments<S, kStripItems, 2>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
+    region_moments<S, ST::ITEMS, 2>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int t = wid; t < ntile; t += kStripThreads / kWave) {
+    for (int t = wid; t < ntile; t += ST::THREADS / kWave) {
         const int bw = min(B, v.width - (i0 + t * B)), bh = sh;
         const Acc acc = wave_tile_acc(rg, rp + 1 + t * B, rp, bw, bh, lane, kWave);
-        tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats, nullptr, lane);
+        tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats,
+                    tparams ? tparams + 3 * t : nullptr, lane);
     }
 }
 

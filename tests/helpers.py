@@ -56,8 +56,8 @@ def params(t_now, **kw):
 
 def buffer_np(buf):
     """GPU deep buffer as float64 numpy planes (dict), plus count and src."""
-    pl = buf.planes.float().cpu().numpy().astype(np.float64)
-    d = {f: np.ascontiguousarray(pl[i].transpose(1, 2, 0)) for i, f in enumerate(buf.FIELDS)}
+    d = {f: np.ascontiguousarray(buf.field(f).float().cpu().numpy().astype(np.float64)
+                                 .transpose(1, 2, 0)) for f in buf.FIELDS}
     d["count"] = buf.count.cpu().numpy()
     d["src"] = None if buf.src is None else buf.src.cpu().numpy().transpose(1, 2, 0)
     return d

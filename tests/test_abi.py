@@ -62,16 +62,23 @@ def test_status_strings_and_sizes(afr):
 
 
 def _fake_buffer(afr, w=16, h=8, k=4, prec=0, t_ref=10.0, null_plane=False):
-    # host addresses only: every call below must fail validation before touching them
-    dummy = 0x1000
-    return afr._DeepBuffer(w, h, k, prec, t_ref, None if null_plane else dummy, dummy, dummy,
-                           dummy, dummy, dummy, dummy, None)
+    # host addresses only: every call below must fail validation before touching them. A binary16
+    # buffer's field pointers address one 12-byte record (ox, oy, r, g, b, age): the struct's order
+    # ox, oy, tage, r, g, b sits at byte offsets 0, 2, 10, 4, 6, 8.
+    d = 0x1000
+    f = (d, d + 2, d + 10, d + 4, d + 6, d + 8) if prec == 1 else (d,) * 6
+    return afr._DeepBuffer(w, h, k, prec, t_ref, None if null_plane else f[0], *f[1:], d, None)
 
 
 @pytest.mark.parametrize("mutate,expect", [
     (dict(), None),
     (dict(k=0), 2), (dict(k=256), 2), (dict(w=0), 2), (dict(prec=3), 2),
     (dict(null_plane=True), 1), (dict(w=1 << 16, h=1 << 12, k=16), 2),
+    (dict(prec=1), None),
+    # one slot plane must stay below 2^31 bytes: 2^29 float32 pixels are too many even at K = 1
+    (dict(w=1 << 15, h=1 << 14, k=1), 2), (dict(w=1 << 15, h=(1 << 14) - 1, k=1), None),
+    # binary16 records are 12 bytes: 2^31 / 12 pixels
+    (dict(w=1 << 14, h=10923, k=1, prec=1), 2), (dict(w=1 << 14, h=10922, k=1, prec=1), None),
 ])
 def test_buffer_validation(afr, mutate, expect):
     lib = afr.library()
@@ -132,6 +139,27 @@ def test_stats_geometry_and_workspace_checks(afr):
     evs = (ctypes.c_void_p * 4)(0x10, 0x20, None, 0x40)
     assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, evs) == 1
     assert lib.afr_build_deep_buffer_staged(ctypes.byref(s), ctypes.byref(b), 0x4000, 1 << 30, None, None, None) == 1
+
+
+def test_fp16_record_layout_is_checked(afr):
+    """Binary16 slots are 12-byte records: field pointers that do not address one record array
+    (separate planes, a misaligned base) are rejected (AFR_E_INVALID) before anything is launched;
+    a consistent record array passes on to the next check (here a radius out of range,
+    AFR_E_RANGE)."""
+    lib = afr.library()
+    p = afr.Params(t_now=11.0, radius=9)._c()
+    st = afr._TileStats(8, 2, 1, 0x7000)
+    ok = _fake_buffer(afr, prec=1)
+    assert lib.afr_estimate_gradients(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(st), None) == 2
+    planes = afr._DeepBuffer(16, 8, 4, 1, 10.0, 0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000,
+                             0x1000, None)
+    assert lib.afr_estimate_gradients(ctypes.byref(planes), ctypes.byref(p), ctypes.byref(st), None) == 1
+    d = 0x1002  # not 4-byte aligned
+    odd = afr._DeepBuffer(16, 8, 4, 1, 10.0, d, d + 2, d + 10, d + 4, d + 6, d + 8, 0x1000, None)
+    assert lib.afr_estimate_gradients(ctypes.byref(odd), ctypes.byref(p), ctypes.byref(st), None) == 1
+    swapped = afr._DeepBuffer(16, 8, 4, 1, 10.0, 0x1000, 0x1002, 0x1004, 0x1006, 0x1008, 0x100a,
+                              0x1000, None)  # planar field order, not the record's
+    assert lib.afr_estimate_gradients(ctypes.byref(swapped), ctypes.byref(p), ctypes.byref(st), None) == 1
 
 
 def test_crosshair_validation(afr):

@@ -161,6 +161,8 @@ def test_launch_shapes_give_identical_output(w, h, radius):
         outs = [afr.reconstruct_launch(gbuf, st, gp, tpw) for tpw in (1, 2, 4)]
         for rgb, aux in outs[1:]:
             assert torch.equal(rgb, outs[0][0]) and torch.equal(aux, outs[0][1])
+        fst, frgb, faux = afr.forward(gbuf, gp)  # the fused launch, the library's shape
+        assert torch.equal(fst, st) and torch.equal(frgb, outs[0][0]) and torch.equal(faux, outs[0][1])
         obuf, _ = O.build_buffer(s, w, h, 8, precision, 40.0)
         orgb, _, _ = O.forward(obuf, op)
         assert np.abs(outs[0][0].cpu().numpy() - orgb).max() <= 1e-5
@@ -225,3 +227,28 @@ def test_reference_statistics_round_trip_and_constants():
     a, _ = afr.reconstruct(gbuf, stats, gp)
     b, _ = afr.reconstruct_plain(gbuf, stats, gp)
     assert float((a - b).abs().max()) <= 2e-6
+
+
+@pytest.mark.parametrize("w,h,radius,precision", [(37, 23, 2, "fp16"), (72, 40, 1, "fp32"),
+                                                  (24, 9, 0, "fp16"), (33, 30, 3, "fp32"),
+                                                  (41, 19, 4, "fp16"), (640, 480, 2, "fp16")])
+def test_fused_forward_equals_estimate_then_gather(w, h, radius, precision):
+    """afr_forward (statistics and gather of each tile group in one launch) gives the statistics of
+    afr_estimate_gradients and the image and aux of afr_reconstruct bit for bit, for every launch
+    shape, including groups past the last tile column."""
+    torch = torch_mod()
+    afr = afr_mod()
+    if (w, h) == (640, 480):
+        wl = workload("c3")
+        s, k, t_ref, t_now = wl.stream, wl.k, wl.t_ref, wl.t_now
+    else:
+        rng = np.random.default_rng(w * 31 + h)
+        scene = S.DiscScene(w, h, rng, 5, 40.0, speed=0.2, radius=(2.0, 7.0))
+        s, k, t_ref, t_now = S.uniform_stream(scene, w, h, w * h * 6, 40.0, 40.0, rng), 8, 40.0, 41.0
+    print(f"fused forward {w}x{h} R={radius} {precision}", flush=True)
+    gbuf, _ = gpu_build(s, w, h, k, precision, t_ref)
+    gp, _ = params(t_now, radius=radius)
+    st = afr.estimate_gradients(gbuf, gp)
+    rgb, aux = afr.reconstruct(gbuf, st, gp)
+    fst, frgb, faux = afr.forward(gbuf, gp)
+    assert torch.equal(fst, st) and torch.equal(frgb, rgb) and torch.equal(faux, aux)
