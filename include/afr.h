@@ -297,6 +297,19 @@ afr_status afr_sampler_select(int32_t width, int32_t height, int32_t tile, const
                               int64_t n, const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
                               void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* afr_sampler_select for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight per-frame serving loops, harnesses that forbid allocation): the same draws, bit for bit, with
+ * no workspace argument. The prefix of tile weights lives in a library-owned device array of
+ * 65 537 64-bit entries (512 KiB, the largest tile count the selection accepts plus one), one per GPU,
+ * held until the process ends. The call allocates nothing and frees nothing. Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different streams) race. More than
+ * 65 536 tiles is AFR_E_RANGE, as for afr_sampler_select. The first call on a device looks up the
+ * array's device address (hipGetSymbolAddress) and keeps it; that lookup is not capturable, so make
+ * one call on each device before capturing. */
+afr_status afr_sampler_select_noalloc(int32_t width, int32_t height, int32_t tile, const float *E,
+                                      int64_t n, const uint32_t *rnd, float *x, float *y,
+                                      int32_t *tile_out, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * RMS error against a reference image (the per-frame error the evaluation of Sec. 7 reports, and the
  * loss the filter parameters sigma and tau are fit on) and its gradient, for chaining into

@@ -24,7 +24,8 @@ __all__ = [
     "reconstruct_backward", "ReconstructFn", "reconstruct_differentiable", "tiles_shape",
     "reconstruct_tune", "Batch", "build_crosshair_buffer", "estimate_gradients_crosshair",
     "SplatParams", "splat_sizes", "reconstruct_scatter", "SamplerParams", "sampler_stats",
-    "sampler_select", "sampler_tile_weights", "SAMPLER_GLOBALS", "rms_loss",
+    "sampler_select", "sampler_select_noalloc", "sampler_tile_weights", "SAMPLER_GLOBALS",
+    "rms_loss",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -162,6 +163,9 @@ def library():
     lib.afr_batch_tiles_per_wave.argtypes = [vp]
     lib.afr_batch_destroy.restype = None
     lib.afr_batch_destroy.argtypes = [vp]
+    lib.afr_sampler_select_noalloc.restype = st
+    lib.afr_sampler_select_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                               ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.afr_reconstruct_launch.restype = st
     lib.afr_reconstruct_launch.argtypes = [P(_DeepBuffer), P(_TileStats), P(_Params), ctypes.c_int32,
                                            vp, vp, vp]
@@ -526,6 +530,29 @@ def sampler_select(width: int, height: int, tile: int, E: torch.Tensor, rnd: tor
                                   _ptr(t) if (t is not None and n) else None, _ptr(ws), wsb,
                                   _stream(stream)), "afr_sampler_select")
     return x, y, t
+
+
+def sampler_select_noalloc(width: int, height: int, tile: int, E: torch.Tensor, rnd: torch.Tensor,
+                           x: torch.Tensor, y: torch.Tensor, tile_out: Optional[torch.Tensor] = None,
+                           stream=None):
+    """``sampler_select`` into caller-provided ``x``, ``y`` (float32 [n]) and ``tile_out`` (int32 [n]
+    or None) through afr_sampler_select_noalloc: no workspace, nothing allocated by the call."""
+    lib = library()
+    ty, tx = tiles_shape(width, height, tile)
+    if E.dtype != torch.float32 or not E.is_contiguous() or tuple(E.shape) != (ty, tx):
+        raise AfrError("E must be a contiguous float32 [tiles_y, tiles_x] tensor")
+    if rnd.dtype != torch.int32 or not rnd.is_contiguous() or rnd.dim() != 1 or rnd.numel() % 3:
+        raise AfrError("rnd must be a contiguous 1-D int32 tensor (uint32 bits) of length 3 n")
+    n = rnd.numel() // 3
+    for name, t, dt in (("x", x, torch.float32), ("y", y, torch.float32),
+                        ("tile_out", tile_out, torch.int32)):
+        if t is not None and (t.dtype != dt or not t.is_contiguous() or t.numel() < n):
+            raise AfrError(f"{name} must be a contiguous {dt} tensor of at least {n} elements")
+    _check(lib.afr_sampler_select_noalloc(width, height, tile, _ptr(E), n, _ptr(rnd) if n else None,
+                                          _ptr(x) if n else None, _ptr(y) if n else None,
+                                          _ptr(tile_out) if (tile_out is not None and n) else None,
+                                          _stream(stream)), "afr_sampler_select_noalloc")
+    return x, y, tile_out
 
 
 def splat_sizes(width: int, height: int, coverage: Optional[torch.Tensor], sp: SplatParams,

@@ -134,6 +134,18 @@ afr_status afr_sampler_select(int32_t width, int32_t height, int32_t tile, const
                                           stream));
 }
 
+afr_status afr_sampler_select_noalloc(int32_t width, int32_t height, int32_t tile, const float *E,
+                                      int64_t n, const uint32_t *rnd, float *x, float *y,
+                                      int32_t *tile_out, hipStream_t stream) {
+    if (!E || n < 0) return AFR_E_INVALID;
+    if (n > 0 && (!rnd || !x || !y)) return AFR_E_INVALID;
+    if (width < 1 || height < 1 || tile < 1) return AFR_E_RANGE;
+    const int64_t nt = (int64_t)((width + tile - 1) / tile) * ((height + tile - 1) / tile);
+    if (nt > kMaxSamplerTiles || n >= (int64_t(1) << 31)) return AFR_E_RANGE;
+    return from_hip(launch_sampler_select_noalloc(width, height, tile, E, n, rnd, x, y, tile_out,
+                                                  stream));
+}
+
 afr_status afr_splat_sizes(int32_t width, int32_t height, const float *coverage,
                            const afr_splat_params *sp, float *size, hipStream_t stream) {
     if (!sp || !size) return AFR_E_INVALID;

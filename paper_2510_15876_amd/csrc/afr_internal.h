@@ -263,6 +263,10 @@ hipError_t launch_sampler_tile_weights(int32_t w, int32_t h, int32_t tile, const
 hipError_t launch_sampler_select(int32_t w, int32_t h, int32_t tile, const float *E, int64_t n,
                                  const uint32_t *rnd, float *x, float *y, int32_t *tile_out,
                                  void *ws, hipStream_t st);
+// The same selection with its prefix in a library-owned device array (no workspace, no allocation).
+hipError_t launch_sampler_select_noalloc(int32_t w, int32_t h, int32_t tile, const float *E,
+                                         int64_t n, const uint32_t *rnd, float *x, float *y,
+                                         int32_t *tile_out, hipStream_t st);
 
 size_t rms_ws_bytes();
 hipError_t launch_rms_loss(const float *img, const float *ref, int64_t n, double scale,

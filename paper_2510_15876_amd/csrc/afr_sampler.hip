@@ -9,6 +9,8 @@
 //                  exclusive prefix sum (exact, so independent of the scan's order)
 //   k_smp_draw     one thread per new sample: the tile whose weight interval holds the draw (binary
 //                  search over the prefix sums) and a uniform spot inside it, in binary32
+#include <mutex>
+
 #include "afr_internal.h"
 
 namespace afr {
@@ -440,6 +442,54 @@ hipError_t launch_sampler_stats(const afr_deep_buffer &buf, const afr_tile_stats
                                                     stats.data, part);
     const SmpParams p{sp.kappa, sp.lambda, sp.m, sp.gain};
     k_smp_global<<<1, kGThreads, 0, st>>>(part, tg, buf.width, buf.height, buf.k, p, E, u, glob);
+    return hipGetLastError();
+}
+
+// ---- spot selection without a caller workspace --------------------------------------------------
+// The prefix of tile weights lives in a file-scope device array instead of the caller's workspace:
+// one per GPU, held until the process ends, shared by every call on that GPU (calls that overlap on
+// one GPU race). k_smp_weights rewrites all of its nt + 1 entries on every call, so nothing in it
+// has to start at zero. In host code `scratch` names a host-side stand-in, not the device array: its
+// device address comes from hipGetSymbolAddress, looked up once per device with that device current
+// and kept per device.
+static __device__ __align__(256) unsigned long long scratch[kMaxSamplerTiles + 1];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's scratch array (looked up on the first call on the device).
+hipError_t sampler_scratch(unsigned long long **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<unsigned long long *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_sampler_select_noalloc(int32_t w, int32_t h, int32_t tile, const float *E,
+                                         int64_t n, const uint32_t *rnd, float *x, float *y,
+                                         int32_t *tile_out, hipStream_t st) {
+    unsigned long long *cum = nullptr;
+    const hipError_t e = sampler_scratch(&cum);
+    if (e != hipSuccess) return e;
+    const int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;
+    const int nt = tiles_x * tiles_y;  // <= kMaxSamplerTiles, checked by the caller
+    k_smp_weights<<<1, kGThreads, 0, st>>>(E, nt, cum);
+    if (n > 0) {
+        const DrawGeom g{w, h, tile, tiles_x, nt};
+        k_smp_draw<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(cum, g, rnd, n, x, y, tile_out);
+    }
     return hipGetLastError();
 }
 

@@ -230,6 +230,14 @@ def test_sampler_validation(afr):
     assert lib.afr_sampler_select(64, 64, 8, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, 0x5000, 16, None) == 4
     assert lib.afr_sampler_select(64, 64, 8, 0x1000, 10, None, 0x3000, 0x4000, None, 0x5000, big, None) == 1
     assert lib.afr_sampler_select(64, 64, 0, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, 0x5000, big, None) == 2
+    # the allocation-free variant: the same checks, up to 65536 tiles (its fixed array), no workspace
+    assert lib.afr_sampler_select_noalloc(4096, 4096, 8, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, None) == 2
+    assert lib.afr_sampler_select_noalloc(2049, 2048, 8, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, None) == 2
+    assert lib.afr_sampler_select_noalloc(64, 64, 8, None, 10, 0x2000, 0x3000, 0x4000, None, None) == 1
+    assert lib.afr_sampler_select_noalloc(64, 64, 8, 0x1000, 10, None, 0x3000, 0x4000, None, None) == 1
+    assert lib.afr_sampler_select_noalloc(64, 64, 8, 0x1000, -1, 0x2000, 0x3000, 0x4000, None, None) == 1
+    assert lib.afr_sampler_select_noalloc(64, 64, 0, 0x1000, 10, 0x2000, 0x3000, 0x4000, None, None) == 2
+    assert lib.afr_sampler_select_noalloc(64, 64, 8, 0x1000, 1 << 31, 0x2000, 0x3000, 0x4000, None, None) == 2
 
 
 def test_sampler_tile_weights_validation(afr):
