@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import subprocess
 import os
 import sys
 import time
@@ -559,19 +560,28 @@ def main():
     # accuracy gate on the rotated buffer 0 against the FP64 reference (same FP16 buffer)
     import oracle as O
     if not args.no_cpu:
-        cores = 1
-        times = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            ob, _ = O.build_buffer(wl.stream, W, H, K, "fp16", wl.t_ref)
-            orgb, _, _ = O.forward(ob, O.Params(t_now=wl.t_now, radius=args.radius))
-            times.append(time.perf_counter() - t0)
-        t_cpu = float(np.median(times))
+        def time_frame(reps):
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ob, _ = O.build_buffer(wl.stream, W, H, K, "fp16", wl.t_ref)
+                o_rgb, _, _ = O.forward(ob, O.Params(t_now=wl.t_now, radius=args.radius))
+                times.append(time.perf_counter() - t0)
+            return float(np.median(times)), o_rgb
+        cores = O.num_threads()
+        t_cpu, orgb = time_frame(3)
+        O.set_num_threads(1)
+        t_one, _ = time_frame(1)
+        O.set_num_threads(cores)
         out["cpu_baseline"] = {"value": round(W * H / t_cpu / 1e6, 5), "unit": "Mpixel/s",
                                "cores": cores, "kind": "oracle",
                                "sample": "one full 640x480 K=16 FP16 frame (build+estimate+gather), "
-                                         "FP64 single-threaded C, median of 3 runs",
-                               "seconds_per_frame": round(t_cpu, 3)}
+                                         "FP64 C with OpenMP over rows (%d threads), median of 3 "
+                                         "runs; single thread: one run" % cores,
+                               "seconds_per_frame": round(t_cpu, 3),
+                               "single_core_value": round(W * H / t_one / 1e6, 5),
+                               "single_core_seconds_per_frame": round(t_one, 3),
+                               "host": host_cpu()}
         # rgbs[0] holds the tiled gather of rotation copy 0 (identical inputs in every copy)
         err = float(np.abs(rgbs[0].cpu().numpy() - orgb).max())
         out["max_abs_err_vs_fp64"] = err
@@ -595,6 +605,21 @@ def main():
     if args.batch > 0:
         out["batch"] = batch_leg(torch, afr, S, dev, args.batch)
     print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    """The host's CPU model (lscpu) and the cores this process may run on."""
+    model = None
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def batch_leg(torch, afr, S, dev, n, reps=10):

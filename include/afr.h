@@ -124,7 +124,7 @@ typedef struct afr_params {
     float alpha;       /* age-weight rate, per ms [3.47e-3]: exp(-3.47 a) with a in s (Sec. 4)   */
     float e_min;       /* spatial std floor, px [0.5]; > 0                                       */
     float e_max;       /* spatial std clamp scale, px [1.0]; > 0 or +inf                         */
-    float g_floor;     /* quadrature floor of spatial gradients, 1/px [1e-3]; >= 0               */
+    float g_floor;     /* quadrature floor of spatial gradients, 1/px [1e-3]; > 0                */
     float dt_floor;    /* floor of the new/old age separation, ms [1e-3]; > 0                    */
     float age_floor;   /* floor of the mean age in the density estimate, ms [1e-3]; > 0          */
     int32_t radius;    /* gather radius R: Chebyshev block of (2R+1)^2 pixels [2]; 0..4          */
@@ -182,7 +182,9 @@ afr_status afr_build_deep_buffer_staged(const afr_samples *s, afr_deep_buffer *o
  * luminance mean and variance, and the extents: with Gx' = sqrt(Gx^2 + g_floor^2) (same for y) and
  * u = tau Gt, ex2 = cbrt(V Gy' u / Gx'^2)^2, ey2 = cbrt(V Gx' u / Gy'^2)^2,
  * kt2 = cbrt(u^2 / (V Gx' Gy'))^2 (all 0 when u = 0), then
- * sx2 = e_min^2 + z e_max^2 / (e_max^2 + z), z = sigma^2 ex2 (likewise sy2).
+ * sx2 = e_min^2 + z e_max^2 / (e_max^2 + z), z = sigma^2 ex2 (likewise sy2). A tile with u > 0 and
+ * no buffered samples (V = +inf; crosshair gradients over an empty tile) takes the large-V limit:
+ * ex2 = ey2 = +inf, sx2 = sy2 = e_min^2 + e_max^2 (+inf when e_max is), kt2 = 0.
  *
  *   buf   a built deep buffer; out->data receives every statistic plane (overwritten)
  * ------------------------------------------------------------------------------------------- */

@@ -26,14 +26,32 @@ NSTAT = len(STAT_NAMES)
 STAT = {n: i for i, n in enumerate(STAT_NAMES)}
 
 
+# gcc flags of the reference: no fast-math, no FP contraction; OpenMP over rows (every output
+# element is computed by one thread in the single-thread order, so results do not depend on the
+# thread count).
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the C reference with gcc (no fast-math, no FP contraction)."""
+    """Compile the C reference with gcc."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def source_path() -> str:
+    return _SRC
+
+
+def num_threads() -> int:
+    """Threads the reference's parallel loops use (OMP_NUM_THREADS, else the host's cores)."""
+    return int(_lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _lib().or_set_num_threads(int(n))
 
 
 class _Params(ctypes.Structure):
@@ -71,9 +89,16 @@ _lib_handle = None
 def _lib():
     global _lib_handle
     if _lib_handle is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("AFR_ORACLE_LIB")  # another build of afr_oracle.c (sanitizers)
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(path):
+                build(force=False)
+        lib = ctypes.CDLL(path)
+        lib.or_num_threads.restype = ctypes.c_int
+        lib.or_num_threads.argtypes = []
+        lib.or_set_num_threads.restype = None
+        lib.or_set_num_threads.argtypes = [ctypes.c_int]
         fp = ctypes.POINTER(ctypes.c_float)
         lib.or_f16_round.restype = ctypes.c_double
         lib.or_f16_round.argtypes = [ctypes.c_double]

@@ -25,6 +25,32 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Threads: the per-row (or per-tile-row) loops below run under OpenMP when the file is built with
+ * -fopenmp. Every output element is computed by one thread in the same operation order as with a
+ * single thread, so results do not depend on the thread count. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 enum {
     OR_GX = 0, OR_GY, OR_GT, OR_VOL, OR_VAR, OR_LMEAN, OR_EX2, OR_EY2, OR_SX2, OR_SY2, OR_KT2,
     OR_NSTAT
@@ -117,6 +143,7 @@ int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, co
         return 1;
     const size_t HW = (size_t)W * H, HWK = HW * K;
     const float t_ref = (float)out->t_ref;
+#pragma omp parallel for schedule(static)
     for (size_t s = 0; s < HWK; ++s) {
         out->ox[s] = out->oy[s] = out->ta[s] = out->r[s] = out->g[s] = out->b[s] = 0.0;
         out->src[s] = -1;
@@ -147,7 +174,15 @@ int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, co
         x = xa;
         y = ya;
     }
-    int64_t nv = 0, nd = 0;
+    /* which samples are kept: decided per sample (in parallel), then collected in stream order */
+    unsigned char *keep = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+    if (!keep) {
+        free(keys);
+        free(xa);
+        free(ya);
+        return 4;
+    }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         int ok = isfinite(x[i]) && isfinite(y[i]) && isfinite(t[i]) && isfinite(r[i]) &&
                  isfinite(g[i]) && isfinite(b[i]);
@@ -158,7 +193,11 @@ int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, co
             ok = isfinite(or_f16_round(age)) && isfinite(or_f16_round(r[i])) &&
                  isfinite(or_f16_round(g[i])) && isfinite(or_f16_round(b[i]));
         }
-        if (ok) {
+        keep[i] = (unsigned char)ok;
+    }
+    int64_t nv = 0, nd = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (keep[i]) {
             keys[nv].t = t[i];
             keys[nv].i = i;
             ++nv;
@@ -166,11 +205,24 @@ int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, co
             ++nd;
         }
     }
+    free(keep);
     qsort(keys, (size_t)nv, sizeof(or_key), or_key_cmp);
 
+    /* Queues of different pixels are independent: each thread takes a band of rows and inserts,
+     * in sorted order, the samples that land in it. */
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+    const int nth = omp_get_num_threads(), th = omp_get_thread_num();
+#else
+    const int nth = 1, th = 0;
+#endif
+    const int row0 = (int)((int64_t)H * th / nth), row1 = (int)((int64_t)H * (th + 1) / nth);
     for (int64_t a = 0; a < nv; ++a) {
         const int64_t i = keys[a].i;
         const double fx = floor((double)x[i]), fy = floor((double)y[i]);
+        if (fy < row0 || fy >= row1)
+            continue;
         const size_t p = (size_t)fy * W + (size_t)fx;
         const size_t base = p * K;
         int c = out->count[p];
@@ -203,6 +255,7 @@ int or_build(int64_t n, const float *x_in, const float *y_in, const float *t, co
         }
         out->src[base] = (int32_t)i;
         out->count[p] = (uint8_t)(c < K ? c + 1 : K);
+    }
     }
     free(keys);
     free(xa);
@@ -246,6 +299,7 @@ int or_pixel_stats(const or_buffer *buf, const or_params *p, double *lbar, doubl
                    double *gx, double *gy, double *gt)
 {
     const int W = buf->width, H = buf->height, K = buf->k;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t px = (size_t)j * W + i;
@@ -278,6 +332,7 @@ int or_pixel_stats(const or_buffer *buf, const or_params *p, double *lbar, doubl
                 gt[px] = fabs(ln - lo) / fmax(ao - an, p->dt_floor);
             }
         }
+#pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t px = (size_t)j * W + i;
@@ -307,8 +362,13 @@ int or_pixel_stats(const or_buffer *buf, const or_params *p, double *lbar, doubl
  * spatial width sits at its floor. Spatial stds get a smooth clamp,
  *   sx2 = e_min^2 + z e_max^2 / (e_max^2 + z),  z = sigma^2 ex2   (sx2 = e_min^2 + z if e_max = inf),
  * which is C-infinity in sigma and tau. Extents are standard deviations with support constant 1
- * (the paper says "proportional"; a reading). Pinned by the paper's own constraints in a test mode
- * (g_floor = e_min = 0, e_max = inf, sigma = tau = 1) and by unit covariance.
+ * (the paper says "proportional"; a reading). A tile with a temporal gradient but no buffered
+ * samples (V = +inf, u > 0: crosshair gradients over an empty tile) takes the formula's limit as V
+ * grows: ex2 = ey2 = +inf, so the clamped width is its ceiling e_min^2 + e_max^2 (+inf without a
+ * clamp), and kt2 = 0 (a reading; the paper does not treat the case). Estimates need g_floor > 0:
+ * with a zero floor a flat tile divides by a zero gradient. Pinned by the paper's own constraints
+ * in a test mode (g_floor = e_min = 0, e_max = inf, sigma = tau = 1), by unit covariance and by the
+ * large-V limit.
  * --------------------------------------------------------------------------------------------- */
 void or_extents(double gx, double gy, double gt, double vol, const or_params *p, double *out5)
 {
@@ -331,8 +391,8 @@ void or_extents(double gx, double gy, double gt, double vol, const or_params *p,
         sx2 = en2 + zx;
         sy2 = en2 + zy;
     } else {
-        sx2 = en2 + zx * em2 / (em2 + zx);
-        sy2 = en2 + zy * em2 / (em2 + zy);
+        sx2 = en2 + (isinf(zx) ? em2 : zx * em2 / (em2 + zx));
+        sy2 = en2 + (isinf(zy) ? em2 : zy * em2 / (em2 + zy));
     }
     out5[0] = ex2;
     out5[1] = ey2;
@@ -356,7 +416,7 @@ void or_extents(double gx, double gy, double gt, double vol, const or_params *p,
 int or_estimate(const or_buffer *buf, const or_params *p, double *stats)
 {
     const int W = buf->width, H = buf->height, K = buf->k, B = p->tile;
-    if (B < 1 || W < 1 || H < 1)
+    if (B < 1 || W < 1 || H < 1 || !(p->g_floor > 0.0))
         return 1;
     const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
     const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty;
@@ -366,6 +426,7 @@ int or_estimate(const or_buffer *buf, const or_params *p, double *stats)
     double *omega = lbar + HW, *gx = lbar + 2 * HW, *gy = lbar + 3 * HW, *gt = lbar + 4 * HW;
     or_pixel_stats(buf, p, lbar, omega, gx, gy, gt);
 
+#pragma omp parallel for schedule(dynamic, 1)
     for (int ty = 0; ty < Ty; ++ty)
         for (int tx = 0; tx < Tx; ++tx) {
             const size_t T = (size_t)ty * Tx + tx;
@@ -524,10 +585,11 @@ int or_crosshair_records(int64_t ns, const float *x, const float *y, const float
 int or_crosshair_tiles(const or_buffer *xbuf, const or_params *p, double *stats)
 {
     const int W = xbuf->width, H = xbuf->height, K = xbuf->k, B = p->tile;
-    if (B < 1 || W < 1 || H < 1 || xbuf->fp16)
+    if (B < 1 || W < 1 || H < 1 || xbuf->fp16 || !(p->g_floor > 0.0))
         return 1;
     const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
     const size_t NT = (size_t)Tx * Ty;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int ty = 0; ty < Ty; ++ty)
         for (int tx = 0; tx < Tx; ++tx) {
             const size_t T = (size_t)ty * Tx + tx;
@@ -595,14 +657,17 @@ int or_reconstruct(const or_buffer *buf, const double *stats, const or_params *p
         return 1;
     const int Tx = (W + B - 1) / B, Ty = (H + B - 1) / B;
     const size_t HW = (size_t)W * H, NT = (size_t)Tx * Ty;
+    for (size_t T = 0; T < NT; ++T)
+        if (!(stats[OR_SX2 * NT + T] > 0.0) || !(stats[OR_SY2 * NT + T] > 0.0) ||
+            !(stats[OR_KT2 * NT + T] >= 0.0))
+            return 2;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t px = (size_t)j * W + i;
             const size_t T = (size_t)(j / B) * Tx + (i / B);
             const double sx2 = stats[OR_SX2 * NT + T], sy2 = stats[OR_SY2 * NT + T];
             const double kt2 = stats[OR_KT2 * NT + T];
-            if (!(sx2 > 0.0) || !(sy2 > 0.0) || !(kt2 >= 0.0))
-                return 2;
             int qx0, qx1, qy0, qy1;
             block_bounds(i, R, W, &qx0, &qx1);
             block_bounds(j, R, H, &qy0, &qy1);
@@ -661,7 +726,8 @@ int or_reconstruct(const or_buffer *buf, const double *stats, const or_params *p
  *   dE/dtheta    = 1/2 (dx^2 dsx2/dtheta / sx2^2 + dy^2 dsy2/dtheta / sy2^2) - 1/2 a^2 dkt2/dtheta
  * From the extents: z = sigma^2 ex2, dsx2/dz = e_max^4 / (e_max^2 + z)^2 (1 without a clamp),
  * dz/dsigma = 2 sigma ex2, dz/dtau = sigma^2 (2/3) ex2 / tau, dkt2/dtau = (4/3) kt2 / tau,
- * dkt2/dsigma = 0. Requires tau > 0. Everything (E, E_max, W', C) is recomputed here.
+ * dkt2/dsigma = 0; at the large-V limit (ex2 = +inf) the width is constant in sigma and tau, so
+ * those derivatives are 0. Requires tau > 0. Everything (E, E_max, W', C) is recomputed here.
  * Pinned by FP64 central finite differences of or_reconstruct and by the adjoint identity
  * <J v, u> = <v, J^T u>.
  * --------------------------------------------------------------------------------------------- */
@@ -692,10 +758,12 @@ int or_backward(const or_buffer *buf, const double *stats, const or_params *p,
                 dsx_dz = em2 * em2 / ((em2 + zx) * (em2 + zx));
                 dsy_dz = em2 * em2 / ((em2 + zy) * (em2 + zy));
             }
-            const double dsx_dsig = dsx_dz * 2.0 * p->sigma * ex2;
-            const double dsy_dsig = dsy_dz * 2.0 * p->sigma * ey2;
-            const double dsx_dtau = dsx_dz * p->sigma * p->sigma * (2.0 / 3.0) * ex2 / p->tau;
-            const double dsy_dtau = dsy_dz * p->sigma * p->sigma * (2.0 / 3.0) * ey2 / p->tau;
+            const double dsx_dsig = isinf(ex2) ? 0.0 : dsx_dz * 2.0 * p->sigma * ex2;
+            const double dsy_dsig = isinf(ey2) ? 0.0 : dsy_dz * 2.0 * p->sigma * ey2;
+            const double dsx_dtau =
+                isinf(ex2) ? 0.0 : dsx_dz * p->sigma * p->sigma * (2.0 / 3.0) * ex2 / p->tau;
+            const double dsy_dtau =
+                isinf(ey2) ? 0.0 : dsy_dz * p->sigma * p->sigma * (2.0 / 3.0) * ey2 / p->tau;
             const double dkt_dtau = (4.0 / 3.0) * kt2 / p->tau;
 
             int qx0, qx1, qy0, qy1;

@@ -59,9 +59,12 @@ __device__ inline TileCoef tile_coef(const float *stats, int nt, int T, const Bw
         dx_dz = m2 * m2 / ((m2 + zx) * (m2 + zx));
         dy_dz = m2 * m2 / ((m2 + zy) * (m2 + zy));
     }
-    const double dsx_ds = dx_dz * 2.0 * p.sigma * ex2, dsy_ds = dy_dz * 2.0 * p.sigma * ey2;
-    const double dsx_dt = dx_dz * p.sigma * p.sigma * (2.0 / 3.0) * ex2 / p.tau;
-    const double dsy_dt = dy_dz * p.sigma * p.sigma * (2.0 / 3.0) * ey2 / p.tau;
+    // at the large-V limit (ex2 = +inf) the width is its ceiling, constant in sigma and tau
+    const bool fx = !isinf(ex2), fy = !isinf(ey2);
+    const double dsx_ds = fx ? dx_dz * 2.0 * p.sigma * ex2 : 0.0;
+    const double dsy_ds = fy ? dy_dz * 2.0 * p.sigma * ey2 : 0.0;
+    const double dsx_dt = fx ? dx_dz * p.sigma * p.sigma * (2.0 / 3.0) * ex2 / p.tau : 0.0;
+    const double dsy_dt = fy ? dy_dz * p.sigma * p.sigma * (2.0 / 3.0) * ey2 / p.tau : 0.0;
     const double dkt_dt = (4.0 / 3.0) * kt2 / p.tau;
     TileCoef c;
     // the exponent coefficients use the forward kernels' float expressions bit for bit

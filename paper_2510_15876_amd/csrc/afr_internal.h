@@ -139,7 +139,7 @@ inline afr_status check_params(const afr_params *p, const afr_deep_buffer *b) {
                           p->age_floor, p->t_now};
     for (float v : vals)
         if (!finite(v)) return AFR_E_RANGE;
-    if (p->sigma < 0.0f || p->tau < 0.0f || p->alpha < 0.0f || p->g_floor < 0.0f) return AFR_E_RANGE;
+    if (p->sigma < 0.0f || p->tau < 0.0f || p->alpha < 0.0f || !(p->g_floor > 0.0f)) return AFR_E_RANGE;
     if (!(p->e_min > 0.0f) || !(p->e_max > 0.0f) || std::isnan(p->e_max)) return AFR_E_RANGE;
     if (!(p->dt_floor > 0.0f) || !(p->age_floor > 0.0f)) return AFR_E_RANGE;
     if (p->radius < 0 || p->radius > kMaxRadius) return AFR_E_RANGE;

@@ -88,7 +88,9 @@ __device__ inline Acc acc_shfl_xor(const Acc &a, int m) {
     return o;
 }
 
-// Filter extents from tile gradients and volume; see afr_estimate_gradients in afr.h.
+// Filter extents from tile gradients and volume; see afr_estimate_gradients in afr.h. V = +inf with
+// u > 0 (a tile with crosshair gradients but no buffered samples) gives ex2 = ey2 = +inf and takes
+// the clamp's limit, the ceiling e_min^2 + e_max^2, and kt2 = 0.
 __device__ inline void extents(double gx, double gy, double gt, double vol, const EstParams &p,
                                double &ex2, double &ey2, double &sx2, double &sy2, double &kt2) {
 #pragma clang fp contract(off)
@@ -111,8 +113,8 @@ __device__ inline void extents(double gx, double gy, double gt, double vol, cons
         sy2 = n2 + zy;
     } else {
         const double m2 = p.e_max * p.e_max;
-        sx2 = n2 + zx * m2 / (m2 + zx);
-        sy2 = n2 + zy * m2 / (m2 + zy);
+        sx2 = n2 + (isinf(zx) ? m2 : zx * m2 / (m2 + zx));
+        sy2 = n2 + (isinf(zy) ? m2 : zy * m2 / (m2 + zy));
     }
 }
 
@@ -263,8 +265,8 @@ __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileG
         sy2 = n2 + zy;
     } else {
         const double m2 = p.e_max * p.e_max;
-        sx2 = n2 + zx * m2 / (m2 + zx);
-        sy2 = n2 + zy * m2 / (m2 + zy);
+        sx2 = n2 + (isinf(zx) ? m2 : zx * m2 / (m2 + zx));
+        sy2 = n2 + (isinf(zy) ? m2 : zy * m2 / (m2 + zy));
     }
     if (lane != 0) return;
     const int nt = tg.nt;

@@ -96,6 +96,7 @@ def test_buffer_validation(afr, mutate, expect):
     ("radius", 5, 2), ("radius", -1, 2), ("tile", 0, 2), ("tile", 17, 2),
     ("e_min", 0.0, 2), ("e_max", 0.0, 2), ("sigma", -1.0, 2), ("tau", float("nan"), 2),
     ("dt_floor", 0.0, 2), ("age_floor", -1.0, 2), ("alpha", float("inf"), 2),
+    ("g_floor", 0.0, 2), ("g_floor", -1e-3, 2),
 ])
 def test_param_validation(afr, field, value, expect):
     lib = afr.library()

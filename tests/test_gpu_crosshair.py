@@ -126,3 +126,49 @@ def test_static_scene_has_zero_temporal_gradient_on_gpu():
     st0 = afr.estimate_gradients(gbuf, gp).cpu().numpy()
     assert np.all(st[O.STAT["gt"]] == 0.0) and np.all(st[O.STAT["kt2"]] == 0.0)
     assert st0[O.STAT["gt"]].max() > 1e-4
+
+
+@pytest.mark.parametrize("radius", [2, 4])
+def test_tiles_without_buffered_samples_take_the_large_volume_limit(radius):
+    """Tiles that hold crosshair records but no buffered samples (V = +inf, G_t > 0): widths at the
+    clamp's ceiling e_min^2 + e_max^2, kt2 = 0, no NaN anywhere; statistics, forward and adjoint
+    against the reference."""
+    torch = torch_mod()
+    afr = afr_mod()
+    cw = _workload()
+    wl, xh = cw.workload, cw.crosshairs
+    print(f"crosshair empty tiles radius={radius}", flush=True)
+    x, y = wl.stream.x, wl.stream.y
+    # tiles (1, 26) and (2, 12) of 8 px: moving content, so their crosshair G_t is > 0
+    empty = (((x >= 208) & (x < 216) & (y >= 8) & (y < 16))
+             | ((x >= 96) & (x < 104) & (y >= 16) & (y < 24)))
+    s = wl.stream.select(~empty)
+    gbuf, _ = gpu_build(s, wl.width, wl.height, wl.k, "fp32", wl.t_ref)
+    obuf, _ = O.build_buffer(s, wl.width, wl.height, wl.k, "fp32", wl.t_ref)
+    gx, _ = _gpu_xbuf(wl.stream, xh, wl.width, wl.height, 4, wl.t_ref)
+    ox, _ = O.crosshair_buffer(wl.stream, xh, wl.width, wl.height, 4, wl.t_ref)
+    gp, op = params(wl.t_now, radius=radius, e_min=0.5, e_max=2.0)
+    gst = afr.estimate_gradients_crosshair(gbuf, gx, gp)
+    ost = O.estimate_crosshair(obuf, ox, op)
+    g = gst.cpu().numpy().astype(np.float64)
+    assert not np.isnan(g).any() and not np.isnan(ost).any()
+    st = O.STAT
+    for ty, tx in ((1, 26), (2, 12)):
+        assert np.isinf(ost[st["vol"]][ty, tx]) and ost[st["gt"]][ty, tx] > 0
+        assert g[st["sx2"]][ty, tx] == np.float32(4.25) and g[st["kt2"]][ty, tx] == 0.0
+    for i, n in enumerate(O.STAT_NAMES):
+        rtol, atol = _stat_tol(n)
+        np.testing.assert_allclose(g[i], ost[i], rtol=rtol, atol=atol, err_msg=f"stat {n}")
+    rgb, aux = afr.reconstruct(gbuf, gst, gp)
+    orgb, _ = O.reconstruct(obuf, ost, op)
+    r = rgb.cpu().numpy()
+    assert np.array_equal(np.isnan(r), np.isnan(orgb))
+    assert float(np.nanmax(np.abs(r - orgb))) <= 1e-5
+    # the adjoint on the same float32 statistics
+    ost32 = np.ascontiguousarray(g)
+    og = np.random.default_rng(radius).standard_normal(orgb.shape) * 1e-3
+    og[np.isnan(orgb)] = 0.0
+    _, gpar = afr.reconstruct_backward(gbuf, gst, gp, rgb, aux, torch.from_numpy(og).float().to(DEV))
+    _, opar = O.backward(obuf, ost32, op, og)
+    assert np.all(np.isfinite(gpar.cpu().numpy()))
+    np.testing.assert_allclose(gpar.cpu().numpy(), opar, rtol=1e-4)

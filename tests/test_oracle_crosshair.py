@@ -176,3 +176,36 @@ def test_crosshair_queue_keeps_the_newest_per_pixel(oracle):
         j, i = divmod(p, w)
         assert xbuf.count[j, i] == min(3, mine.size)
         np.testing.assert_array_equal(xbuf.src[j, i, :xbuf.count[j, i]], newest)
+
+
+def test_empty_tile_with_crosshair_gradients_takes_the_large_volume_limit(oracle):
+    """A 4 px tile whose pixels hold crosshair records but no buffered samples has V = +inf. With a
+    temporal gradient its spatial widths sit at the clamp's ceiling e_min^2 + e_max^2 and kt2 = 0;
+    the gather at radius 4 reaches the neighbouring tiles' slots from every pixel of it, and the
+    gather and its adjoint stay finite."""
+    w, h, t_now = 12, 8, 100.0
+    rng = np.random.default_rng(12)
+    xb = _xbuf(oracle, w, h, 2)
+    for j in range(h):
+        for i in range(w):
+            _put(xb, j, i, 0, t_now - 1.0, (0.2, 0.1, 0.05))
+    buf = oracle.Buffer.empty(w, h, 2, fp16=False, t_ref=t_now)
+    for j in range(h):
+        for i in range(w):
+            if i < 4 and j < 4:
+                continue  # tile (0, 0) stays empty
+            buf.ta[j, i, 0] = t_now - rng.random() * 20.0
+            buf.ox[j, i, 0], buf.oy[j, i, 0] = rng.random(2)
+            buf.r[j, i, 0], buf.g[j, i, 0], buf.b[j, i, 0] = rng.random(3)
+            buf.count[j, i] = 1
+    p = oracle.Params(t_now=t_now, tile=4, e_min=0.5, e_max=2.0, radius=4)
+    st = oracle.estimate_crosshair(buf, xb, p)
+    S_ = oracle.STAT
+    assert np.isinf(st[S_["vol"]][0, 0]) and st[S_["gt"]][0, 0] == pytest.approx(0.05, rel=1e-14)
+    assert st[S_["sx2"]][0, 0] == 4.25 and st[S_["sy2"]][0, 0] == 4.25 and st[S_["kt2"]][0, 0] == 0.0
+    for n in ("sx2", "sy2", "kt2"):
+        assert np.all(np.isfinite(st[S_[n]]))
+    rgb, aux = oracle.reconstruct(buf, st, p)
+    assert np.all(np.isfinite(rgb)) and np.all(aux[1] > 0)
+    gs, gp = oracle.backward(buf, st, p, rng.standard_normal(rgb.shape))
+    assert np.all(np.isfinite(gs)) and np.all(np.isfinite(gp))

@@ -209,3 +209,30 @@ def test_extents_clamp_limits(oracle):
     small_gt = oracle.extents(0.1, 0.1, 0.001, 4.0, p)
     # a larger temporal gradient gives a shorter temporal filter and a wider spatial one (Sec. 5.1)
     assert big_gt["kt2"] > small_gt["kt2"] and big_gt["sx2"] > small_gt["sx2"]
+
+
+def test_extents_large_volume_limit(oracle):
+    """V = +inf with a temporal gradient (crosshair gradients over a tile with no buffered samples)
+    gives the limit of the extents as V grows (Sec. 5.1): ex2, ey2 -> inf, the clamped width at its
+    ceiling e_min^2 + e_max^2, kt2 -> 0; with no clamp the width is infinite."""
+    p = oracle.Params(e_min=0.5, e_max=2.0)
+    lim = oracle.extents(0.1, 0.3, 0.2, np.inf, p)
+    assert lim["ex2"] == np.inf and lim["ey2"] == np.inf and lim["kt2"] == 0.0
+    assert lim["sx2"] == 4.25 and lim["sy2"] == 4.25
+    prev_kt2 = np.inf
+    for v in (1e6, 1e12, 1e24):
+        e = oracle.extents(0.1, 0.3, 0.2, v, p)
+        z = p.sigma ** 2 * e["ex2"]
+        # 4.25 - sx2 = e_max^4 / (e_max^2 + z) < 16 / z, up to rounding of the sum
+        assert 0.0 <= lim["sx2"] - e["sx2"] <= 16.0 / z + 1e-15
+        assert 0.0 < e["kt2"] < prev_kt2
+        prev_kt2 = e["kt2"]
+    assert oracle.extents(0.1, 0.3, 0.2, np.inf, p.with_(e_max=np.inf))["sx2"] == np.inf
+
+
+@pytest.mark.parametrize("g_floor", [0.0, -1e-3])
+def test_estimate_requires_a_positive_gradient_floor(oracle, g_floor):
+    """With no floor a spatially flat tile that changes in time divides by a zero gradient."""
+    buf = oracle.Buffer.empty(16, 8, 2, fp16=False, t_ref=10.0)
+    with pytest.raises(ValueError):
+        oracle.estimate(buf, oracle.Params(t_now=10.0, g_floor=g_floor))
