@@ -121,3 +121,46 @@ def test_graph_capture_replays_match_eager():
         for a, b in zip(eager_stats, batch.stats):
             assert torch.equal(a, b)
     batch.close()
+
+
+@pytest.mark.timeout(900)
+def test_c5_recipe_equals_separate_calls_and_reference():
+    """The C5 batch as configured: 64 items drawn from {128x128, 320x240, 640x480, 1024x768} x
+    K {4, 8, 16}, FP16 storage, R = 2. Every item of the batched launch (default shape, then the
+    tuned one) equals its separate estimate + gather calls bit for bit, and the largest items (both
+    1024x768 K=16 drawn first) match the FP64 reference on the same buffers to 1e-5."""
+    torch = torch_mod()
+    afr = afr_mod()
+    recipe = S.c5_recipe()
+    largest = [i for i, r in enumerate(recipe) if r == (1024, 768, 16)][:2]
+    items, kept = [], {}
+    for i in range(len(recipe)):
+        wl = S.make_c5_batch(instances=[i])[0]
+        if i % 8 == 0:
+            print(f"c5 item {i}: {wl.width}x{wl.height} K={wl.k}", flush=True)
+        buf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, "fp16", wl.t_ref)
+        items.append((buf, afr.Params(t_now=wl.t_now)))
+        if i in largest:
+            kept[i] = wl
+    batch = afr.Batch(items)
+    for label in ("default", "tuned"):
+        if label == "tuned":
+            tpw, _ = batch.tune()
+            print(f"tuned tiles_per_wave {tpw}", flush=True)
+        batch.run()
+        torch.cuda.synchronize()
+        for i, (buf, p) in enumerate(items):
+            st = afr.estimate_gradients(buf, p)
+            rgb, aux = afr.reconstruct(buf, st, p)
+            assert torch.equal(batch.stats[i], st), (label, i)
+            assert torch.equal(batch.rgb[i], rgb), (label, i)
+            assert torch.equal(batch.aux[i], aux), (label, i)
+    for i in largest:
+        wl = kept[i]
+        print(f"c5 item {i} against the reference", flush=True)
+        ob, _ = O.build_buffer(wl.stream, wl.width, wl.height, wl.k, "fp16", wl.t_ref)
+        orgb, _, _ = O.forward(ob, O.Params(t_now=wl.t_now))
+        err = float(np.abs(batch.rgb[i].cpu().numpy() - orgb).max())
+        print(f"  max |C - C_ref| = {err:.3g}", flush=True)
+        assert err <= 1e-5
+    batch.close()
