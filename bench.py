@@ -5,9 +5,10 @@ R = 2, 8 px statistics tiles; 64 discs with specular-like highlights over a rota
 stratified over 64 ms (seeded, synthetic: the paper's BART animations are not available).
 
 One step = the whole forward path on one frame's worth of samples already resident in HBM:
-afr_build_deep_buffer (stream -> per-pixel deep buffer), afr_estimate_gradients (tile statistics),
-afr_reconstruct (adaptive gather). Six independent copies of the inputs rotate between steps so the
-~0.5 GB the steps touch is not served from the 256 MB Infinity Cache.
+afr_build_deep_buffer (stream -> per-pixel deep buffer), then afr_forward (tile statistics and the
+adaptive gather in one launch, bit-identical to afr_estimate_gradients + afr_reconstruct). Six
+independent copies of the inputs rotate between steps so the ~0.5 GB the steps touch is not served
+from the 256 MB Infinity Cache.
 
 Printed: one JSON line. ``value`` is reconstructed Mpixel/s of whole steps, timed with nothing but the
 path's launches between two events; extra keys give the per-kernel stage times (from a second pass
@@ -57,6 +58,9 @@ def _args():
                     help="also time the steps replayed from a captured graph (0 skips it)")
     ap.add_argument("--batch", type=int, default=64,
                     help="items in the batched-launch leg (the 64-item uneven batch; 0 skips it)")
+    ap.add_argument("--no-scatter", action="store_true", help="skip the scatter-form leg")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain-vs-chosen comparison on FP32 buffers")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "COMMAND"),
                     help="print a text summary of a rocprofv3 --stats kernel table and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -66,6 +70,9 @@ def _args():
                          "counter_collection.csv files (one pass each) and exit; the command that "
                          "made them goes in --summary-command")
     ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
+    ap.add_argument("--summary-kernels",
+                    default=r"^k_(bin_|scan_|forward<__half,2,|gather<__half,[12],4>|estimate_strip<__half>)",
+                    help="regular expression of the kernels a counter summary lists")
     return ap.parse_args()
 
 
@@ -124,7 +131,7 @@ def pmc_summary(fetch_csv, write_csv, command, copy_kib=262144):
     return "\n".join(out)
 
 
-def counter_summary(csvs, command, radius=2):
+def counter_summary(csvs, command, radius=2, kernels=r"^k_"):
     """Per-kernel averages (per dispatch) of every SQ/TCC counter found in the given rocprofv3
     counter-collection CSVs, and for the gather kernels the per-pair and per-cycle ratios the design
     notes quote: VALU wave-instructions per (slot, pixel) pair-wave (a pair-wave is 64 pairs), LDS
@@ -149,8 +156,9 @@ def counter_summary(csvs, command, radius=2):
            "# command (one rocprofv3 --pmc pass per counter group): " + command,
            "# (slot, pixel) pairs of the gather: R=1 %d, R=2 %d" % (pairs[1], pairs[2]),
            "# kernel | counter | mean per dispatch | dispatches"]
+    import re
     for k in sorted(vals):
-        if not k.startswith("k_"):
+        if not re.search(kernels, k):
             continue
         for c in sorted(vals[k]):
             v = vals[k][c]
@@ -173,7 +181,7 @@ def counter_summary(csvs, command, radius=2):
     return "\n".join(out)
 
 
-STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "estimate", "gather")
+STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_select", "forward")
 
 
 def kernel_of(stage, k, radius, tpw):
@@ -184,9 +192,13 @@ def kernel_of(stage, k, radius, tpw):
             "bin_scatter": "k_bin_scatter<false,*>",
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),
+            "forward": "k_forward<__half,%d,%d>" % (radius, tpw),
             "estimate": "k_estimate_strip<__half>",
             "gather": "k_gather<__half,%d,%d>" % (radius, tpw)}[stage]
-SINGLE_KERNEL = ("bin_scatter", "bin_select", "estimate", "gather")
+SINGLE_KERNEL = ("bin_scatter", "bin_select", "forward")
+# Algorithmic bytes of the 640x480 K=16 forward (statistics + gather) as the design target states
+# them: every occupied binary16 slot record read once, the image written once.
+FORWARD_TARGET_BYTES = 63.0e6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_k16_fp16.txt")
 
 
@@ -238,6 +250,24 @@ def read_traffic(kernel):
     return int(round((fk * vals["f_fetch"] + wk * vals["f_write"]) * 1024))
 
 
+_SLEEP_PER_MS = []
+
+
+def hold_gpu(torch, ms=2.0):
+    """Queue a spin kernel of about ``ms`` milliseconds, so that the launches that follow are all
+    enqueued while the GPU is still busy and event-timed regions measure GPU time, not the host's
+    launch rate. The spin rate is calibrated once."""
+    if not _SLEEP_PER_MS:
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda._sleep(1000)
+        e[0].record()
+        torch.cuda._sleep(1000000)
+        e[1].record()
+        torch.cuda.synchronize()
+        _SLEEP_PER_MS.append(1000000 / max(e[0].elapsed_time(e[1]), 1e-3))
+    torch.cuda._sleep(int(_SLEEP_PER_MS[0] * ms))
+
+
 def copy_bandwidth(torch, dev, mib=256, reps=5):
     """Device-to-device copy of ``mib`` MiB: achieved GB/s (read + write) and the per-copy size,
     the known-size reference for the PMC byte counters."""
@@ -267,6 +297,8 @@ def algorithmic_bytes(stage, n, n_binned, occupied, W, H, K, nt):
         return W * H + occupied * 4 * e + 11 * 4 * nt
     if stage == "gather":        # every occupied slot once, count, 3-channel float image
         return W * H + occupied * 6 * e + 12 * W * H
+    if stage == "forward":       # every occupied slot record once, count, image, 11 stats planes
+        return W * H + occupied * 6 * e + 12 * W * H + 11 * 4 * nt
     return None
 
 
@@ -281,9 +313,9 @@ def gather_pairs(count, radius):
 
 
 def roofline_entry(stage, kernel, nbytes, ms, traffic, pairs):
-    """Roofline of the dominant kernel: the build kernels and the estimator against HBM bandwidth,
-    the gather against vector FP32 arithmetic (per pair one multiply and four fused multiply-adds,
-    9 flops)."""
+    """Roofline of the dominant kernel against HBM bandwidth by its algorithmic bytes; the gather
+    alone against vector FP32 arithmetic (per pair one multiply and four fused multiply-adds,
+    9 flops). The forward also carries its arithmetic fraction."""
     if stage == "gather":
         flops = 9 * pairs
         tf = flops / (ms * 1e-3) / 1e12
@@ -295,9 +327,14 @@ def roofline_entry(stage, kernel, nbytes, ms, traffic, pairs):
                 "frac_of_unpacked_fp32": round(tf / (FP32_VECTOR_PEAK_TFLOPS / 2), 4),
                 "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
     gbs = nbytes / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes": nbytes, "ms_per_launch": round(ms, 5)}
+    out = {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes": nbytes, "ms_per_launch": round(ms, 5)}
+    if stage == "forward":
+        tf = 9 * pairs / (ms * 1e-3) / 1e12
+        out["pair_arithmetic_tflops"] = round(tf, 3)
+        out["pair_arithmetic_frac_of_unpacked_fp32"] = round(tf / (FP32_VECTOR_PEAK_TFLOPS / 2), 4)
+    return out
 
 
 def main():
@@ -309,7 +346,8 @@ def main():
         print(pmc_summary(*args.pmc_summary))
         return
     if args.counter_summary:
-        print(counter_summary(args.counter_summary, args.summary_command, args.radius))
+        print(counter_summary(args.counter_summary, args.summary_command, args.radius,
+                              args.summary_kernels))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU layout "
@@ -344,16 +382,13 @@ def main():
         s = streams[r]
         if ev is None:
             afr.build_deep_buffer(*s, W, H, K, "fp16", wl.t_ref, out=bufs[r], dropped=drop)
-            afr.estimate_gradients(bufs[r], p, out=stats[r])
-            afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
+            afr.forward(bufs[r], p, stats=stats[r], rgb=rgbs[r], want_aux=False)
             return
         ev[0][i].record()
         afr.build_deep_buffer(*s, W, H, K, "fp16", wl.t_ref, out=bufs[r], dropped=drop,
                               stage_events=[ev[1 + j][i] for j in range(nst)])
-        afr.estimate_gradients(bufs[r], p, out=stats[r])
+        afr.forward(bufs[r], p, stats=stats[r], rgb=rgbs[r], want_aux=False)
         ev[nst + 1][i].record()
-        afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
-        ev[nst + 2][i].record()
 
     # launch shape of the gather: the tuner's choice for this geometry (output is identical for
     # every shape)
@@ -364,7 +399,7 @@ def main():
     for i in range(args.warmup):
         step(i % ROTATE)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(args.steps)] for _ in range(nst + 3)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(args.steps)] for _ in range(nst + 2)]
     for row in ev:  # create every event before the timed regions
         for e in row:
             e.record()
@@ -372,6 +407,7 @@ def main():
     torch.cuda.synchronize()
     # the timed steps: nothing but the path's own launches between the two events
     t0 = time.perf_counter()
+    hold_gpu(torch)
     t_beg.record()
     for i in range(args.steps):
         step(i % ROTATE)
@@ -380,6 +416,7 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = t_beg.elapsed_time(t_end) / args.steps
     # the same steps again with an event after every stage (per-stage times, the roofline's kernel)
+    hold_gpu(torch)
     for i in range(args.steps):
         step(i % ROTATE, ev, i)
     torch.cuda.synchronize()
@@ -388,6 +425,7 @@ def main():
         stage_ms[name] = float(np.mean([ev[j][i].elapsed_time(ev[j + 1][i])
                                         for i in range(args.steps)]))
     build_ms = sum(stage_ms[s] for s in STAGES[:4])
+    fwd_ms = stage_ms["forward"]
 
     occupied = int(bufs[0].count.sum().item())
     n = len(wl.stream)
@@ -418,8 +456,7 @@ def main():
             with torch.cuda.stream(streams2[i % 2]):
                 afr.build_deep_buffer(*streams[r], W, H, K, "fp16", wl.t_ref, out=bufs[r],
                                       dropped=drops2[i % 2])
-                afr.estimate_gradients(bufs[r], p, out=stats[r])
-                afr.reconstruct(bufs[r], stats[r], p, rgb=rgbs[r], want_aux=False)
+                afr.forward(bufs[r], p, stats=stats[r], rgb=rgbs[r], want_aux=False)
         for s2 in streams2:
             torch.cuda.current_stream().wait_stream(s2)
         e2[1].record()
@@ -467,31 +504,39 @@ def main():
                        "replay_equals_eager": bool(torch.equal(replayed, rgbs[0]))}
         del graph
 
-    # plain direct gather on the same buffers, for the plain-vs-tiled comparison
+    # the forward's two steps as separate launches on the same buffers (estimate, then gather)
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     n_plain = max(5, args.steps // 5)
     rgb_plain = torch.empty((3, H, W), device=dev)
+    ue = [[torch.cuda.Event(enable_timing=True) for _ in range(n_plain)] for _ in range(3)]
     torch.cuda.synchronize()
-    pe[0].record()
+    hold_gpu(torch)
     for i in range(n_plain):
-        afr.reconstruct_plain(bufs[i % ROTATE], stats[i % ROTATE], p, rgb=rgb_plain, want_aux=False)
-    pe[1].record()
+        r = i % ROTATE
+        ue[0][i].record()
+        afr.estimate_gradients(bufs[r], p, out=stats[r])
+        ue[1][i].record()
+        afr.reconstruct(bufs[r], stats[r], p, rgb=rgb_plain, want_aux=False)
+        ue[2][i].record()
     torch.cuda.synchronize()
-    plain_ms = pe[0].elapsed_time(pe[1]) / n_plain
+    est_ms = float(np.mean([ue[0][i].elapsed_time(ue[1][i]) for i in range(n_plain)]))
+    gat_ms = float(np.mean([ue[1][i].elapsed_time(ue[2][i]) for i in range(n_plain)]))
+    fused_equal = bool(torch.equal(rgb_plain, rgbs[(n_plain - 1) % ROTATE]))
 
     # scatter form on the same buffers: splats of the gather's block size, then the sizes the
     # adaptive rule settles on after a few images of the same buffer
     sp = afr.SplatParams()
     size = afr.splat_sizes(W, H, None, sp, device=dev)
     cov = torch.empty((2, H, W), device=dev)
-    scatter_ms = {}
-    for label in ("block", "adaptive"):
+    scatter_ms = None if args.no_scatter else {}
+    for label in (() if args.no_scatter else ("block", "adaptive")):
         if label == "adaptive":
             for _ in range(4):
                 afr.reconstruct_scatter(bufs[0], stats[0], p, size, sp.size_max, rgb=rgb_plain,
                                         want_aux=False, coverage=cov)
                 afr.splat_sizes(W, H, cov, sp, out=size)
         torch.cuda.synchronize()
+        hold_gpu(torch)
         pe[0].record()
         for i in range(n_plain):
             afr.reconstruct_scatter(bufs[i % ROTATE], stats[i % ROTATE], p, size, sp.size_max,
@@ -499,8 +544,8 @@ def main():
         pe[1].record()
         torch.cuda.synchronize()
         scatter_ms[label] = round(pe[0].elapsed_time(pe[1]) / n_plain, 5)
-    scatter_ms["adaptive_mean_size"] = round(float(size.mean().item()), 4)
-    fwd_ms = stage_ms["estimate"] + stage_ms["gather"]
+    if scatter_ms is not None:
+        scatter_ms["adaptive_mean_size"] = round(float(size.mean().item()), 4)
 
     # the gather at R = 1 (9 pixels per block instead of 25) on the same buffers: the radius at
     # which the gather is bound by HBM rather than by arithmetic
@@ -508,6 +553,7 @@ def main():
     afr.estimate_gradients(bufs[0], p1, out=stats[0])
     afr.reconstruct(bufs[0], stats[0], p1, rgb=rgb_plain, want_aux=False)
     torch.cuda.synchronize()
+    hold_gpu(torch)
     pe[0].record()
     for i in range(n_plain):
         afr.reconstruct(bufs[i % ROTATE], stats[i % ROTATE], p1, rgb=rgb_plain, want_aux=False)
@@ -519,6 +565,15 @@ def main():
                  "hbm_frac": round(g_bytes / (r1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     for r in range(ROTATE):  # statistics of the R = 2 parameters again
         afr.estimate_gradients(bufs[r], p, out=stats[r])
+
+    # plain against chosen form at FP32 storage (and the images of both forms at both storage
+    # precisions, for the precision study below)
+    images = {"chosen_fp16": rgbs[0].clone(),
+              "plain_fp16": afr.reconstruct_plain(bufs[0], stats[0], p, want_aux=False)[0]}
+    plain = None
+    if not args.no_plain:
+        plain, images32 = plain_vs_chosen(torch, afr, wl, streams, p, dev, n_plain)
+        images.update(images32)
 
     out = {
         "metric": "reconstructed Mpixel/s (build + estimate + gather per frame)",
@@ -549,7 +604,15 @@ def main():
         "build_samples_per_s": round(n / (build_ms * 1e-3), 1),
         "two_streams": two_streams,
         "graph_steps": graph_steps,
-        "plain_reconstruct_ms": round(plain_ms, 5),
+        "forward_algorithmic_bytes": algorithmic_bytes("forward", n, n_binned, occupied, W, H, K, nt),
+        "forward_hbm_frac": round(FORWARD_TARGET_BYTES / (fwd_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "unfused": {"estimate_ms": round(est_ms, 5), "gather_ms": round(gat_ms, 5),
+                    "sum_ms": round(est_ms + gat_ms, 5), "gather_equals_fused": fused_equal,
+                    "gather_hbm_frac": round(algorithmic_bytes("gather", n, n_binned, occupied, W, H,
+                                                               K, nt) / (gat_ms * 1e-3) / 1e9
+                                             / HBM_PEAK_GBS, 4),
+                    "gather_pair_tflops": round(9 * pairs / (gat_ms * 1e-3) / 1e12, 3)},
+        "plain_vs_chosen_fp32": plain,
         "gather_r1": gather_r1,
         "scatter_reconstruct_ms": scatter_ms,
         "roofline": roofline_entry(dom, dom_kernel, dom_bytes, stage_ms[dom], traffic, pairs),
@@ -593,6 +656,7 @@ def main():
         out["fp16_storage_err_vs_fp64_fp32_buffer"] = {
             "max": float(e16.max()), "p99": float(np.quantile(e16, 0.99)),
             "mean": float(e16.mean()), "gate_2e-3": bool(e16.max() <= 2e-3)}
+        out["precision"] = precision_study(images, orgb, orgb32)
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(torch, afr, S, dev, args.frames)
@@ -605,6 +669,64 @@ def main():
     if args.batch > 0:
         out["batch"] = batch_leg(torch, afr, S, dev, args.batch)
     print(json.dumps(out), flush=True)
+
+
+def plain_vs_chosen(torch, afr, wl, streams, p, dev, reps):
+    """The plain direct gather (one thread per pixel, global loads, an exponential per pair, one
+    binary32 running sum per pixel) against the chosen form (the fused statistics + LDS-tiled
+    gather) on FP32-storage buffers of the same workload: three copies rotate so that the 354 MB
+    they hold is not served from the Infinity Cache. The plain form takes the statistics the
+    forward wrote. Returns the timings and both forms' images of copy 0."""
+    W, H, K = wl.width, wl.height, wl.k
+    bufs = []
+    for r in range(3):
+        b, _ = afr.build_deep_buffer(*streams[r], W, H, K, "fp32", wl.t_ref)
+        bufs.append(b)
+    st = [afr.forward(b, p, want_aux=False)[0] for b in bufs]
+    out = torch.empty((3, H, W), device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn(0)
+        torch.cuda.synchronize()
+        hold_gpu(torch)
+        ev[0].record()
+        for i in range(reps):
+            fn(i % 3)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    plain_ms = timed(lambda r: afr.reconstruct_plain(bufs[r], st[r], p, rgb=out, want_aux=False))
+    chosen_ms = timed(lambda r: afr.forward(bufs[r], p, stats=st[r], rgb=out, want_aux=False))
+    gather_ms = timed(lambda r: afr.reconstruct(bufs[r], st[r], p, rgb=out, want_aux=False))
+    images = {"plain_fp32": afr.reconstruct_plain(bufs[0], st[0], p, want_aux=False)[0],
+              "chosen_fp32": afr.forward(bufs[0], p, want_aux=False)[1]}
+    torch.cuda.synchronize()
+    return ({"plain_gather_ms": round(plain_ms, 5), "chosen_forward_ms": round(chosen_ms, 5),
+             "chosen_gather_ms": round(gather_ms, 5),
+             "plain_over_chosen_forward": round(plain_ms / chosen_ms, 2),
+             "note": "FP32 storage; the plain time excludes the statistics it reads, the chosen "
+                     "forward includes them"}, images)
+
+
+def precision_study(images, orgb16, orgb32):
+    """Error distributions (max, p99, mean of |C - C_ref| over every pixel and channel) of both
+    forms at both storage precisions against the FP64 reference: on the same FP16 buffer (the
+    arithmetic's error) and on the FP32 buffer (for FP16, the storage error). The chosen form sums
+    each slot plane's terms in binary32 and the planes in binary64; the plain form keeps one
+    binary32 running sum per pixel."""
+    def dist(a, ref):
+        e = np.abs(a.cpu().numpy().astype(np.float64) - ref)
+        return {"max": float(e.max()), "p99": float(np.quantile(e, 0.99)), "mean": float(e.mean())}
+    out = {"accumulation": {"chosen": "binary32 per slot plane, planes summed in binary64",
+                            "plain": "one binary32 running sum per pixel"}}
+    for name, img in images.items():
+        ref = orgb16 if name.endswith("fp16") else orgb32
+        out[name] = dist(img, ref)
+        if name.endswith("fp16"):
+            out[name + "_vs_fp32_buffer"] = dist(img, orgb32)
+    return out
 
 
 def host_cpu():
