@@ -1,8 +1,9 @@
 """GPU scatter form and adaptive splat size (Sec. 5.2, 6.2) against the FP64 reference.
 
 Footprints, coverage counts, mean splat sizes and the size rule are integer or exactly rounded
-binary32 decisions on both sides: compared bit for bit. Colours are sums of float32 terms added
-with LDS atomics in arrival order: max |C - C_ref| <= 1e-5 on [0, 1] colours, as for the gather.
+binary32 decisions on both sides: compared bit for bit. Colours are sums of float32 terms (one
+partial per source pixel, added in binary64 in a fixed order per output pixel): max |C - C_ref| <=
+1e-5 on [0, 1] colours, as for the gather, and two runs give the same bits.
 """
 import numpy as np
 import pytest
@@ -41,8 +42,8 @@ def _run(gbuf, obuf, st, gp, op, size, max_size):
 
 
 @pytest.mark.parametrize("name,precision,sizes", [
-    ("c1", "fp32", "block"), ("c1", "fp32", "mixed"), ("c2", "fp32", "block"),
-    ("c2", "fp32", "mixed"), ("c3", "fp16", "block")])
+    ("c1", "fp32", "block"), ("c1", "fp32", "mixed"), ("c1", "fp16", "large"),
+    ("c2", "fp32", "block"), ("c2", "fp32", "mixed"), ("c3", "fp16", "block")])
 def test_scatter_matches_reference(name, precision, sizes):
     wl = workload(name)
     print(f"scatter parity {name} {precision} {sizes}", flush=True)
@@ -53,9 +54,12 @@ def test_scatter_matches_reference(name, precision, sizes):
     if sizes == "block":
         size = np.full((wl.height, wl.width), 5.0, np.float32)
         max_size = 16.0
-    else:
+    elif sizes == "mixed":
         size = _sizes(np.random.default_rng(3), wl.height, wl.width)
         max_size = 12.0
+    else:  # splats above 16 px: the walk reads sizes and counts from global memory
+        size = _sizes(np.random.default_rng(4), wl.height, wl.width)
+        max_size = 40.0
     _run(gbuf, obuf, st, gp, op, size, max_size)
 
 
@@ -119,3 +123,27 @@ def test_adaptive_splat_loop_matches_reference():
         _, cov = _run(gbuf, obuf, st, gp, op, osize, sp.size_max)
         gcov = torch.from_numpy(cov).to(DEV)
         _, _, ocov = O.scatter(obuf, stats_f32_as_f64(st), op, osize, sp.size_max)
+
+
+@pytest.mark.parametrize("max_size", [16.0, 40.0])
+def test_scatter_is_deterministic(max_size):
+    """Every output pixel adds its splats in a fixed order: two runs (and a run on another stream)
+    give identical images, aux and coverage, for LDS-staged (<= 16 px) and global-memory walks."""
+    torch = torch_mod()
+    afr = afr_mod()
+    wl = workload("c2")
+    print(f"scatter determinism max_size={max_size}", flush=True)
+    gbuf, _ = gpu_build(wl.stream, wl.width, wl.height, wl.k, "fp16", wl.t_ref)
+    gp, _ = params(wl.t_now)
+    st = afr.estimate_gradients(gbuf, gp)
+    size = torch.from_numpy(_sizes(np.random.default_rng(9), wl.height, wl.width)).to(DEV)
+    a = afr.reconstruct_scatter(gbuf, st, gp, size, max_size)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b = afr.reconstruct_scatter(gbuf, st, gp, size, max_size)
+    torch.cuda.current_stream().wait_stream(side)
+    c = afr.reconstruct_scatter(gbuf, st, gp, size, max_size)
+    torch.cuda.synchronize()
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y) and torch.equal(x, z)
