@@ -288,6 +288,12 @@ __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileG
     }
 }
 
+// Holds a loaded value in place: an empty asm statement that consumes (and nominally rewrites) it.
+// A slot's fields are used only under the test k < n, so without this the compiler sinks each load
+// into its test and the lane then waits for memory once per slot; placed after the last load of a
+// chunk it keeps every load of the chunk ahead of the first wait.
+__device__ inline void hold(unsigned &w) { asm volatile("" : "+v"(w)); }
+
 // Phase 1 over the region pixels h = threadIdx.x + it * blockDim.x (it < ITEMS, h < nh) of a region
 // with origin (x0, y0) and pitch rp: the slot planes are visited in chunks of KC, and every load of
 // a chunk (all items, all planes of the chunk) is issued before any is used, so a lane waits for
@@ -311,23 +317,22 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
     PixAcc m[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) m[it] = pix_zero();
-    for (int k0 = 0; k0 < kmax; k0 += KC) {
-        S cr[KC][ITEMS], cg[KC][ITEMS], cb[KC][ITEMS], ct[KC][ITEMS];
+    // raw 32-bit words of each slot: binary16 (r | g, b | age_ref), binary32 (r, g, b, t)
+    constexpr int NW = std::is_same<S, __half>::value ? 2 : 4;
+    using Chunk = unsigned[KC][ITEMS][NW];
+    auto load = [&](Chunk &raw, int k0) {
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             const int k = min(k0 + j, v.k - 1);  // planes past K are never used
             if constexpr (std::is_same<S, __half>::value) {
-                // the record's last two words: (r, g), (b, age_ref)
                 const size_t bytes = hw * Slots<__half>::kBytes;
                 const auto rs = plane_rsrc(v.ox + (size_t)k * hw * Slots<__half>::kStride, bytes);
 #pragma unroll
                 for (int it = 0; it < ITEMS; ++it) {
                     const unsigned off = (unsigned)px_[it] * Slots<__half>::kBytes + 4u;
                     const uint2 w = load_u32x2(rs, off);
-                    cr[j][it] = __ushort_as_half((unsigned short)(w.x & 0xffffu));
-                    cg[j][it] = __ushort_as_half((unsigned short)(w.x >> 16));
-                    cb[j][it] = __ushort_as_half((unsigned short)(w.y & 0xffffu));
-                    ct[j][it] = __ushort_as_half((unsigned short)(w.y >> 16));
+                    raw[j][it][0] = w.x;
+                    raw[j][it][1] = w.y;
                 }
             } else {
                 const size_t base = (size_t)k * hw, bytes = hw * sizeof(S);
@@ -336,19 +341,49 @@ __device__ inline void region_moments(const BufView<S> &v, const EstParams &p, c
 #pragma unroll
                 for (int it = 0; it < ITEMS; ++it) {
                     const unsigned off = (unsigned)px_[it] * (unsigned)sizeof(S);
-                    cr[j][it] = plane_load<S>(rr, off);
-                    cg[j][it] = plane_load<S>(rg_, off);
-                    cb[j][it] = plane_load<S>(rb, off);
-                    ct[j][it] = plane_load<S>(rt, off);
+                    raw[j][it][0] = __builtin_amdgcn_raw_buffer_load_b32(rr, off, 0, 0);
+                    raw[j][it][1] = __builtin_amdgcn_raw_buffer_load_b32(rg_, off, 0, 0);
+                    raw[j][it][2] = __builtin_amdgcn_raw_buffer_load_b32(rb, off, 0, 0);
+                    raw[j][it][3] = __builtin_amdgcn_raw_buffer_load_b32(rt, off, 0, 0);
                 }
             }
         }
+    };
+    auto consume = [&](Chunk &raw, int k0) {
 #pragma unroll
         for (int j = 0; j < KC; ++j)
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it)
-                if (k0 + j < n_[it])
-                    pix_add<S>(m[it], p, cr[j][it], cg[j][it], cb[j][it], ct[j][it], k0 + j, n_[it]);
+#pragma unroll
+                for (int f = 0; f < NW; ++f) hold(raw[j][it][f]);
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                if (k0 + j >= n_[it]) continue;
+                S cr, cg, cb, ct;
+                if constexpr (std::is_same<S, __half>::value) {
+                    cr = __ushort_as_half((unsigned short)(raw[j][it][0] & 0xffffu));
+                    cg = __ushort_as_half((unsigned short)(raw[j][it][0] >> 16));
+                    cb = __ushort_as_half((unsigned short)(raw[j][it][1] & 0xffffu));
+                    ct = __ushort_as_half((unsigned short)(raw[j][it][1] >> 16));
+                } else {
+                    cr = __uint_as_float(raw[j][it][0]);
+                    cg = __uint_as_float(raw[j][it][1]);
+                    cb = __uint_as_float(raw[j][it][2]);
+                    ct = __uint_as_float(raw[j][it][3]);
+                }
+                pix_add<S>(m[it], p, cr, cg, cb, ct, k0 + j, n_[it]);
+            }
+    };
+    // two chunks in flight: the next chunk's loads are issued before the current one is consumed
+    Chunk ca, cb;
+    if (kmax > 0) load(ca, 0);
+    for (int k0 = 0; k0 < kmax; k0 += 2 * KC) {
+        load(cb, k0 + KC);
+        consume(ca, k0);
+        load(ca, k0 + 2 * KC);
+        consume(cb, k0 + KC);
     }
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
@@ -432,7 +467,7 @@ __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const Ti
     const int i0 = tx0 * B, j0 = ty * B;
     const int sw = min(ntile * B, v.width - i0), sh = min(B, v.height - j0);
     const int rp = sw + 2;
-    region_moments<S, ST::ITEMS, 2>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
+    region_moments<S, ST::ITEMS, (std::is_same<S, __half>::value ? 4 : 2)>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int t = wid; t < ntile; t += ST::THREADS / kWave) {
