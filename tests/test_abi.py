@@ -259,3 +259,45 @@ def test_rms_loss_validation(afr):
     assert lib.afr_rms_loss(0x1000, 0x2000, 10, 1.0, None, None, None, need, None) == 1
     assert lib.afr_rms_loss(0x1000, 0x2000, 10, float("nan"), None, None, 0x3000, need, None) == 2
     assert lib.afr_rms_loss(0x1000, 0x2000, 10, 1.0, None, None, 0x3000, need - 1, None) == 4
+
+
+def _batch_item(afr, w=16, h=8, k=4, tile=8, radius=2, prec=0):
+    buf = _fake_buffer(afr, w=w, h=h, k=k, prec=prec)
+    p = afr.Params(t_now=11.0).with_(tile=tile, radius=radius)._c()
+    s = afr._TileStats(tile, (w + tile - 1) // tile, (h + tile - 1) // tile, 0x1000)
+    return afr._BatchItem(buf, s, p, 0x1000, None)
+
+
+def test_batch_plan_validation(afr):
+    """The batch plan (afr_batch_create / run / tune / destroy) validates every item on the host
+    before it uploads anything, and the plan calls reject a NULL plan."""
+    lib = afr.library()
+    assert lib.afr_batch_workspace_bytes(0) == 0
+    assert lib.afr_batch_workspace_bytes(64) >= 64 * 8 * 8
+    ws_ok = lib.afr_batch_workspace_bytes(2)
+    plan = ctypes.c_void_p()
+
+    def create(items, tpw=0, ws=0x1000, nbytes=ws_ok):
+        arr = (afr._BatchItem * max(1, len(items)))(*items)
+        return lib.afr_batch_create(arr if items else None, len(items), tpw, ws, nbytes,
+                                    ctypes.byref(plan))
+
+    good = [_batch_item(afr), _batch_item(afr, w=24, h=16)]
+    assert create([]) == 1                                   # no items
+    assert create(good, ws=None) == 1                        # no workspace
+    assert create(good, nbytes=ws_ok - 1) == 4               # workspace too small
+    assert create(good, tpw=3) == 2                          # launch shape outside 0, 1, 2, 4
+    bad_k = [_batch_item(afr), _batch_item(afr, k=0)]
+    assert create(bad_k) == 2                                # an invalid buffer
+    assert create([_batch_item(afr, tile=4)]) == 5           # statistics tiles other than 8 px
+    assert create([_batch_item(afr), _batch_item(afr, radius=1)]) == 5   # mixed radius
+    assert create([_batch_item(afr), _batch_item(afr, prec=1)]) == 5     # mixed precision
+    no_rgb = _batch_item(afr)
+    no_rgb.rgb = None
+    assert create([no_rgb]) == 1                             # no output image
+    assert create([_batch_item(afr, radius=3)], tpw=4) == 2  # four tiles per group need R <= 2
+    assert not plan.value
+    assert lib.afr_batch_run(None, None) == 1
+    assert lib.afr_batch_tune(None, None, None, None) == 1
+    assert lib.afr_batch_tiles_per_wave(None) == 0
+    lib.afr_batch_destroy(None)
