@@ -411,6 +411,10 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     float gxm[NM];
 #pragma unroll
     for (int m = 0; m < 2 * R; ++m) gxm[m] = __builtin_amdgcn_exp2f(-(float)(2 * (m - R) + 1) * cx2);
+    float gym[2 * R > 0 ? 2 * R : 1];
+    gym[0] = 1.0f;
+#pragma unroll
+    for (int n = 0; n < 2 * R; ++n) gym[n] = __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
     // Recurrences start from the smallest value of a row and need it in float32's range: Y(-R) >=
     // 2^-(R+1/2)^2 cy2 normal, (R + 1/2)^2 cy2 <= 120; X(-R) carries Tm, and a product below the
     // subnormal range would drop the larger X values too (at most 2^((R+1/2)^2 cx2) times larger), so
@@ -487,24 +491,40 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             const float ux = (float)(m - R) + dx;
             dx2[m] = ux * ux;
         }
-        const float rhoy = __builtin_amdgcn_exp2f(-2.0f * dy * cy2);
-        // first row offset this wave needs (see n_lo below), its Y directly
-        const float ey0 = dy + (float)(n_lo - R);
-        float yv = __builtin_amdgcn_exp2f(-ey0 * ey0 * cy2);
+        // Y for the 2R+1 row offsets, by the recurrence from the first row this wave needs or by
+        // one exponential each, before the rows are visited, so that the rows form one unrolled
+        // sequence whose LDS reads the compiler can issue ahead of the previous row's arithmetic.
+        float Y[NM];
+        {
+            const float rhoy = __builtin_amdgcn_exp2f(-2.0f * dy * cy2);
+            const float ey0 = dy + (float)(n_lo - R);
+            float yv = __builtin_amdgcn_exp2f(-ey0 * ey0 * cy2);
+#pragma unroll
+            for (int n = 0; n < NM; ++n) {
+                if (yrec) {
+                    Y[n] = yv;  // valid from n_lo on; rows before it are not visited
+                    if (n >= n_lo) yv *= rhoy * gym[n < 2 * R ? n : 0];
+                } else {
+                    const float e = dy + (float)(n - R);
+                    Y[n] = __builtin_amdgcn_exp2f(-e * e * cy2);
+                }
+            }
+        }
         // The a^2 factor of the tau terms enters as a^2 - amin^2: for every pixel the pi-weighted sum
         // of h over its slots is zero, so a constant offset of a^2 changes nothing but the
         // rounding, and this one keeps the factor small wherever a weight is not negligible.
         const float a2 = da2;
         float gr = 0.0f, gg = 0.0f, gb = 0.0f;
-#pragma unroll 1
-        for (int n = n_lo; n <= n_hi; ++n) {
+#pragma unroll
+        for (int n = 0; n < NM; ++n) {
+            if (n < n_lo || n > n_hi) continue;  // uniform over the wave
             const float uy = (float)(n - R) + dy;
             const float dyn2 = uy * uy;
             const float4 *grow = gk0 + (2 * R - n) * GP + 2 * R;
             float rx = 0.0f, rh = 0.0f;  // sums of hwt dx^2 and of hwt over the row
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-                const float w = X[m] * yv;
+                const float w = X[m] * Y[n];
                 const float4 g4 = grow[-m];
                 gr += w * g4.x;
                 gg += w * g4.y;
@@ -516,13 +536,6 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
             Sx += (double)rx;
             Sy += (double)rh * dyn2;
             Sa += (double)rh * a2;
-            // next row: Y(n+1) = Y(n) rho exp2(-(2(n-R)+1) cy2), or its own exponential
-            if (yrec) {
-                yv *= rhoy * __builtin_amdgcn_exp2f(-(float)(2 * (n - R) + 1) * cy2);
-            } else {
-                const float e = dy + (float)(n + 1 - R);
-                yv = __builtin_amdgcn_exp2f(-e * e * cy2);
-            }
         }
         if (on) {
             float *pt = ws.part + ((size_t)T * K + k) * 3 * NP + pix;

@@ -7,8 +7,10 @@
 //   1. k_bin_count    per chunk of the stream: LDS histogram over bins of 64 x 4 px;
 //                     samples outside the image are dropped here (after reprojection to the
 //                     reference time when the stream carries velocities; the scatter repeats it)
-//   2. scan           exclusive prefix sum of the (bin, chunk) counts, bin-major -> write offsets
-//                     (block scans, then each block adds the sum of the blocks before it)
+//   2. k_scan_rows    per bin: exclusive prefix sum of its row of (bin, chunk) counts, in place,
+//                     and the bin's total; a record's position in the bucket is the sum of the
+//                     totals of the bins before its own (each consumer adds those up itself) plus
+//                     its chunk's offset in the row
 //   3. k_bin_scatter  per chunk: coalesced loads of every field, an LDS counting sort by bin, and
 //                     32-byte records (order key, x, y, t, r, g, b) staged in LDS in bin order, a
 //                     window at a time, so that consecutive lanes store consecutive records of a
@@ -203,42 +205,45 @@ __device__ inline int block_scan_lds(const int *in, int *out, int n) {
     return carry;
 }
 
-// Per-block exclusive scan of cnt into off (in place allowed); block totals into bsum.
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t *cnt, int64_t len,
-                                                             int32_t *off, int32_t *bsum) {
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int sum = 0;
+// One workgroup per bin: exclusive scan of the bin's row of the bin-major (bin, chunk) count table
+// in place, and the bin's total into tot[bin].
+__global__ __launch_bounds__(kScanThreads) void k_scan_rows(int32_t *tab, int nchunks, int32_t *tot) {
+    const int b = blockIdx.x;
+    int32_t *row = tab + (size_t)b * nchunks;
+    int carry = 0;
+    for (int c0 = 0; c0 < nchunks; c0 += kScanBlock) {
+        const int base = c0 + threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
 #pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        v[e] = (base + e < len) ? cnt[base + e] : 0;
-        sum += v[e];
-    }
-    int total;
-    int run = block_exclusive_scan<kScanThreads>(sum, total);
+        for (int e = 0; e < kScanItems; ++e) {
+            v[e] = base + e < nchunks ? row[base + e] : 0;
+            sum += v[e];
+        }
+        int total;
+        int run = carry + block_exclusive_scan<kScanThreads>(sum, total);
 #pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        if (base + e < len) off[base + e] = run;
-        run += v[e];
+        for (int e = 0; e < kScanItems; ++e) {
+            if (base + e < nchunks) row[base + e] = run;
+            run += v[e];
+        }
+        carry += total;
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    if (threadIdx.x == 0) tot[b] = carry;
 }
 
-// Adds to block b's entries the sum of the block sums before it (each block sums that prefix itself,
-// so no separate scan of the block sums is needed); the last block also writes off[len] = total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *off, int64_t len,
-                                                          const int32_t *bsum, int32_t nb) {
-    __shared__ int s_add;
+// Position in the bucket of bin b's first record: the totals of the bins before it, summed by the
+// calling workgroup (NT threads) in a fixed order; valid in every thread.
+template <int NT>
+__device__ inline int bin_start(const int32_t *tot, int b) {
+    __shared__ int s_start;
+    __syncthreads();  // an earlier block_sum_int of the caller has been read out
     int v = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) v += bsum[i];
-    v = block_sum_int<kScanThreads>(v);
-    if (threadIdx.x == 0) s_add = v;
+    for (int i = threadIdx.x; i < b; i += NT) v += tot[i];
+    v = block_sum_int<NT>(v);
+    if (threadIdx.x == 0) s_start = v;
     __syncthreads();
-    const int add = s_add;
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
-    for (int e = threadIdx.x; e < kScanBlock; e += kScanThreads)
-        if (base + e < len) off[base + e] += add;
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) off[len] = add + bsum[blockIdx.x];
+    return s_start;
 }
 
 struct alignas(16) Record {
@@ -271,13 +276,15 @@ __device__ inline unsigned pack_half2(__half lo, __half hi) {
 }
 
 // LDS: the per-bin table [nb] (counts, then offsets in the chunk's sorted order, then the global
-// position minus that offset) and the staged records [kWin]; a staged record's bin, and so its
-// destination, is recomputed from its own x, y. H: binary16 buffer, whose payload is encoded to its
+// position minus that offset) and the staged records [kWin], whose key array first holds the bins'
+// first positions in the bucket (an exclusive scan of the bin totals); a staged record's bin, and
+// so its destination, is recomputed from its own x, y. H: binary16 buffer, whose payload is encoded to its
 // four halves as soon as the record is loaded, so the record holds fewer registers and is staged in
 // 24 instead of 32 bytes.
 template <bool MOTION, int kChunkPer, bool H>
-__global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
-                                                               const int32_t *ot, int nchunks,
+__global__ __launch_bounds__(kChunkThreads, 4) void k_bin_scatter(afr_samples s, ValidCtx c, BinGeom g,
+                                                               const int32_t *ot,
+                                                               const int32_t *tot, int nchunks,
                                                                Bucket bucket, int32_t *bad_tab) {
     constexpr int kChunk = kChunkThreads * kChunkPer;
     extern __shared__ uint4 scat_lds[];  // 16-byte aligned for the staged records
@@ -287,10 +294,16 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
     // of one 8- or 16-byte field meets fewer bank conflicts than a 32-byte record's, and the store
     // loop reads each array in order
     unsigned long long *skey = reinterpret_cast<unsigned long long *>(scat_sm + ((g.nb + 3) & ~3));
+    // the bins' first positions [nb] live in the key array until the records are staged
+    static_assert(kWin * sizeof(unsigned long long) >= kMaxBins * sizeof(int), "room for [nb]");
+    int *bstart = reinterpret_cast<int *>(skey);
     float2 *sxy = reinterpret_cast<float2 *>(skey + kWin);
     float4 *spl = reinterpret_cast<float4 *>(sxy + kWin);  // binary32 payload
     uint2 *sph = reinterpret_cast<uint2 *>(sxy + kWin);    // binary16 payload
-    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) tab[b] = 0;
+    for (int b = threadIdx.x; b < g.nb; b += kChunkThreads) {
+        tab[b] = 0;
+        bstart[b] = tot[b];
+    }
     const int chunk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)chunk * kChunk;
     Record rec[kChunkPer];
@@ -306,6 +319,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         if constexpr (MOTION) advect(rec[j].x, rec[j].y, rec[j].t, s.vx[i], s.vy[i], c.t_ref);
     }
     __syncthreads();
+    // while the samples arrive: the first bucket position of each bin (fewer values are live here
+    // than after the histogram, which keeps two workgroups per CU within the registers)
+    block_scan_lds<kChunkThreads>(bstart, bstart, g.nb);
     int bin[kChunkPer], sp[kChunkPer];
     uint2 hp[H ? kChunkPer : 1];
     int bad = 0;
@@ -331,7 +347,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_bin_scatter(afr_samples s, Va
         if (bin[j] >= 0) sp[j] += tab[bin[j]];  // position in the chunk's bin-sorted order
     __syncthreads();
     for (int b = threadIdx.x; b < g.nb; b += kChunkThreads)
-        tab[b] = ot[(size_t)b * nchunks + chunk] - tab[b];
+        tab[b] = bstart[b] + ot[(size_t)b * nchunks + chunk] - tab[b];
     __syncthreads();
     for (int w0 = 0; w0 < nvalid; w0 += kWin) {
 #pragma unroll
@@ -603,7 +619,7 @@ __device__ inline KeyXY load_key_xy(const KeyXY *r) { return *r; }
 // kListSlots entries (kListCap records plus the pads of swz).
 template <typename S, int KMAX>
 __global__ __launch_bounds__(sel_threads<KMAX>()) void k_bin_select(afr_deep_buffer out, BinGeom g,
-                                                            const int32_t *ot, int nchunks,
+                                                            const int32_t *tot, int nchunks,
                                                             Bucket bucket, const int32_t *bad_tab,
                                                             unsigned long long *dropped) {
     constexpr int kSelThreads = sel_threads<KMAX>(), kSelPer = kListCap / kSelThreads;
@@ -621,8 +637,8 @@ __global__ __launch_bounds__(sel_threads<KMAX>()) void k_bin_select(afr_deep_buf
     unsigned short *pos = reinterpret_cast<unsigned short *>(keys + kListSlots);
     unsigned *oxy = reinterpret_cast<unsigned *>(pos + kListSlots);  // binary16 only
     const int b = blockIdx.x;
-    const int s0 = ot[(size_t)b * nchunks], s1 = ot[(size_t)(b + 1) * nchunks];
-    const int nrec = s1 - s0;
+    const int s0 = bin_start<kSelThreads>(tot, b);
+    const int nrec = tot[b];
     const BinRecs recs{bucket.a + s0, bucket.b + s0, bucket.h + s0};
     const int bx0 = (b % g.nbx) * kBinW, by0 = (b / g.nbx) * g.bh;
     const int W = out.width, H = out.height;
@@ -734,14 +750,14 @@ size_t select_shmem(const BinGeom &g) {
 }
 
 template <typename S>
-hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *ot,
+hipError_t launch_select(const afr_deep_buffer &out, const BinGeom &g, const int32_t *tot,
                          int nchunks, Bucket bucket, const int32_t *bad_tab,
                          unsigned long long *dropped, hipStream_t st) {
     const size_t shmem = select_shmem<S>(g);
     const dim3 grid(g.nb);
     auto go = [&](auto kmax_c) {
         constexpr int KM = decltype(kmax_c)::value;
-        k_bin_select<S, KM><<<grid, dim3(sel_threads<KM>()), shmem, st>>>(out, g, ot, nchunks,
+        k_bin_select<S, KM><<<grid, dim3(sel_threads<KM>()), shmem, st>>>(out, g, tot, nchunks,
                                                                         bucket, bad_tab, dropped);
     };
     if (out.k <= 4) go(std::integral_constant<int, 4>{});
@@ -809,9 +825,8 @@ bool build_supported(int32_t w, int32_t h) { return bin_geom(w, h).nb <= kMaxBin
 size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
     const BinGeom g = bin_geom(w, h);
     const int64_t len = (int64_t)g.nb * n_chunks(n, kPerMin);
-    const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    return align_up((size_t)(len + 1) * 4) + align_up((size_t)(nsb + 1) * 4) +
+    return align_up((size_t)(len + 1) * 4) + align_up((size_t)(g.nb + 1) * 4) +
            align_up((size_t)2 * n_chunks(n, kPerMin) * 4) + 2 * align_up(nn * sizeof(KeyXY)) +
            align_up(8);
 }
@@ -819,14 +834,13 @@ size_t build_ws_bytes(int64_t n, int32_t w, int32_t h) {
 BuildWs build_ws_carve(void *ws, int64_t n, int32_t w, int32_t h) {
     const BinGeom g = bin_geom(w, h);
     const int64_t len = (int64_t)g.nb * n_chunks(n, kPerMin);
-    const int64_t nsb = (len + kScanBlock - 1) / kScanBlock;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     char *p = static_cast<char *>(ws);
     BuildWs o;
     o.offsets = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)(len + 1) * 4);
     o.bsum = reinterpret_cast<int32_t *>(p);
-    p += align_up((size_t)(nsb + 1) * 4);
+    p += align_up((size_t)(g.nb + 1) * 4);
     o.bad = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)2 * n_chunks(n, kPerMin) * 4);
     o.bucket = p;
@@ -843,7 +857,6 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     const int per = pick_per(s.n);
     const int64_t nch = n_chunks(s.n, per);
     const int64_t len = (int64_t)g.nb * nch;
-    const int nsb = (int)((len + kScanBlock - 1) / kScanBlock);
     const size_t half = align_up((size_t)(s.n > 0 ? s.n : 1) * sizeof(KeyXY));
     char *pay = static_cast<char *>(ws.bucket) + half;
     const Bucket bucket{static_cast<KeyXY *>(ws.bucket), reinterpret_cast<float4 *>(pay),
@@ -863,16 +876,16 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
                                                                       (int)nch, ws.bad);
         else if (s.vx && H)
             k_bin_scatter<true, P, true><<<(int)nch, kChunkThreads, shmem, st>>>(
-                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+                s, c, g, ws.offsets, ws.bsum, (int)nch, bucket, ws.bad);
         else if (s.vx)
             k_bin_scatter<true, P, false><<<(int)nch, kChunkThreads, shmem, st>>>(
-                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+                s, c, g, ws.offsets, ws.bsum, (int)nch, bucket, ws.bad);
         else if (H)
             k_bin_scatter<false, P, true><<<(int)nch, kChunkThreads, shmem, st>>>(
-                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+                s, c, g, ws.offsets, ws.bsum, (int)nch, bucket, ws.bad);
         else
             k_bin_scatter<false, P, false><<<(int)nch, kChunkThreads, shmem, st>>>(
-                s, c, g, ws.offsets, (int)nch, bucket, ws.bad);
+                s, c, g, ws.offsets, ws.bsum, (int)nch, bucket, ws.bad);
     };
     auto launch_chunked = [&](bool count) {
         if (per == 6) chunked(std::integral_constant<int, 6>{}, count);
@@ -888,14 +901,13 @@ hipError_t launch_build(const afr_samples &s, const afr_deep_buffer &out, const 
     }
     hipError_t e = mark(0);
     if (e != hipSuccess) return e;
-    k_scan_blocks<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.offsets, ws.bsum);
-    k_scan_add<<<nsb, kScanThreads, 0, st>>>(ws.offsets, len, ws.bsum, nsb);
+    k_scan_rows<<<g.nb, kScanThreads, 0, st>>>(ws.offsets, (int)nch, ws.bsum);
     if ((e = mark(1)) != hipSuccess) return e;
     if (s.n > 0) launch_chunked(false);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     e = out.precision == AFR_FP16
-            ? launch_select<__half>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st)
-            : launch_select<float>(out, g, ws.offsets, (int)nch, bucket, ws.bad, dropped, st);
+            ? launch_select<__half>(out, g, ws.bsum, (int)nch, bucket, ws.bad, dropped, st)
+            : launch_select<float>(out, g, ws.bsum, (int)nch, bucket, ws.bad, dropped, st);
     return e != hipSuccess ? e : mark(3);
 }
 

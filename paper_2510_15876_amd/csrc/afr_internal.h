@@ -163,8 +163,8 @@ void record_tiles_per_wave(const afr_deep_buffer &b, int radius, int tpw);
 
 // ---- launchers (each returns hipGetLastError() of its launches) ---------------------------------
 struct BuildWs {
-    int32_t *offsets;   // [bins * chunks + 1] (bin, chunk) counts, then their exclusive scan
-    int32_t *bsum;      // scan block sums
+    int32_t *offsets;   // [bins * chunks + 1] (bin, chunk) counts, then each bin row's exclusive scan
+    int32_t *bsum;      // [bins] record count of each bin
     int32_t *bad;       // [2 * chunks] dropped samples per chunk (outside the image; invalid payload)
     void *bucket;       // [n] records grouped by bin, as two 16-byte halves in two arrays
     unsigned long long *dropped_internal;
