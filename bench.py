@@ -796,7 +796,8 @@ def batch_leg(torch, afr, S, dev, n, reps=10):
 
 def fwd_bwd(torch, afr, S, dev, frames):
     """Forward + adjoint per frame on the 512x512, K=8, FP32 sequence (60 Hz frames, RMS loss
-    against the analytic ground truth): build + estimate + gather + loss gradient + adjoint."""
+    against the analytic ground truth): build + forward (statistics and gather in one launch) +
+    loss gradient + adjoint."""
     seq = S.make_c4_sequence(n_frames=frames)
     W, H, K = seq.width, seq.height, seq.k
     data = []
@@ -812,8 +813,7 @@ def fwd_bwd(torch, afr, S, dev, frames):
         wl, s, gt = data[f]
         afr.build_deep_buffer(*s, W, H, K, "fp32", wl.t_ref, out=buf, dropped=drop)
         p = afr.Params(t_now=wl.t_now)
-        st = afr.estimate_gradients(buf, p)
-        rgb, aux = afr.reconstruct(buf, st, p)
+        st, rgb, aux = afr.forward(buf, p)
         _, g = afr.rms_loss(rgb, gt, 1.0 / frames)   # gradient of the mean per-frame RMS error
         return afr.reconstruct_backward(buf, st, p, rgb, aux, g)
 

@@ -121,10 +121,10 @@ __device__ inline void extents(double gx, double gy, double gt, double vol, cons
 // ---- per-pixel moments (phase 1) ---------------------------------------------------------------
 
 struct PixAcc {
-    double s0, s1, s2, ln, lo, an, ao, sa;
+    double s0, s1, s2, lt, ln, an, sa;  // lt: all slots' luminance; ln, an: the newer half's
 };
 
-__device__ inline PixAcc pix_zero() { return PixAcc{0, 0, 0, 0, 0, 0, 0, 0}; }
+__device__ inline PixAcc pix_zero() { return PixAcc{0, 0, 0, 0, 0, 0, 0}; }
 
 // Age weight e^{-alpha a} (Sec. 4) over the FP64 exponent range: with x = alpha a log2(e) = n + f,
 // n an integer and f in [0, 1), the weight is 2^-f (float32, within 2 ulp) scaled exactly by 2^-n.
@@ -140,25 +140,25 @@ __device__ inline double age_weight(double alpha, double a) {
     return ldexp((double)__builtin_amdgcn_exp2f((float)(n - x)), -e);
 }
 
-// Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta.
+// Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta. The
+// older half's sums are the totals minus the newer half's (pix_store), so a slot adds to the newer
+// half by one select per sum instead of choosing between two pairs of sums.
 template <typename S>
 __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S ta, int k, int n) {
 #pragma clang fp contract(off)
-    const double L = kLumR * (double)Codec<S>::dec(r) + kLumG * (double)Codec<S>::dec(g) +
-                     kLumB * (double)Codec<S>::dec(b);
+    const double L = fma(kLumB, (double)Codec<S>::dec(b),
+                         fma(kLumG, (double)Codec<S>::dec(g), kLumR * (double)Codec<S>::dec(r)));
     const double a = Codec<S>::age64(ta, p.t_now, p.dt_ref);
     const double w = age_weight(p.alpha, a);
+    const double wl = w * L;
     m.s0 += w;
-    m.s1 += w * L;
-    m.s2 += w * L * L;
+    m.s1 += wl;
+    m.s2 = fma(wl, L, m.s2);
     m.sa += a;
-    if (k < (n + 1) / 2) {
-        m.ln += L;
-        m.an += a;
-    } else {
-        m.lo += L;
-        m.ao += a;
-    }
+    m.lt += L;
+    const bool newer = k < (n + 1) / 2;
+    m.ln += newer ? L : 0.0;
+    m.an += newer ? a : 0.0;
 }
 
 // Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum, M2)
@@ -179,7 +179,7 @@ __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n
     if (n >= 2) {
         const int half = (n + 1) / 2;
         const double dn = half, dd = n - half;
-        gt = fabs(m.ln / dn - m.lo / dd) / fmax(m.ao / dd - m.an / dn, dt_floor);
+        gt = fabs(m.ln / dn - (m.lt - m.ln) / dd) / fmax((m.sa - m.an) / dd - m.an / dn, dt_floor);
     }
     rg.n[h] = n;
     rg.om[h] = om;
