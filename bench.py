@@ -188,7 +188,7 @@ def kernel_of(stage, k, radius, tpw):
     """The kernel instantiation a stage launches for the FP16 workload (rocprofv3's short name). The
     count and scatter kernels also carry the samples per thread the library picks for the launch
     (from the sample count and the CU count), written here as a trailing '*'."""
-    return {"bin_count": "k_bin_count<false,*>", "bin_scan": "k_scan_blocks+k_scan_add",
+    return {"bin_count": "k_bin_count<false,*>", "bin_scan": "k_scan_rows",
             "bin_scatter": "k_bin_scatter<false,*>",
             "bin_select": "k_bin_select<__half,%d>" % (4 if k <= 4 else 8 if k <= 8 else 16 if
                                                        k <= 16 else 32 if k <= 32 else 64),
