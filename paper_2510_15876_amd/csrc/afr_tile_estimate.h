@@ -121,7 +121,7 @@ __device__ inline void extents(double gx, double gy, double gt, double vol, cons
 // ---- per-pixel moments (phase 1) ---------------------------------------------------------------
 
 struct PixAcc {
-    double s0, s1, s2, lt, ln, an, sa;  // lt: all slots' luminance; ln, an: the newer half's
+    double s0, s1, s2, ln, lo, an, sa;  // ln, lo: luminance of the newer and older half; an: newer ages
 };
 
 __device__ inline PixAcc pix_zero() { return PixAcc{0, 0, 0, 0, 0, 0, 0}; }
@@ -141,8 +141,9 @@ __device__ inline double age_weight(double alpha, double a) {
 }
 
 // Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta. The
-// older half's sums are the totals minus the newer half's (pix_store), so a slot adds to the newer
-// half by one select per sum instead of choosing between two pairs of sums.
+// older half's age sum is the total minus the newer half's (pix_store); the luminance sums of both
+// halves are kept, so that a pixel whose samples share one luminance has a temporal difference of
+// exactly zero.
 template <typename S>
 __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S ta, int k, int n) {
 #pragma clang fp contract(off)
@@ -155,9 +156,9 @@ __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S t
     m.s1 += wl;
     m.s2 = fma(wl, L, m.s2);
     m.sa += a;
-    m.lt += L;
     const bool newer = k < (n + 1) / 2;
     m.ln += newer ? L : 0.0;
+    m.lo += newer ? 0.0 : L;
     m.an += newer ? a : 0.0;
 }
 
@@ -179,7 +180,7 @@ __device__ inline void pix_store(const Region &rg, int h, const PixAcc &m, int n
     if (n >= 2) {
         const int half = (n + 1) / 2;
         const double dn = half, dd = n - half;
-        gt = fabs(m.ln / dn - (m.lt - m.ln) / dd) / fmax((m.sa - m.an) / dd - m.an / dn, dt_floor);
+        gt = fabs(m.ln / dn - m.lo / dd) / fmax((m.sa - m.an) / dd - m.an / dn, dt_floor);
     }
     rg.n[h] = n;
     rg.om[h] = om;
