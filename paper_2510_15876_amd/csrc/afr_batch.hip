@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "afr_gather.h"
@@ -52,8 +53,15 @@ __device__ inline BufView<S> item_view(const DevItem &d) {
 
 __global__ void k_batch_reset(int *counter) { *counter = 0; }
 
+// Waves per SIMD the batch kernel is compiled for: four with binary16 storage at R <= 2 (at most 128
+// VGPRs, a few spilled) instead of the three its registers would allow unbounded, so that more
+// workgroups are resident to hide each other's memory latency; unbounded otherwise (binary32 items
+// would spill about forty registers).
+template <typename S, int R>
+constexpr int batch_waves() { return R <= 2 && std::is_same<S, __half>::value ? 4 : 1; }
+
 template <typename S, int R, int TPG>
-__global__ __launch_bounds__(64 * TPG) void k_batch(const DevItem *__restrict__ items, int n,
+__global__ __launch_bounds__(64 * TPG, (batch_waves<S, R>())) void k_batch(const DevItem *__restrict__ items, int n,
                                                    const int *__restrict__ first,
                                                    int *__restrict__ counter) {
     constexpr size_t kEst = sizeof(est::StripSmem<TPG>), kGat = sizeof(gat::Smem<S, R, TPG>);

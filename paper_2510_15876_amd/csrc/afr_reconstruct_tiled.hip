@@ -3,6 +3,8 @@
 // the strip estimator of afr_estimate_gradients (afr_tile_estimate.h) and hands their filter widths
 // to the gather through LDS, so one launch reads the deep buffer for both steps. Workgroups are
 // assigned so that each XCD's L2 serves a contiguous band of the image.
+#include <type_traits>
+
 #include "afr_gather.h"
 #include "afr_tile_estimate.h"
 
@@ -12,10 +14,16 @@ namespace {
 // Largest group the static LDS allows at a radius (tables of R >= 3 regions take two tiles at most).
 constexpr int max_group(int R) { return R <= 2 ? 4 : 2; }
 
-// Four tiles per workgroup at R <= 2 keeps five waves per SIMD (at most 96 VGPRs); the LDS of five
-// such workgroups (27.8 KiB each with binary16 storage) fits a CU.
+// Waves per SIMD the kernels are compiled for. Four tiles per workgroup at R <= 2 with binary16
+// storage: five (at most 96 VGPRs), so that five workgroups share a CU (their LDS, 30 KiB each, fits)
+// and the 1200 workgroups of a 640x480 image run in one round; the fused kernel, whose statistics
+// phase alone would take 104 VGPRs, gives up one spilled register for it (forward 82 -> 77 us).
+// Binary32 storage: four (at most 128 VGPRs), one round for 1024 workgroups (512x512).
+template <typename S, int R>
+constexpr int waves_per_simd() { return R <= 2 ? (std::is_same<S, __half>::value ? 5 : 4) : 1; }
+
 template <typename S, int R, int TPG>
-__global__ __launch_bounds__(64 * TPG, (R <= 2) ? 5 : 1) void k_gather(
+__global__ __launch_bounds__(64 * TPG, (waves_per_simd<S, R>())) void k_gather(
     BufView<S> v, gat::TiledParams p, TileGeom tg, const float *__restrict__ stats,
     float *__restrict__ rgb, float *__restrict__ aux, int gx) {
     __shared__ gat::Smem<S, R, TPG> sm;
@@ -34,7 +42,7 @@ __global__ __launch_bounds__(64 * TPG, (R <= 2) ? 5 : 1) void k_gather(
 
 // Statistics, then the gather, of one group of TPG tiles (8 px tiles only).
 template <typename S, int R, int TPG>
-__global__ __launch_bounds__(64 * TPG, (R <= 2) ? 4 : 1) void k_forward(
+__global__ __launch_bounds__(64 * TPG, (waves_per_simd<S, R>())) void k_forward(
     BufView<S> v, est::EstParams ep, gat::TiledParams p, TileGeom tg, float *__restrict__ stats,
     float *__restrict__ rgb, float *__restrict__ aux, int gx) {
     constexpr size_t kEst = sizeof(est::StripSmem<TPG>), kGat = sizeof(gat::Smem<S, R, TPG>);
