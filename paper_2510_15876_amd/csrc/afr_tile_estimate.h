@@ -5,10 +5,11 @@
 // slots a single time in rank order and accumulating in FP64: the age-weighted mean luminance
 // (needed by the neighbours' spatial differences), the weighted second moment, the new-half /
 // old-half means that give the temporal difference quotient, and the age sum. Results go to LDS.
-// Phase 2 gives each tile pixel its spatial gradients from the LDS neighbours and folds all
-// per-pixel terms of a tile into one accumulator per lane (pixel e on lane e mod 64); lanes are
-// combined by a fixed-shape butterfly within the wave and in wave order across waves. Luminance
-// variance merges per-pixel (weight, mean, M2) triples with the pairwise form of Welford's update.
+// Phase 2 gives each tile pixel its spatial gradients from the LDS neighbours and reduces a tile
+// with 16 lanes of one wave (so that a wave reduces four tiles at once): lane g folds the pixels
+// e = g, g + 16, ... in increasing order, and the 16 partial accumulators are combined by a fixed
+// tree (g with g + 8, then + 4, + 2, + 1, the lower first). Luminance variance merges per-pixel
+// (weight, mean, M2) triples with the pairwise form of Welford's update.
 //
 // Two drivers share these routines: a strip kernel (afr_estimate_gradients, tiles of edge <= 8)
 // where a workgroup covers a 32-pixel-wide strip of tiles, so that each wave reads whole image rows
@@ -85,6 +86,23 @@ __device__ inline Acc acc_shfl_xor(const Acc &a, int m) {
     o.w = shfl_xor_d(a.w, m);
     o.mean = shfl_xor_d(a.mean, m);
     o.m2 = shfl_xor_d(a.m2, m);
+    return o;
+}
+
+// The accumulator of lane src, in every lane.
+__device__ inline Acc acc_shfl(const Acc &a, int src) {
+    Acc o;
+    o.gx = __shfl(a.gx, src, kWave);
+    o.wx = __shfl(a.wx, src, kWave);
+    o.gy = __shfl(a.gy, src, kWave);
+    o.wy = __shfl(a.wy, src, kWave);
+    o.gt = __shfl(a.gt, src, kWave);
+    o.wt = __shfl(a.wt, src, kWave);
+    o.n = __shfl(a.n, src, kWave);
+    o.sa = __shfl(a.sa, src, kWave);
+    o.w = __shfl(a.w, src, kWave);
+    o.mean = __shfl(a.mean, src, kWave);
+    o.m2 = __shfl(a.m2, src, kWave);
     return o;
 }
 
@@ -216,28 +234,36 @@ __device__ inline Acc pixel_acc(const Region &rg, int h, int rp) {
     return a;
 }
 
-// Folds the pixels e = lane, lane + 64, ... of a bw x bh tile whose top-left region pixel is h0
-// into one accumulator per lane, then butterflies them across the wave (every lane ends with the
-// wave's sum).
-__device__ inline Acc wave_tile_acc(const Region &rg, int h0, int rp, int bw, int bh, int lane,
-                                    int stride) {
+// Lanes that reduce one tile: an aligned segment of a wave.
+constexpr int kGroups = 16;
+
+// Reduces a bw x bh tile whose top-left region pixel is h0 with the calling lane's 16-lane segment
+// (g = lane mod 16): group g folds the pixels e = g, g + 16, ... in increasing order, then the
+// groups are combined by the tree g + 8, g + 4, g + 2, g + 1 (the lower group first). Every lane
+// of the wave must call this together (the segments may reduce different tiles); every lane of a
+// segment receives its tile's sum.
+__device__ inline Acc segment_tile_acc(const Region &rg, int h0, int rp, int bw, int bh, int lane) {
 #pragma clang fp contract(off)
     Acc acc = acc_zero();
-    for (int e = lane; e < bw * bh; e += stride)
+    for (int e = lane % kGroups; e < bw * bh; e += kGroups)
         acc = acc_combine(acc, pixel_acc(rg, h0 + (e / bw) * rp + e % bw, rp));
+    // A lane g < m of the segment combines its value with lane g + m's, which holds the tree over
+    // its own subtree after the previous level; lanes g >= m compute values that are never read.
 #pragma unroll
-    for (int m = kWave / 2; m > 0; m >>= 1) acc = acc_combine(acc, acc_shfl_xor(acc, m));
-    return acc;
+    for (int m = kGroups / 2; m > 0; m >>= 1) acc = acc_combine(acc, acc_shfl_xor(acc, m));
+    return acc_shfl(acc, lane & ~(kGroups - 1));
 }
 
-// Tile statistics from the tile's accumulator, evaluated by all lanes of one wave: the gradient,
-// count and age sums are plain sums, equal in every lane after the butterfly, so lanes 0, 1 and 2
-// take the three cube roots of the extents at once (the same operations as extents()); lane 0's
-// luminance moments are the wave's, and lane 0 writes the stats planes and, if tparams is not NULL,
-// (sx2, sy2, kt2) to tparams.
+// Tile statistics from the tile's accumulator, evaluated by the 16 lanes of a segment (every lane
+// of the wave calls it; `write` false for segments without a tile): lanes g = 0, 1, 2 of the
+// segment take the three cube roots of the extents at once (the same operations as extents()), and
+// lane 0 of the segment writes the stats planes and, if tparams is not NULL, (sx2, sy2, kt2) to
+// tparams.
 __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileGeom &tg, int T,
-                                   int bw, int bh, float *stats, float *tparams, int lane) {
+                                   int bw, int bh, float *stats, float *tparams, int lane,
+                                   bool write) {
 #pragma clang fp contract(off)
+    const int g = lane % kGroups, base = lane - g;
     const double gx = t.wx > 0.0 ? t.gx / t.wx : 0.0;
     const double gy = t.wy > 0.0 ? t.gy / t.wy : 0.0;
     const double gt = t.wt > 0.0 ? t.gt / t.wt : 0.0;
@@ -249,14 +275,17 @@ __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileG
     const double hy = sqrt(gy * gy + p.g_floor * p.g_floor);
     const double u = p.tau * gt;
     double ex2 = 0.0, ey2 = 0.0, kt2 = 0.0;
-    if (u != 0.0) {  // uniform over the wave
-        const double num = lane == 0 ? vol * hy * u : (lane == 1 ? vol * hx * u : u * u);
-        const double den = lane == 0 ? hx * hx : (lane == 1 ? hy * hy : vol * hx * hy);
-        const double c = cbrt(num / den);
-        const double cx = __shfl(c, 0, kWave), cy = __shfl(c, 1, kWave), ck = __shfl(c, 2, kWave);
-        ex2 = cx * cx;
-        ey2 = cy * cy;
-        kt2 = ck * ck;
+    {  // every lane takes part in the shuffles; u is uniform over a segment
+        const double num = g == 0 ? vol * hy * u : (g == 1 ? vol * hx * u : u * u);
+        const double den = g == 0 ? hx * hx : (g == 1 ? hy * hy : vol * hx * hy);
+        const double c = u != 0.0 && g < 3 ? cbrt(num / den) : 0.0;
+        const double cx = __shfl(c, base, kWave), cy = __shfl(c, base + 1, kWave);
+        const double ck = __shfl(c, base + 2, kWave);
+        if (u != 0.0) {
+            ex2 = cx * cx;
+            ey2 = cy * cy;
+            kt2 = ck * ck;
+        }
     }
     const double zx = p.sigma * p.sigma * ex2, zy = p.sigma * p.sigma * ey2;
     const double n2 = p.e_min * p.e_min;
@@ -269,7 +298,7 @@ __device__ inline void tile_finish(const Acc &t, const EstParams &p, const TileG
         sx2 = n2 + (isinf(zx) ? m2 : zx * m2 / (m2 + zx));
         sy2 = n2 + (isinf(zy) ? m2 : zy * m2 / (m2 + zy));
     }
-    if (lane != 0) return;
+    if (g != 0 || !write) return;
     const int nt = tg.nt;
     stats[AFR_STAT_GX * nt + T] = (float)gx;
     stats[AFR_STAT_GY * nt + T] = (float)gy;
@@ -401,7 +430,6 @@ struct Smem {
     static constexpr int kHalo = (TB + 2) * (TB + 2);
     double lbar[kHalo], om[kHalo], gt[kHalo], sa[kHalo], m2[kHalo];
     int n[kHalo];
-    Acc wave[256 / kWave];
 };
 
 // Evaluates tile T (edge tg.tile <= TB) with the calling workgroup (blockDim.x threads, a multiple
@@ -420,14 +448,10 @@ __device__ void estimate_tile(const BufView<S> &v, const EstParams &p, const Til
     // one wave, keeps its register count (and so its waves per SIMD) down (3.86 -> 3.77 ms per batch)
     region_moments<S, 2, 4>(v, p, rg, i0 - 1, j0 - 1, rw, rw * rh);
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const Acc acc = wave_tile_acc(rg, rw + 1, rw, bw, bh, threadIdx.x, blockDim.x);
-    if (lane == 0) sm.wave[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x < kWave) {  // the first wave, every lane with the same sum
-        Acc t = sm.wave[0];
-        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) t = acc_combine(t, sm.wave[w]);
-        tile_finish(t, p, tg, T, bw, bh, stats, tparams, lane);
+    if (threadIdx.x < kWave) {  // the first wave; its first segment's result is written
+        const int lane = threadIdx.x;
+        const Acc t = segment_tile_acc(rg, rw + 1, rw, bw, bh, lane);
+        tile_finish(t, p, tg, T, bw, bh, stats, tparams, lane, lane < kGroups);
     }
     __syncthreads();  // the LDS scratch may be reused by the caller after this point
 }
@@ -455,9 +479,10 @@ struct StripSmem {
 __host__ __device__ inline int strip_tiles(int B, int tiles) { return 8 * tiles / B; }
 
 // Evaluates the tiles tx0 .. tx0 + strip_tiles(B, TILES) - 1 of tile row ty with a 64 TILES-thread
-// workgroup. Each tile is reduced by one wave in the per-tile routine's order (pixel e on lane e), so
-// the statistics do not depend on TILES. If tparams is not NULL (LDS), wave t's lane 0 also stores
-// the (sx2, sy2, kt2) of tile tx0 + t there, visible after the caller's next barrier.
+// workgroup. Tile t of the strip is reduced by segment t mod 4 of wave (t / 4) mod TILES, in the
+// per-tile routine's order, so the statistics do not depend on TILES or on which wave reduces a
+// tile. If tparams is not NULL (LDS), the (sx2, sy2, kt2) of tile tx0 + t are also stored at
+// tparams + 3 t, visible after the caller's next barrier.
 template <typename S, int TILES>
 __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const TileGeom &tg, int tx0,
                                int ty, float *stats, StripSmem<TILES> &sm, float *tparams) {
@@ -471,11 +496,15 @@ __device__ void estimate_strip(const BufView<S> &v, const EstParams &p, const Ti
     region_moments<S, ST::ITEMS, (std::is_same<S, __half>::value ? 4 : 2)>(v, p, rg, i0 - 1, j0 - 1, rp, rp * (sh + 2));
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int t = wid; t < ntile; t += ST::THREADS / kWave) {
-        const int bw = min(B, v.width - (i0 + t * B)), bh = sh;
-        const Acc acc = wave_tile_acc(rg, rp + 1 + t * B, rp, bw, bh, lane, kWave);
-        tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + t, bw, bh, stats,
-                    tparams ? tparams + 3 * t : nullptr, lane);
+    constexpr int kSeg = kWave / kGroups;  // tiles per wave and round
+    for (int t0 = wid * kSeg; t0 < ntile; t0 += TILES * kSeg) {  // uniform over the wave
+        const int t = t0 + lane / kGroups;
+        const bool has = t < ntile;
+        const int tt = has ? t : t0;  // a segment without a tile repeats the round's first (unused)
+        const int bw = min(B, v.width - (i0 + tt * B)), bh = sh;
+        const Acc acc = segment_tile_acc(rg, rp + 1 + tt * B, rp, bw, bh, lane);
+        tile_finish(acc, p, tg, ty * tg.tiles_x + tx0 + tt, bw, bh, stats,
+                    tparams ? tparams + 3 * tt : nullptr, lane, has);
     }
 }
 
