@@ -388,16 +388,19 @@ __global__ __launch_bounds__(RegionGeom<R>::ITEMS *kWave) void k_bwd_tile(
     constexpr int RW = G::RW, NP = G::NP, NM = G::NM, NW = G::ITEMS;
     // (g', k') of the tile's pixels on a grid padded by 2R zeros on every side (tile-local rows and
     // columns -2R .. 8 + 2R - 1): a slot reads its 2R+1 x 2R+1 pixels at fixed offsets, and pixels
-    // outside the tile (or the image) contribute nothing without a test
-    constexpr int GP = kTB + 4 * R;
-    __shared__ float4 s_gk[GP * GP];
+    // outside the tile (or the image) contribute nothing without a test. Rows are GP entries apart
+    // with GP = RW (mod 16): the lanes of a wave (slots in row-major order, RW per region row) then
+    // read consecutive 16-byte entries as far as the LDS banks are concerned, without conflicts.
+    constexpr int GW = kTB + 4 * R;
+    constexpr int GP = GW + ((RW - GW) % 16 + 16) % 16;
+    __shared__ float4 s_gk[GW * GP];
     __shared__ double s_red[2][NW];
     const int T = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = T % tg.tiles_x, ty = T / tg.tiles_x;
     const int W = v.width, H = v.height, K = v.k;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const size_t hw = (size_t)W * H;
-    for (int e = tid; e < GP * GP; e += NW * kWave) {
+    for (int e = tid; e < GW * GP; e += NW * kWave) {
         const int li = e % GP - 2 * R, lj = e / GP - 2 * R;
         const int i = tx * kTB + li, j = ty * kTB + lj;
         const bool inside = li >= 0 && li < kTB && lj >= 0 && lj < kTB && i < W && j < H;
