@@ -70,6 +70,8 @@ def _args():
                          "counter_collection.csv files (one pass each) and exit; the command that "
                          "made them goes in --summary-command")
     ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
+    ap.add_argument("--summary-workload", default="640x480 K=16 FP16 workload",
+                    help="workload named in the first line of a counter summary")
     ap.add_argument("--summary-kernels",
                     default=r"^k_(bin_|scan_|forward<__half,2,|gather<__half,[12],4>|estimate_strip<__half>)",
                     help="regular expression of the kernels a counter summary lists")
@@ -131,7 +133,7 @@ def pmc_summary(fetch_csv, write_csv, command, copy_kib=262144):
     return "\n".join(out)
 
 
-def counter_summary(csvs, command, radius=2, kernels=r"^k_"):
+def counter_summary(csvs, command, radius=2, kernels=r"^k_", workload="640x480 K=16 FP16 workload"):
     """Per-kernel averages (per dispatch) of every SQ/TCC counter found in the given rocprofv3
     counter-collection CSVs, and for the gather kernels the per-pair and per-cycle ratios the design
     notes quote: VALU wave-instructions per (slot, pixel) pair-wave (a pair-wave is 64 pairs), LDS
@@ -152,7 +154,7 @@ def counter_summary(csvs, command, radius=2, kernels=r"^k_"):
                       minlength=W * H)
     count = np.minimum(cnt, K).reshape(H, W)
     pairs = {r: gather_pairs(count, r) for r in (1, 2)}
-    out = ["# rocprofv3 counters per dispatch (average over dispatches), 640x480 K=16 FP16 workload",
+    out = ["# rocprofv3 counters per dispatch (average over dispatches), " + workload,
            "# command (one rocprofv3 --pmc pass per counter group): " + command,
            "# (slot, pixel) pairs of the gather: R=1 %d, R=2 %d" % (pairs[1], pairs[2]),
            "# kernel | counter | mean per dispatch | dispatches"]
@@ -347,7 +349,7 @@ def main():
         return
     if args.counter_summary:
         print(counter_summary(args.counter_summary, args.summary_command, args.radius,
-                              args.summary_kernels))
+                              args.summary_kernels, args.summary_workload))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU layout "
