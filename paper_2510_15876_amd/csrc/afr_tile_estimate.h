@@ -153,9 +153,9 @@ __device__ inline double age_weight(double alpha, double a) {
 #pragma clang fp contract(off)
     const double x = alpha * a * 1.4426950408889634;
     const double n = floor(x);
-    const int e = (int)fmin(fmax(n, -2000.0), 2000.0);
+    const int e = (int)fmin(fmax(-n, -2000.0), 2000.0);  // -n, clamped
     // n - x lies in (-1, 0]: the hardware exponential needs no range handling there
-    return ldexp((double)__builtin_amdgcn_exp2f((float)(n - x)), -e);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(n - x)), e);
 }
 
 // Adds slot k (rank order) of a pixel with n slots: colour (r, g, b) and stored age field ta. The
@@ -174,10 +174,13 @@ __device__ inline void pix_add(PixAcc &m, const EstParams &p, S r, S g, S b, S t
     m.s1 += wl;
     m.s2 = fma(wl, L, m.s2);
     m.sa += a;
+    // the half is chosen by exact 0/1 multipliers: fma(1, x, s) = s + x and fma(0, x, s) = s (the
+    // sums start at +0 and are never -0), three fused multiply-adds instead of selects and adds
     const bool newer = k < (n + 1) / 2;
-    m.ln += newer ? L : 0.0;
-    m.lo += newer ? 0.0 : L;
-    m.an += newer ? a : 0.0;
+    const double in_new = newer ? 1.0 : 0.0, in_old = newer ? 0.0 : 1.0;
+    m.ln = fma(in_new, L, m.ln);
+    m.lo = fma(in_old, L, m.lo);
+    m.an = fma(in_new, a, m.an);
 }
 
 // Region scratch: per-pixel (count, Omega, mean luminance, temporal gradient or -1, age sum, M2)
