@@ -16,8 +16,8 @@ constexpr int max_group(int R) { return R <= 2 ? 4 : 2; }
 
 // Waves per SIMD the kernels are compiled for. Four tiles per workgroup at R <= 2 with binary16
 // storage: five (at most 96 VGPRs), so that five workgroups share a CU (their LDS, 30 KiB each, fits)
-// and the 1200 workgroups of a 640x480 image run in one round; the fused kernel, whose statistics
-// phase alone would take 104 VGPRs, gives up one spilled register for it (forward 82 -> 77 us).
+// and the 1200 workgroups of a 640x480 image run in one round; the fused kernel, which unbounded
+// took 104 VGPRs (four waves, two rounds), fits without spills (forward 82 -> 77 us when bounded).
 // Binary32 storage: four (at most 128 VGPRs), one round for 1024 workgroups (512x512).
 template <typename S, int R>
 constexpr int waves_per_simd() { return R <= 2 ? (std::is_same<S, __half>::value ? 5 : 4) : 1; }
