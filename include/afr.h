@@ -488,6 +488,26 @@ int32_t afr_batch_tiles_per_wave(const afr_batch *plan);
 
 void afr_batch_destroy(afr_batch *plan);
 
+/* The whole batch in one call, without a plan: the same validation and result as afr_batch_create
+ * followed by afr_batch_run, bit for bit, with the item table written to the workspace by small
+ * kernels that carry it in their arguments. The call enqueues only kernels (no allocation, host
+ * synchronisation, copy or memset), so it can be captured into a HIP graph with the items' values
+ * at capture time; a replay writes those values again.
+ *   items, n   as afr_batch_create (host memory, read during the call only)
+ *   tune       tiles_per_wave: 1, 2 or 4, or 0 for the library's choice (the shape afr_batch_tune
+ *              last found fastest for this precision and radius in this process, else the
+ *              default); ws, ws_bytes: device workspace of afr_batch_workspace_bytes(n) bytes, which
+ *              must not be in use by another batch while the call's kernels run
+ * Errors: as afr_batch_create; AFR_E_INVALID for a NULL tune or workspace, AFR_E_NOMEM for a small
+ * one. */
+typedef struct afr_tune {
+    int32_t tiles_per_wave;
+    void *ws;
+    size_t ws_bytes;
+} afr_tune;
+afr_status afr_batch_reconstruct(const afr_batch_item *items, int32_t n, const afr_tune *tune,
+                                 hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

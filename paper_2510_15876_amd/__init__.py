@@ -49,6 +49,11 @@ class _Samples(ctypes.Structure):
                 ("n", ctypes.c_int64), ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("tiles_per_wave", ctypes.c_int32), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
 class _Crosshairs(ctypes.Structure):
     _fields_ = [("centre", ctypes.c_void_p), ("xm", ctypes.c_void_p), ("xp", ctypes.c_void_p),
                 ("ym", ctypes.c_void_p), ("yp", ctypes.c_void_p), ("old", ctypes.c_void_p),
@@ -161,6 +166,8 @@ def library():
     lib.afr_batch_tune.argtypes = [vp, vp, P(ctypes.c_int32), P(ctypes.c_float)]
     lib.afr_batch_tiles_per_wave.restype = ctypes.c_int32
     lib.afr_batch_tiles_per_wave.argtypes = [vp]
+    lib.afr_batch_reconstruct.restype = st
+    lib.afr_batch_reconstruct.argtypes = [P(_BatchItem), ctypes.c_int32, P(_Tune), vp]
     lib.afr_batch_destroy.restype = None
     lib.afr_batch_destroy.argtypes = [vp]
     lib.afr_sampler_select_noalloc.restype = st
@@ -753,9 +760,22 @@ class Batch:
         _check(lib.afr_batch_create(arr, n, int(tiles_per_wave), _ptr(self.ws), nbytes,
                                     ctypes.byref(plan)), "afr_batch_create")
         self._plan = plan
+        self._arr = arr
 
     def run(self, stream=None):
         _check(library().afr_batch_run(self._plan, _stream(stream)), "afr_batch_run")
+
+    def reconstruct(self, tiles_per_wave: int = 0, stream=None):
+        """The same batch through the plan-free call (afr_batch_reconstruct): the item table is
+        written into a workspace of its own by the call's kernels, so this can be captured."""
+        lib = library()
+        n = len(self.items)
+        nbytes = lib.afr_batch_workspace_bytes(n)
+        if getattr(self, "_ws1", None) is None:
+            self._ws1 = torch.empty(nbytes, dtype=torch.uint8, device=self.ws.device)
+        t = _Tune(int(tiles_per_wave), _ptr(self._ws1).value, nbytes)
+        _check(lib.afr_batch_reconstruct(self._arr, n, ctypes.byref(t), _stream(stream)),
+               "afr_batch_reconstruct")
 
     def tune(self, stream=None):
         best, ms = ctypes.c_int32(0), ctypes.c_float(0.0)

@@ -131,6 +131,130 @@ bool shape_supported(int tpw, int R) { return tpw == 1 || tpw == 2 || (tpw == 4 
 size_t table_bytes(int n) { return align_up((size_t)n * sizeof(DevItem)); }
 size_t first_bytes(int n) { return align_up((size_t)(n + 1) * sizeof(int)); }
 
+// Host image of a validated batch: the item table in work order (larger items first, so that the
+// last items taken are the smallest, which evens the tail) and, per launch shape, the first work
+// item of every batch item (with the total at [n]).
+struct HostPlan {
+    int n = 0, precision = 0, radius = 0, tpw = 0;
+    std::vector<DevItem> table;
+    std::vector<int> first[3];
+};
+
+afr_status make_host_plan(const afr_batch_item *items, int32_t n, int32_t tiles_per_wave,
+                          int default_tpw, HostPlan &hp) {
+    if (tiles_per_wave != 0 && tiles_per_wave != 1 && tiles_per_wave != 2 && tiles_per_wave != 4)
+        return AFR_E_RANGE;
+    const int R = items[0].params.radius, prec = items[0].buf.precision;
+    for (int i = 0; i < n; ++i) {
+        const afr_batch_item &it = items[i];
+        afr_status st = check_buffer(&it.buf);
+        if (st == AFR_OK) st = check_params(&it.params, &it.buf);
+        if (st == AFR_OK) st = check_stats(&it.stats, &it.buf, &it.params);
+        if (st != AFR_OK) return st;
+        if (!it.rgb) return AFR_E_INVALID;
+        if (it.params.tile != 8 || it.params.radius != R || it.buf.precision != prec)
+            return AFR_E_UNSUPPORTED;
+    }
+    const int tpw = tiles_per_wave == 0 ? default_tpw : tiles_per_wave;
+    if (!shape_supported(tpw, R)) return AFR_E_RANGE;
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double wa = (double)items[a].buf.width * items[a].buf.height * items[a].buf.k;
+        const double wb = (double)items[b].buf.width * items[b].buf.height * items[b].buf.k;
+        return wa > wb;
+    });
+    hp.n = n;
+    hp.precision = prec;
+    hp.radius = R;
+    hp.tpw = tpw;
+    hp.table.assign(n, DevItem{});
+    for (int s = 0; s < 3; ++s) hp.first[s].assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) {
+        const afr_batch_item &it = items[order[j]];
+        DevItem &d = hp.table[j];
+        d.ox = it.buf.ox;
+        d.oy = it.buf.oy;
+        d.ta = it.buf.tage;
+        d.r = it.buf.r;
+        d.g = it.buf.g;
+        d.b = it.buf.b;
+        d.count = it.buf.count;
+        d.width = it.buf.width;
+        d.height = it.buf.height;
+        d.k = it.buf.k;
+        d.t_ref = it.buf.t_ref;
+        d.tg = geom_of(it.stats);
+        d.stats = it.stats.data;
+        d.rgb = it.rgb;
+        d.aux = it.aux;
+        d.ep = est_params(it.buf, it.params);
+        d.tp = gat::TiledParams{it.params.t_now, it.params.t_now - it.buf.t_ref};
+        for (int s = 0; s < 3; ++s) {
+            const int gx = (d.tg.tiles_x + kShapes[s] - 1) / kShapes[s];
+            const int64_t next = (int64_t)hp.first[s][j] + (int64_t)gx * d.tg.tiles_y;
+            if (next >= (int64_t(1) << 31)) return AFR_E_RANGE;
+            hp.first[s][j + 1] = (int)next;
+        }
+    }
+    return AFR_OK;
+}
+
+// Resident workgroups of the batch kernel for (precision, radius, shape), from the occupancy
+// query, kept per device.
+std::mutex g_grid_mu;
+std::map<std::tuple<int, int, int, int>, int> g_resident;
+
+hipError_t resident_groups(int prec, int R, int s, int *out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_grid_mu);
+    const auto key = std::make_tuple(dev, prec, R, s);
+    const auto it = g_resident.find(key);
+    if (it != g_resident.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])),
+            kWave * kShapes[s], 0);
+    if (e != hipSuccess) return e;
+    *out = g_resident[key] = std::max(1, per_cu) * std::max(1, cus);
+    return hipSuccess;
+}
+
+// Launch shape that afr_batch_tune last found fastest, per (precision, radius).
+std::mutex g_btune_mu;
+std::map<std::pair<int, int>, int> g_btune;
+
+// Writes words to device memory from a kernel's arguments (passed by value, so the launch can be
+// captured into a graph with the data in it).
+constexpr int kArgWords = 480;
+struct WordBlock {
+    uint32_t w[kArgWords];
+};
+__global__ void k_put_words(uint32_t *__restrict__ dst, WordBlock b, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = b.w[i];
+}
+
+hipError_t put_bytes(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    static_assert(sizeof(DevItem) % 4 == 0, "the item table is whole words");
+    const uint32_t *w = static_cast<const uint32_t *>(src);
+    uint32_t *d = static_cast<uint32_t *>(dst);
+    const size_t nw = bytes / 4;
+    for (size_t o = 0; o < nw; o += kArgWords) {
+        WordBlock b;
+        const int m = (int)std::min<size_t>(kArgWords, nw - o);
+        std::copy(w + o, w + o + m, b.w);
+        k_put_words<<<1, 256, 0, st>>>(d + o, b, m);
+    }
+    return hipGetLastError();
+}
+
 // ---- single-frame tuner cache: (width, height, k, precision, radius) -> tiles per wave ---------
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, int> g_tune;
@@ -175,95 +299,76 @@ afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tile
     if (!items || n < 1 || !ws || !plan) return AFR_E_INVALID;
     *plan = nullptr;
     if (ws_bytes < afr_batch_workspace_bytes(n)) return AFR_E_NOMEM;
-    if (tiles_per_wave != 0 && tiles_per_wave != 1 && tiles_per_wave != 2 && tiles_per_wave != 4)
-        return AFR_E_RANGE;
-    const int R = items[0].params.radius, prec = items[0].buf.precision;
-    for (int i = 0; i < n; ++i) {
-        const afr_batch_item &it = items[i];
-        afr_status st = check_buffer(&it.buf);
-        if (st == AFR_OK) st = check_params(&it.params, &it.buf);
-        if (st == AFR_OK) st = check_stats(&it.stats, &it.buf, &it.params);
-        if (st != AFR_OK) return st;
-        if (!it.rgb) return AFR_E_INVALID;
-        if (it.params.tile != 8 || it.params.radius != R || it.buf.precision != prec)
-            return AFR_E_UNSUPPORTED;
-    }
-    const int tpw = tiles_per_wave == 0 ? (R <= 2 ? 4 : 2) : tiles_per_wave;
-    if (!shape_supported(tpw, R)) return AFR_E_RANGE;
-
-    // Larger items first: the last items taken are the smallest, which evens the tail.
-    std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const double wa = (double)items[a].buf.width * items[a].buf.height * items[a].buf.k;
-        const double wb = (double)items[b].buf.width * items[b].buf.height * items[b].buf.k;
-        return wa > wb;
-    });
-    std::vector<DevItem> table(n);
-    std::vector<int> first[3];
-    for (int s = 0; s < 3; ++s) first[s].assign(n + 1, 0);
-    for (int j = 0; j < n; ++j) {
-        const afr_batch_item &it = items[order[j]];
-        DevItem &d = table[j];
-        d.ox = it.buf.ox;
-        d.oy = it.buf.oy;
-        d.ta = it.buf.tage;
-        d.r = it.buf.r;
-        d.g = it.buf.g;
-        d.b = it.buf.b;
-        d.count = it.buf.count;
-        d.width = it.buf.width;
-        d.height = it.buf.height;
-        d.k = it.buf.k;
-        d.t_ref = it.buf.t_ref;
-        d.tg = geom_of(it.stats);
-        d.stats = it.stats.data;
-        d.rgb = it.rgb;
-        d.aux = it.aux;
-        d.ep = est_params(it.buf, it.params);
-        d.tp = gat::TiledParams{it.params.t_now, it.params.t_now - it.buf.t_ref};
-        for (int s = 0; s < 3; ++s) {
-            const int gx = (d.tg.tiles_x + kShapes[s] - 1) / kShapes[s];
-            const int64_t next = (int64_t)first[s][j] + (int64_t)gx * d.tg.tiles_y;
-            if (next >= (int64_t(1) << 31)) return AFR_E_RANGE;
-            first[s][j + 1] = (int)next;
-        }
-    }
+    HostPlan hp;
+    const afr_status st = make_host_plan(items, n, tiles_per_wave,
+                                         items[0].params.radius <= 2 ? 4 : 2, hp);
+    if (st != AFR_OK) return st;
     char *p = static_cast<char *>(ws);
     afr_batch *b = new (std::nothrow) afr_batch;
     if (!b) return AFR_E_NOMEM;
     b->n = n;
-    b->precision = prec;
-    b->radius = R;
-    b->tpw = tpw;
+    b->precision = hp.precision;
+    b->radius = hp.radius;
+    b->tpw = hp.tpw;
     b->d_items = reinterpret_cast<DevItem *>(p);
     p += table_bytes(n);
     for (int s = 0; s < 3; ++s) {
         b->d_first[s] = reinterpret_cast<int *>(p);
         p += first_bytes(n);
-        b->total[s] = first[s][n];
+        b->total[s] = hp.first[s][n];
     }
     b->d_counter = reinterpret_cast<int *>(p);
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipSuccess;
     for (int s = 0; s < 3 && e == hipSuccess; ++s) {
-        if (!shape_supported(kShapes[s], R)) continue;
-        int per_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])),
-            kWave * kShapes[s], 0);
-        b->grid[s] = std::max(1, std::min(b->total[s], std::max(1, per_cu) * cus));
+        if (!shape_supported(kShapes[s], hp.radius)) continue;
+        int res = 1;
+        e = resident_groups(hp.precision, hp.radius, s, &res);
+        b->grid[s] = std::max(1, std::min(b->total[s], res));
     }
-    if (e == hipSuccess) e = hipMemcpy(b->d_items, table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_items, hp.table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
     for (int s = 0; s < 3 && e == hipSuccess; ++s)
-        e = hipMemcpy(b->d_first[s], first[s].data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->d_first[s], hp.first[s].data(), (n + 1) * sizeof(int),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         delete b;
         return AFR_E_DEVICE;
     }
     *plan = b;
     return AFR_OK;
+}
+
+afr_status afr_batch_reconstruct(const afr_batch_item *items, int32_t n, const afr_tune *tune,
+                                 hipStream_t stream) {
+    if (!items || n < 1 || !tune || !tune->ws) return AFR_E_INVALID;
+    if (tune->ws_bytes < afr_batch_workspace_bytes(n)) return AFR_E_NOMEM;
+    int def = items[0].params.radius <= 2 ? 4 : 2;
+    {
+        std::lock_guard<std::mutex> lock(g_btune_mu);
+        const auto it = g_btune.find({items[0].buf.precision, items[0].params.radius});
+        if (it != g_btune.end()) def = it->second;
+    }
+    HostPlan hp;
+    const afr_status st = make_host_plan(items, n, tune->tiles_per_wave, def, hp);
+    if (st != AFR_OK) return st;
+    const int s = shape_index(hp.tpw);
+    int res = 1;
+    if (resident_groups(hp.precision, hp.radius, s, &res) != hipSuccess) return AFR_E_DEVICE;
+    const int total = hp.first[s][n];
+    char *p = static_cast<char *>(tune->ws);
+    DevItem *d_items = reinterpret_cast<DevItem *>(p);
+    p += table_bytes(n);
+    int *d_first = reinterpret_cast<int *>(p);  // this shape's first items only
+    p += 3 * first_bytes(n);
+    int *d_counter = reinterpret_cast<int *>(p);
+    hipError_t e = put_bytes(d_items, hp.table.data(), n * sizeof(DevItem), stream);
+    if (e == hipSuccess) e = put_bytes(d_first, hp.first[s].data(), (n + 1) * sizeof(int), stream);
+    if (e != hipSuccess) return AFR_E_DEVICE;
+    k_batch_reset<<<1, 1, 0, stream>>>(d_counter);
+    KernelFn fn = batch_kernel(hp.precision, hp.radius, hp.tpw);
+    hipLaunchKernelGGL(fn, dim3(std::max(1, std::min(total, res))), dim3(kWave * hp.tpw), 0, stream,
+                       d_items, n, d_first, d_counter);
+    return hipGetLastError() == hipSuccess ? AFR_OK : AFR_E_DEVICE;
 }
 
 afr_status afr_batch_run(const afr_batch *b, hipStream_t stream) {
@@ -308,6 +413,10 @@ afr_status afr_batch_tune(afr_batch *b, hipStream_t stream, int32_t *best_tpw, f
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->tpw = st == AFR_OK ? best : keep;
+    if (st == AFR_OK) {
+        std::lock_guard<std::mutex> lock(g_btune_mu);
+        g_btune[{b->precision, b->radius}] = best;
+    }
     if (st == AFR_OK) {
         if (best_tpw) *best_tpw = best;
         if (best_ms) *best_ms = best_t;

@@ -301,3 +301,28 @@ def test_batch_plan_validation(afr):
     assert lib.afr_batch_tune(None, None, None, None) == 1
     assert lib.afr_batch_tiles_per_wave(None) == 0
     lib.afr_batch_destroy(None)
+
+
+def test_batch_reconstruct_validation(afr):
+    """The plan-free batch call (afr_batch_reconstruct) validates the items and its tune struct on
+    the host before it enqueues anything, with afr_batch_create's status codes."""
+    lib = afr.library()
+    ws_ok = lib.afr_batch_workspace_bytes(2)
+
+    def call(items, tpw=0, ws=0x1000, nbytes=ws_ok, tune=True):
+        arr = (afr._BatchItem * max(1, len(items)))(*items)
+        t = afr._Tune(tpw, ws, nbytes)
+        return lib.afr_batch_reconstruct(arr if items else None, len(items),
+                                         ctypes.byref(t) if tune else None, None)
+
+    good = [_batch_item(afr), _batch_item(afr, w=24, h=16)]
+    assert call([]) == 1                                     # no items
+    assert call(good, tune=False) == 1                       # no tune struct
+    assert call(good, ws=None) == 1                          # no workspace
+    assert call(good, nbytes=ws_ok - 1) == 4                 # workspace too small
+    assert call(good, tpw=3) == 2                            # launch shape outside 0, 1, 2, 4
+    assert call([_batch_item(afr), _batch_item(afr, k=0)]) == 2           # an invalid buffer
+    assert call([_batch_item(afr, tile=4)]) == 5             # statistics tiles other than 8 px
+    assert call([_batch_item(afr), _batch_item(afr, radius=1)]) == 5      # mixed radius
+    assert call([_batch_item(afr), _batch_item(afr, prec=1)]) == 5        # mixed precision
+    assert call([_batch_item(afr, radius=3)], tpw=4) == 2    # four tiles per group need R <= 2

@@ -123,6 +123,49 @@ def test_graph_capture_replays_match_eager():
     batch.close()
 
 
+def test_plan_free_call_equals_plan_and_replays():
+    """afr_batch_reconstruct (no plan: the item table written by the call's own kernels) gives the
+    plan's outputs bit for bit for every launch shape, on a side stream too, and replays of a graph
+    that captured it (with eager work between them) give them again."""
+    torch = torch_mod()
+    afr = afr_mod()
+    bufs = _build_all(_items(n=7, seed=29))
+    batch = afr.Batch(bufs)
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [r.clone() for r in batch.rgb] + [s.clone() for s in batch.stats]
+    eager += [a.clone() for a in batch.aux]
+    outs = lambda: list(batch.rgb) + list(batch.stats) + list(batch.aux)
+    for tpw in (0, 1, 2, 4):
+        print(f"plan-free batch, tiles per wave {tpw}", flush=True)
+        for o in outs():
+            o.fill_(float("nan"))
+        batch.reconstruct(tiles_per_wave=tpw)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(eager, outs())), tpw
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.reconstruct(tiles_per_wave=2, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(eager, outs()))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.reconstruct(tiles_per_wave=4)
+    for rep in range(3):
+        for o in outs():
+            o.fill_(float("nan"))
+        batch.run()  # eager work between replays, which also rewrites the outputs
+        for o in outs():
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(eager, outs())), rep
+    batch.close()
+
+
 @pytest.mark.timeout(900)
 def test_c5_recipe_equals_separate_calls_and_reference():
     """The C5 batch as configured: 64 items drawn from {128x128, 320x240, 640x480, 1024x768} x
