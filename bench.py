@@ -353,7 +353,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU layout "
-              "is a design note, not part of this build)", file=sys.stderr)
+              "is described in the design notes and not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 

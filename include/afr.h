@@ -45,7 +45,7 @@ typedef enum afr_status {
     AFR_E_RANGE = 2,        /* a size or parameter outside its documented range                 */
     AFR_E_DEVICE = 3,       /* a HIP launch or runtime call failed                              */
     AFR_E_NOMEM = 4,        /* the caller's workspace is smaller than the query returned        */
-    AFR_E_UNSUPPORTED = 5   /* a valid request that this build does not implement               */
+    AFR_E_UNSUPPORTED = 5   /* a valid request that this library does not implement             */
 } afr_status;
 
 /* Storage precision of a deep buffer. Arithmetic is FP32 (FP64 in the statistics) either way. */
