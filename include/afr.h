@@ -444,14 +444,14 @@ afr_status afr_reconstruct_backward(const afr_deep_buffer *buf, const afr_tile_s
 
 /* ---------------------------------------------------------------------------------------------
  * Batched reconstruction: many independent estimate + gather pipelines of uneven size in one
- * persistent launch. Work items are (item, group of tiles_per_wave tiles); each work item
- * estimates its own tiles' statistics and then gathers them, so items never wait on each other.
- * Workgroups take items from a counter in the workspace (reset by a small kernel in the same
- * submission), larger items first. Outputs are bit-identical to afr_estimate_gradients followed by
- * afr_reconstruct on each item, for every tiles_per_wave.
+ * launch. Work items are (item, group of tiles_per_wave tiles), one workgroup each, numbered with
+ * the larger items first; each work item estimates its own tiles' statistics and then gathers them,
+ * so items never wait on each other. Outputs are bit-identical to afr_estimate_gradients followed
+ * by afr_reconstruct on each item, for every tiles_per_wave.
  *
  * Restrictions: every item uses 8 px statistics tiles, the same radius and the same precision;
- * other batches return AFR_E_UNSUPPORTED. Items must not share output memory.
+ * other batches return AFR_E_UNSUPPORTED. Items must not share output memory. At most 2^24 work
+ * items in all (AFR_E_RANGE).
  * ------------------------------------------------------------------------------------------- */
 typedef struct afr_batch_item {
     afr_deep_buffer buf;   /* a built deep buffer                                               */
@@ -463,7 +463,7 @@ typedef struct afr_batch_item {
 
 typedef struct afr_batch afr_batch; /* opaque host-side plan */
 
-/* Device workspace for a batch of n items (item table, work offsets, counter). */
+/* Device workspace for a batch of n items (item table, first work item of each item). */
 size_t afr_batch_workspace_bytes(int32_t n_items);
 
 /* Validates the items, orders them by work, uploads the item table to ws (a blocking host-to-device
@@ -473,7 +473,7 @@ size_t afr_batch_workspace_bytes(int32_t n_items);
 afr_status afr_batch_create(const afr_batch_item *items, int32_t n_items, int32_t tiles_per_wave,
                             void *ws, size_t ws_bytes, afr_batch **plan);
 
-/* Enqueues the whole batch (counter reset + persistent kernel) on the stream. Performs no host
+/* Enqueues the whole batch (one kernel launch) on the stream. Performs no host
  * synchronisation, allocation, memset or copy, so it can be captured into a HIP graph and replayed;
  * replays of one plan must not overlap. */
 afr_status afr_batch_run(const afr_batch *plan, hipStream_t stream);

@@ -1,12 +1,14 @@
-// Batched reconstruction in one persistent launch, and the launch-shape tuner.
+// Batched reconstruction in one launch, and the launch-shape tuner.
 //
-// A work item is (batch item, group of TPG statistics tiles in one tile row). The workgroup that
-// takes it first evaluates the statistics of its own tiles (est::estimate_strip, the code of
+// A work item is (batch item, group of TPG statistics tiles in one tile row). One workgroup per work
+// item first evaluates the statistics of its own tiles (est::estimate_strip, the code of
 // afr_estimate_gradients) and then gathers them (gat::gather_strip, the code of afr_reconstruct), so
-// no work item depends on another and nothing spins. The grid is sized to the number of resident
-// workgroups; each workgroup loops taking the next item from a counter until the counter passes
-// the last item, which every wave reaches. A one-thread kernel resets the counter before each run,
-// so a run is two kernel launches and nothing else: capturable and replayable.
+// no work item depends on another and nothing spins. Work items are numbered with the larger batch
+// items first and dealt to workgroups in that order (no per-XCD remapping: consecutive work items go
+// to different XCDs, so the XCDs share the large and the small items alike and finish together),
+// so a run is one kernel launch and nothing else: capturable and replayable. (A persistent grid
+// taking items from a counter needed 128 registers and four waves per SIMD; one item per workgroup
+// fits in 96 and five: 2.69 -> 2.17 ms for the 64-item batch.)
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -51,32 +53,21 @@ __device__ inline BufView<S> item_view(const DevItem &d) {
     return v;
 }
 
-__global__ void k_batch_reset(int *counter) { *counter = 0; }
-
-// Waves per SIMD the batch kernel is compiled for: four with binary16 storage at R <= 2 (at most 128
-// VGPRs, a few spilled) instead of the three its registers would allow unbounded, so that more
-// workgroups are resident to hide each other's memory latency; unbounded otherwise (binary32 items
-// would spill about forty registers).
+// Waves per SIMD the batch kernel is compiled for, as the fused single-frame kernel: five with
+// binary16 storage at R <= 2 (at most 96 VGPRs), four with binary32, unbounded at larger radii.
 template <typename S, int R>
-constexpr int batch_waves() { return R <= 2 && std::is_same<S, __half>::value ? 4 : 1; }
+constexpr int batch_waves() { return R <= 2 ? (std::is_same<S, __half>::value ? 5 : 4) : 1; }
 
 template <typename S, int R, int TPG>
 __global__ __launch_bounds__(64 * TPG, (batch_waves<S, R>())) void k_batch(const DevItem *__restrict__ items, int n,
-                                                   const int *__restrict__ first,
-                                                   int *__restrict__ counter) {
+                                                   const int *__restrict__ first) {
     constexpr size_t kEst = sizeof(est::StripSmem<TPG>), kGat = sizeof(gat::Smem<S, R, TPG>);
     __shared__ __align__(16) unsigned char raw[kEst > kGat ? kEst : kGat];
     __shared__ float tparam[3 * TPG];
-    __shared__ int s_item;
     est::StripSmem<TPG> &esm = *reinterpret_cast<est::StripSmem<TPG> *>(raw);
     gat::Smem<S, R, TPG> &gsm = *reinterpret_cast<gat::Smem<S, R, TPG> *>(raw);
-    const int total = first[n];
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int w = s_item;
-        __syncthreads();  // every lane has read s_item before lane 0 may overwrite it
-        if (w >= total) break;
+    {
+        const int w = (int)blockIdx.x;  // the work item; the grid is exactly first[n] workgroups
         int lo = 0, hi = n - 1;  // the item b with first[b] <= w < first[b + 1]
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
@@ -96,11 +87,10 @@ __global__ __launch_bounds__(64 * TPG, (batch_waves<S, R>())) void k_batch(const
         est::estimate_strip<S, TPG>(v, d.ep, d.tg, tx0, ty, d.stats, esm, tparam);
         __syncthreads();
         gat::gather_strip<S, R, TPG>(v, d.tp, d.tg, tx0, ty, gsm, tparam, d.rgb, d.aux);
-        __syncthreads();  // LDS is reused by the next item
     }
 }
 
-using KernelFn = void (*)(const DevItem *, int, const int *, int *);
+using KernelFn = void (*)(const DevItem *, int, const int *);
 
 template <typename S, int R>
 KernelFn kernel_for(int tpw) {
@@ -193,38 +183,11 @@ afr_status make_host_plan(const afr_batch_item *items, int32_t n, int32_t tiles_
         for (int s = 0; s < 3; ++s) {
             const int gx = (d.tg.tiles_x + kShapes[s] - 1) / kShapes[s];
             const int64_t next = (int64_t)hp.first[s][j] + (int64_t)gx * d.tg.tiles_y;
-            if (next >= (int64_t(1) << 31)) return AFR_E_RANGE;
+            if (next >= (int64_t(1) << 24)) return AFR_E_RANGE;  // one workgroup per work item
             hp.first[s][j + 1] = (int)next;
         }
     }
     return AFR_OK;
-}
-
-// Resident workgroups of the batch kernel for (precision, radius, shape), from the occupancy
-// query, kept per device.
-std::mutex g_grid_mu;
-std::map<std::tuple<int, int, int, int>, int> g_resident;
-
-hipError_t resident_groups(int prec, int R, int s, int *out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    std::lock_guard<std::mutex> lock(g_grid_mu);
-    const auto key = std::make_tuple(dev, prec, R, s);
-    const auto it = g_resident.find(key);
-    if (it != g_resident.end()) {
-        *out = it->second;
-        return hipSuccess;
-    }
-    int cus = 0, per_cu = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(batch_kernel(prec, R, kShapes[s])),
-            kWave * kShapes[s], 0);
-    if (e != hipSuccess) return e;
-    *out = g_resident[key] = std::max(1, per_cu) * std::max(1, cus);
-    return hipSuccess;
 }
 
 // Launch shape that afr_batch_tune last found fastest, per (precision, radius).
@@ -278,11 +241,9 @@ struct afr_batch {
     int n = 0;
     int precision = 0, radius = 0;
     int tpw = 2;
-    int total[3] = {0, 0, 0};
-    int grid[3] = {0, 0, 0};
+    int total[3] = {0, 0, 0};  // work items (workgroups) per launch shape
     afr::DevItem *d_items = nullptr;
     int *d_first[3] = {nullptr, nullptr, nullptr};
-    int *d_counter = nullptr;
 };
 
 using namespace afr;
@@ -291,7 +252,7 @@ extern "C" {
 
 size_t afr_batch_workspace_bytes(int32_t n) {
     if (n < 1) return 0;
-    return table_bytes(n) + 3 * first_bytes(n) + align_up(sizeof(int));
+    return table_bytes(n) + 3 * first_bytes(n);
 }
 
 afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tiles_per_wave,
@@ -317,16 +278,7 @@ afr_status afr_batch_create(const afr_batch_item *items, int32_t n, int32_t tile
         p += first_bytes(n);
         b->total[s] = hp.first[s][n];
     }
-    b->d_counter = reinterpret_cast<int *>(p);
-    hipError_t e = hipSuccess;
-    for (int s = 0; s < 3 && e == hipSuccess; ++s) {
-        if (!shape_supported(kShapes[s], hp.radius)) continue;
-        int res = 1;
-        e = resident_groups(hp.precision, hp.radius, s, &res);
-        b->grid[s] = std::max(1, std::min(b->total[s], res));
-    }
-    if (e == hipSuccess)
-        e = hipMemcpy(b->d_items, hp.table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(b->d_items, hp.table.data(), n * sizeof(DevItem), hipMemcpyHostToDevice);
     for (int s = 0; s < 3 && e == hipSuccess; ++s)
         e = hipMemcpy(b->d_first[s], hp.first[s].data(), (n + 1) * sizeof(int),
                       hipMemcpyHostToDevice);
@@ -352,32 +304,27 @@ afr_status afr_batch_reconstruct(const afr_batch_item *items, int32_t n, const a
     const afr_status st = make_host_plan(items, n, tune->tiles_per_wave, def, hp);
     if (st != AFR_OK) return st;
     const int s = shape_index(hp.tpw);
-    int res = 1;
-    if (resident_groups(hp.precision, hp.radius, s, &res) != hipSuccess) return AFR_E_DEVICE;
     const int total = hp.first[s][n];
     char *p = static_cast<char *>(tune->ws);
     DevItem *d_items = reinterpret_cast<DevItem *>(p);
     p += table_bytes(n);
     int *d_first = reinterpret_cast<int *>(p);  // this shape's first items only
-    p += 3 * first_bytes(n);
-    int *d_counter = reinterpret_cast<int *>(p);
     hipError_t e = put_bytes(d_items, hp.table.data(), n * sizeof(DevItem), stream);
     if (e == hipSuccess) e = put_bytes(d_first, hp.first[s].data(), (n + 1) * sizeof(int), stream);
     if (e != hipSuccess) return AFR_E_DEVICE;
-    k_batch_reset<<<1, 1, 0, stream>>>(d_counter);
+    if (total == 0) return AFR_OK;  // no tiles at all
     KernelFn fn = batch_kernel(hp.precision, hp.radius, hp.tpw);
-    hipLaunchKernelGGL(fn, dim3(std::max(1, std::min(total, res))), dim3(kWave * hp.tpw), 0, stream,
-                       d_items, n, d_first, d_counter);
+    hipLaunchKernelGGL(fn, dim3(total), dim3(kWave * hp.tpw), 0, stream, d_items, n, d_first);
     return hipGetLastError() == hipSuccess ? AFR_OK : AFR_E_DEVICE;
 }
 
 afr_status afr_batch_run(const afr_batch *b, hipStream_t stream) {
     if (!b) return AFR_E_INVALID;
     const int s = shape_index(b->tpw);
-    k_batch_reset<<<1, 1, 0, stream>>>(b->d_counter);
+    if (b->total[s] == 0) return AFR_OK;  // no tiles at all
     KernelFn fn = batch_kernel(b->precision, b->radius, b->tpw);
-    hipLaunchKernelGGL(fn, dim3(b->grid[s]), dim3(kWave * b->tpw), 0, stream, b->d_items, b->n,
-                       b->d_first[s], b->d_counter);
+    hipLaunchKernelGGL(fn, dim3(b->total[s]), dim3(kWave * b->tpw), 0, stream, b->d_items, b->n,
+                       b->d_first[s]);
     return hipGetLastError() == hipSuccess ? AFR_OK : AFR_E_DEVICE;
 }
 
