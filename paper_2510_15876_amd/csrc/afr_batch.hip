@@ -4,11 +4,11 @@
 // item first evaluates the statistics of its own tiles (est::estimate_strip, the code of
 // afr_estimate_gradients) and then gathers them (gat::gather_strip, the code of afr_reconstruct), so
 // no work item depends on another and nothing spins. Work items are numbered with the larger batch
-// items first and dealt to workgroups in that order (no per-XCD remapping: consecutive work items go
-// to different XCDs, so the XCDs share the large and the small items alike and finish together),
-// so a run is one kernel launch and nothing else: capturable and replayable. (A persistent grid
-// taking items from a counter needed 128 registers and four waves per SIMD; one item per workgroup
-// fits in 96 and five: 2.69 -> 2.17 ms for the 64-item batch.)
+// items first and dealt to workgroups in that order, in short runs per XCD (not one contiguous
+// range per XCD, which would leave the XCDs holding the large items to finish last), so a run is
+// one kernel launch and nothing else: capturable and replayable. (A persistent grid taking items
+// from a counter needed 128 registers and four waves per SIMD; one item per workgroup fits in 96
+// and five: 2.69 -> 2.1-2.2 ms for the 64-item batch.)
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -67,7 +67,13 @@ __global__ __launch_bounds__(64 * TPG, (batch_waves<S, R>())) void k_batch(const
     est::StripSmem<TPG> &esm = *reinterpret_cast<est::StripSmem<TPG> *>(raw);
     gat::Smem<S, R, TPG> &gsm = *reinterpret_cast<gat::Smem<S, R, TPG> *>(raw);
     {
-        const int w = (int)blockIdx.x;  // the work item; the grid is exactly first[n] workgroups
+        // The work item (the grid is exactly first[n] workgroups). Workgroups are dealt to the eight
+        // XCDs in turn; within each group of 64, XCD x takes the 8 consecutive items from 8x, so
+        // neighbouring tile groups (which share halo rows) meet in one L2 while every XCD still
+        // moves through the list, large items to small, with the others (2.16 -> 2.11 ms).
+        const int bid = (int)blockIdx.x, g64 = bid / 64;
+        const int w = (g64 + 1) * 64 <= (int)gridDim.x ? g64 * 64 + (bid % 8) * 8 + (bid / 8) % 8
+                                                         : bid;
         int lo = 0, hi = n - 1;  // the item b with first[b] <= w < first[b + 1]
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
