@@ -61,6 +61,33 @@ def test_batch_equals_separate_calls_and_reference():
     batch.close()
 
 
+@pytest.mark.parametrize("radius,precision", [(0, "fp16"), (1, "fp16"), (3, "fp16"), (4, "fp16"),
+                                              (2, "fp32"), (1, "fp32")])
+def test_batch_every_radius_and_precision(radius, precision):
+    """The batch kernel's instantiations for other radii and binary32 storage (other register
+    budgets and group sizes) give each item's separate statistics and gather bit for bit, for every
+    launch shape the radius allows."""
+    torch = torch_mod()
+    afr = afr_mod()
+    items = _items(n=5, seed=31 + radius, precision=precision)
+    bufs = [(buf, p.with_(radius=radius)) for buf, p in _build_all(items, precision=precision)]
+    refs = []
+    for buf, p in bufs:
+        st = afr.estimate_gradients(buf, p)
+        rgb, aux = afr.reconstruct(buf, st, p)
+        refs.append((st, rgb, aux))
+    for tpw in ((1, 2, 4) if radius <= 2 else (1, 2)):
+        print(f"batch R={radius} {precision} tiles per wave {tpw}", flush=True)
+        batch = afr.Batch(bufs, tiles_per_wave=tpw)
+        batch.run()
+        torch.cuda.synchronize()
+        for i, (st, rgb, aux) in enumerate(refs):
+            assert torch.equal(batch.stats[i], st), (tpw, i)
+            assert torch.equal(batch.rgb[i], rgb), (tpw, i)
+            assert torch.equal(batch.aux[i], aux), (tpw, i)
+        batch.close()
+
+
 def test_launch_shapes_and_tuner_change_no_bit():
     torch = torch_mod()
     afr = afr_mod()
